@@ -1,0 +1,258 @@
+/*
+ * ksym -- batched closed-form eigendecomposition of 2x2 and 3x3 real symmetric
+ * matrices on AMD MI355X (gfx950).
+ *
+ * Method: M.J. Kronenburg, "A Method for Fast Diagonalization of a 2x2 or 3x3
+ * Real Symmetric Matrix", arXiv:1306.6291.  For each matrix A the library finds
+ * the eigenvalues from the characteristic polynomial (paper §3 for 2x2, §4 for
+ * 3x3), solves the rotation angles from A = D Lambda D^T (§3, §5), forms
+ * D = R(phi) (2x2, eq. (2.5)) or D = R1(phi1) R2(phi2) R3(phi3) (3x3, eq. (2.6))
+ * and returns the angles, which are the Euler angles of the eigenvectors (§6).
+ *
+ * ---------------------------------------------------------------- conventions
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller.  The
+ * library never allocates inside ksym_eig2, ksym_eig3, ksym_eig3_aos,
+ * ksym_eig3_backward or ksym_plan_run / ksym_plan_replay.  ksym_plan_create
+ * allocates one small descriptor buffer, freed by ksym_plan_destroy.
+ *
+ * Layout.  Structure of arrays: one contiguous plane of n elements per
+ * quantity, element type float (KSYM_F32) or double (KSYM_F64), each plane
+ * aligned to its element size.  A 3x3 input is the six planes of its unique
+ * entries in the order {A11, A22, A33, A12, A13, A23}; a 2x2 input is
+ * {A11, A22, A12}.  D is given as row-major planes {D11, D12, D13, D21, ...};
+ * column k of D is the unit eigenvector of lam[k].
+ *
+ * Output slots.  3x3: lam = {max, min, mid}, the order in which eqs.
+ * (4.10)-(4.12) produce lam1 >= lam3 >= lam2; det D = +1 always;
+ * phi = {phi1, phi2, phi3} with D = R1(phi1) R2(phi2) R3(phi3),
+ * phi1 in (-pi, pi], phi2 and phi3 in [-pi/2, pi/2].  2x2: lam = {lam1, lam2}
+ * with lam1 the eigenvalue on A11's side (eqs. (3.2)-(3.3), sign(0) = +1),
+ * D = R(phi), phi in [-pi/4, pi/4] (eq. (3.5)).
+ *
+ * Optional outputs.  Any output pointer (a whole pointer array, or one entry of
+ * it) may be NULL: that quantity is not written.
+ *
+ * Errors.  Calls return ksym_status and never abort or throw.  n == 0 returns
+ * KSYM_OK with nothing enqueued.  n < 0, a NULL required input, a pointer not
+ * aligned to its element size or an unknown dtype/path are rejected before any
+ * HIP call.  Asynchronous kernel faults surface as KSYM_E_HIP from a later call
+ * or from the caller's stream synchronisation.  Non-finite input entries are not
+ * an error: that matrix's outputs are NaN and its flag has KSYM_FLAG_NONFINITE.
+ * ksym_last_error() returns text for the last non-OK status of the calling
+ * thread.
+ *
+ * Streams.  Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ * stream) without host synchronisation.  Calls are re-entrant; the library
+ * keeps no mutable global state except a per-device cache of the CU count.
+ *
+ * Range.  Inputs are assumed finite with |A_ij| below 1e18 (float) or 1e150
+ * (double); larger magnitudes may overflow intermediate squares.
+ */
+#ifndef KSYM_H
+#define KSYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KSYM_VERSION 100   /* 1.0.0 */
+
+typedef enum { KSYM_F32 = 0, KSYM_F64 = 1 } ksym_dtype;
+
+typedef enum {
+    KSYM_OK = 0,
+    KSYM_E_ARG = 1,          /* bad size, NULL required pointer, misalignment */
+    KSYM_E_DTYPE = 2,        /* unknown dtype, or dtype/path combination not offered */
+    KSYM_E_WORKSPACE = 3,    /* workspace pointer NULL or smaller than required */
+    KSYM_E_HIP = 4,          /* a HIP runtime call failed; see ksym_last_error() */
+    KSYM_E_UNSUPPORTED = 5   /* option outside the compiled variants */
+} ksym_status;
+
+/* Per-matrix flag bits, written to the optional uint8 flags plane. */
+#define KSYM_FLAG_GENERAL   0u   /* general branch of §5 */
+#define KSYM_FLAG_DOUBLE    1u   /* two eigenvalues coincide (special case q^2 = 4p^3 != 0 of §5) */
+#define KSYM_FLAG_TRIPLE    2u   /* p = 0: triple eigenvalue, D = I, angles 0 (§5) */
+#define KSYM_FLAG_FIXUP     4u   /* result rewritten by the float64 refinement */
+#define KSYM_FLAG_NONFINITE 8u   /* an input entry was Inf or NaN; outputs are NaN */
+
+/*
+ * Numerical paths for the 3x3 forward.
+ *  KSYM_PATH_FP32_FIXUP (dtype F32 only): float32 inputs and outputs; the
+ *    cubic step (p, q, arccos, cos/sin, eqs. (4.7)-(4.12)) in float64; the angle
+ *    solve of §5 in float32; a float64 a-posteriori check of D; matrices that
+ *    fail the check, whose relative eigenvalue gap is below tau_gap, or whose
+ *    eigenvalues coincide are rewritten by a float64 refinement (isolated
+ *    eigenvector by cross products, Rayleigh-Ritz on its complement and one
+ *    2x2 Jacobi rotation).
+ *  KSYM_PATH_FP64_PLAIN (dtype F64 only): the paper's formulas in float64,
+ *    including the double-root branch, with no check and no refinement.
+ *  KSYM_PATH_FP64_FIXUP (dtype F64 only): as PLAIN, plus the float64 check and
+ *    refinement with float64 thresholds.
+ */
+typedef enum {
+    KSYM_PATH_DEFAULT = -1,     /* FP32_FIXUP for F32, FP64_FIXUP for F64 */
+    KSYM_PATH_FP32_FIXUP = 0,
+    KSYM_PATH_FP64_PLAIN = 1,
+    KSYM_PATH_FP64_FIXUP = 2
+} ksym_path;
+
+/*
+ * Launch and threshold options.  Fill with ksym_opts_default() and change
+ * fields; a NULL ksym_opts* means the defaults.
+ *   block          threads per workgroup: 64, 128, 256, 512 or 1024.
+ *   mats_per_lane  matrices each lane handles per tile: 1, 2 or 4.
+ *   grid_mult      workgroups per compute unit of the grid-stride launch
+ *                  (the grid is min(tiles, grid_mult * CUs)); 1..64.
+ *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
+ *                  below which a matrix always takes the refinement (0 = off).
+ *   tau_res        refinement if some |d_j^T A d_k| (j != k) exceeds
+ *                  tau_res * ||A||_F (a residual bound).
+ *   tau_vec        refinement if some |d_j^T A d_k| / |lam_k - lam_j| exceeds
+ *                  tau_vec (first-order angle error of the eigenvectors;
+ *                  0 = off).
+ *   tau_dbl        relative split (min distance of the middle eigenvalue to
+ *                  the others, divided by sqrt(p)) below which the computed
+ *                  eigenvalues are taken as a double root.
+ * Negative thresholds select the dtype's default.
+ */
+typedef struct {
+    int32_t path;
+    int32_t block;
+    int32_t mats_per_lane;
+    int32_t grid_mult;
+    double  tau_gap;
+    double  tau_res;
+    double  tau_vec;
+    double  tau_dbl;
+} ksym_opts;
+
+/* Library version (KSYM_VERSION of the build). */
+int ksym_version(void);
+
+/* Text describing the calling thread's last non-OK status ("" if none).
+   The pointer stays valid until that thread's next ksym call. */
+const char *ksym_last_error(void);
+
+/* Defaults for dtype (thresholds and launch shape). */
+void ksym_opts_default(ksym_dtype dtype, ksym_opts *opts);
+
+/*
+ * 2x2 forward, paper §3.  in = {A11, A22, A12} (3 planes, required when n > 0).
+ * lam = {lam1, lam2} (eqs. (3.2)-(3.3)), D = {D11, D12, D21, D22} = R(phi)
+ * (eq. (2.5)), phi of eq. (3.5) evaluated as 1/2 atan2(2 A12 sign(A11 - A22),
+ * |A11 - A22|) (the same value where A11 != A22, 0 when also A12 = 0).
+ * flags: KSYM_FLAG_NONFINITE or 0.  Only opts->block and grid_mult are used.
+ */
+ksym_status ksym_eig2(ksym_dtype dtype, int64_t n, const void *const in[3],
+                      void *const lam[2], void *const D[4], void *phi,
+                      uint8_t *flags, const ksym_opts *opts, void *stream);
+
+/*
+ * Bytes of workspace ksym_eig3 / ksym_eig3_aos need (a few counters; the
+ * refinement queue lives in on-chip memory).  Workspace layout: uint32 word 0
+ * accumulates the number of refined matrices, word 1 the number of matrices
+ * with non-finite input.  The caller zeroes it when it wants fresh counts
+ * (ksym_zero_counters); the library only adds.
+ */
+size_t ksym_eig3_workspace_bytes(ksym_dtype dtype, int64_t n);
+
+/* Zero the counter words of a workspace on `stream` (a kernel, so it may be
+   captured in a HIP graph). */
+ksym_status ksym_zero_counters(void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * 3x3 forward, paper §4-§5 (see the path descriptions above).
+ * in  = {A11, A22, A33, A12, A13, A23}: 6 planes, required when n > 0.
+ * lam = 3 planes (slots max, min, mid), D = 9 planes (row-major), phi = 3 planes.
+ * gap = optional 3 planes {lam1 - lam2, lam1 - lam3, lam3 - lam2} (max - min,
+ *       max - mid, mid - min) evaluated in float64 before rounding: saved state
+ *       for ksym_eig3_backward (NULL array = not written).
+ * flags = optional uint8 plane (KSYM_FLAG_* bits).
+ * ws  = workspace of ksym_eig3_workspace_bytes() bytes, or NULL (no counters).
+ */
+ksym_status ksym_eig3(ksym_dtype dtype, int64_t n, const void *const in[6],
+                      void *const lam[3], void *const D[9], void *const phi[3],
+                      void *const gap[3], uint8_t *flags, void *ws, size_t ws_bytes,
+                      const ksym_opts *opts, void *stream);
+
+/*
+ * 3x3 forward on array-of-structures input: a_aos holds n records of six
+ * entries {A11, A22, A33, A12, A13, A23} (n x 6 contiguous, record stride 6
+ * elements, base aligned to 16 bytes).  Each workgroup stages its records
+ * through on-chip memory; outputs and everything else as ksym_eig3.
+ */
+ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos,
+                          void *const lam[3], void *const D[9], void *const phi[3],
+                          void *const gap[3], uint8_t *flags, void *ws, size_t ws_bytes,
+                          const ksym_opts *opts, void *stream);
+
+/*
+ * 3x3 adjoint (not in the paper; first-order perturbation theory of the
+ * symmetric eigenproblem).  From the saved forward outputs lam (3 planes) and D
+ * (9 planes) and the cotangents glam = dL/dlam (3 planes) and gD = dL/dD
+ * (9 planes), writes gA = dL/d(plane) for the six input planes:
+ *   Abar = D [diag(glam) + F o (D^T gD)] D^T,
+ *   F_ij = (lam_j - lam_i) / ((lam_j - lam_i)^2 + eps^2) (i != j), F_ii = 0,
+ *   eps  = eps_rel * sqrt(lam1^2 + lam2^2 + lam3^2)  (= eps_rel * ||A||_F),
+ *   gA_ii = Abar_ii, gA_ij = Abar_ij + Abar_ji (each off-diagonal plane feeds
+ *   both A_ij and A_ji).
+ * gap (optional, from ksym_eig3) supplies the eigenvalue differences in place
+ * of differences of the rounded lam.  glam or gD NULL = zero cotangent.
+ * gA: 6 planes, required.
+ */
+ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                               const void *const D[9], const void *const gap[3],
+                               const void *const glam[3], const void *const gD[9],
+                               void *const gA[6], double eps_rel, void *stream);
+
+/*
+ * Mixed persistent batch: many groups of 2x2 or 3x3 matrices in one launch.
+ * kind = 2 uses in[0..2], lam[0..1], D[0..3], phi[0]; kind = 3 uses the full
+ * arrays as in ksym_eig3.  Pointers of unused slots are ignored.
+ */
+typedef struct {
+    int32_t kind;          /* 2 or 3 */
+    int64_t n;             /* matrices in this group (>= 0) */
+    const void *in[6];
+    void *lam[3];
+    void *D[9];
+    void *phi[3];
+    uint8_t *flags;
+} ksym_group;
+
+typedef struct ksym_plan ksym_plan;
+
+/*
+ * Build a plan for `ngroups` groups (copied; the group array may be freed
+ * afterwards, the device planes it points to may not).  Allocates the device
+ * descriptor table (the only allocating call).  *ws_bytes receives the
+ * workspace size ksym_plan_run needs.
+ */
+ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
+                             const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes);
+
+/* Enqueue the whole batch (counter reset kernel + one persistent kernel) on
+   `stream`.  No allocation, no synchronisation: safe under stream capture. */
+ksym_status ksym_plan_run(ksym_plan *plan, void *ws, void *stream);
+
+/* Capture ksym_plan_run(plan, ws, stream) into a HIP graph held by the plan
+   (replacing any previous one).  Not itself capturable. */
+ksym_status ksym_plan_capture(ksym_plan *plan, void *ws, void *stream);
+
+/* Launch the captured graph on `stream`. */
+ksym_status ksym_plan_replay(ksym_plan *plan, void *stream);
+
+/* Number of tiles and the grid size the plan launches (for reporting). */
+ksym_status ksym_plan_info(const ksym_plan *plan, int64_t *tiles, int32_t *grid);
+
+/* Free the plan, its descriptor table and its graph.  NULL is a no-op. */
+void ksym_plan_destroy(ksym_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSYM_H */

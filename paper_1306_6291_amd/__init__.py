@@ -1,0 +1,378 @@
+"""ksym: batched closed-form eigendecomposition of 2x2 / 3x3 real symmetric
+matrices on AMD MI355X (gfx950), after Kronenburg, arXiv:1306.6291.
+
+This module is argument marshalling only: torch supplies device memory and the
+current HIP stream, every computation runs in the HIP kernels of libksym.so
+behind the C ABI of include/ksym.h.  If libksym.so is missing, importing this
+package raises -- there is no fallback path.
+
+Tensors are structure-of-arrays: a 3x3 batch is a (6, n) tensor whose rows are
+the planes A11, A22, A33, A12, A13, A23; a 2x2 batch is (3, n) with rows A11,
+A22, A12.  Outputs: lam (3, n) in the slots (max, min, mid), D (9, n) row-major
+with column k the eigenvector of lam[k], phi (3, n) with D = R1 R2 R3 (paper
+eq. (2.6)), gap (3, n) = (max-min, max-mid, mid-min), flags (n,) uint8.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libksym.so")
+TUNED_PATH = os.path.join(_HERE, "tuned.json")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1306_6291_amd.build` "
+        "(hipcc, gfx950).  There is no fallback implementation.")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+F32, F64 = 0, 1
+PATH_DEFAULT, PATH_FP32_FIXUP, PATH_FP64_PLAIN, PATH_FP64_FIXUP = -1, 0, 1, 2
+FLAG_GENERAL, FLAG_DOUBLE, FLAG_TRIPLE, FLAG_FIXUP, FLAG_NONFINITE = 0, 1, 2, 4, 8
+STATUS = {0: "KSYM_OK", 1: "KSYM_E_ARG", 2: "KSYM_E_DTYPE", 3: "KSYM_E_WORKSPACE",
+          4: "KSYM_E_HIP", 5: "KSYM_E_UNSUPPORTED"}
+
+
+class KsymError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("mats_per_lane", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
+                ("tau_gap", ctypes.c_double), ("tau_res", ctypes.c_double),
+                ("tau_vec", ctypes.c_double), ("tau_dbl", ctypes.c_double)]
+
+    @classmethod
+    def defaults(cls, dtype=F32, **kw):
+        o = cls()
+        _lib.ksym_opts_default(dtype, ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Group(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("in_", ctypes.c_void_p * 6), ("lam", ctypes.c_void_p * 3),
+                ("D", ctypes.c_void_p * 9), ("phi", ctypes.c_void_p * 3),
+                ("flags", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_lib.ksym_version.restype = ctypes.c_int
+_lib.ksym_last_error.restype = ctypes.c_char_p
+_lib.ksym_opts_default.argtypes = [ctypes.c_int, ctypes.POINTER(Opts)]
+_lib.ksym_opts_default.restype = None
+_lib.ksym_eig2.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P]
+_lib.ksym_eig3_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int64]
+_lib.ksym_eig3_workspace_bytes.restype = ctypes.c_size_t
+_lib.ksym_zero_counters.argtypes = [_P, ctypes.c_size_t, _P]
+_lib.ksym_eig3.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                           ctypes.POINTER(Opts), _P]
+_lib.ksym_eig3_aos.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P,
+                               ctypes.c_size_t, ctypes.POINTER(Opts), _P]
+_lib.ksym_eig3_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                    ctypes.c_double, _P]
+_lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
+                                  ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_size_t)]
+_lib.ksym_plan_run.argtypes = [_P, _P, _P]
+_lib.ksym_plan_capture.argtypes = [_P, _P, _P]
+_lib.ksym_plan_replay.argtypes = [_P, _P]
+_lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+_lib.ksym_plan_destroy.argtypes = [_P]
+_lib.ksym_plan_destroy.restype = None
+for _f in ("ksym_eig2", "ksym_zero_counters", "ksym_eig3", "ksym_eig3_aos", "ksym_eig3_backward",
+           "ksym_plan_create", "ksym_plan_run", "ksym_plan_capture", "ksym_plan_replay",
+           "ksym_plan_info"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def version():
+    return _lib.ksym_version()
+
+
+def _check(status):
+    if status != 0:
+        raise KsymError(status, _lib.ksym_last_error().decode(errors="replace"))
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"ksym supports float32 and float64 tensors, got {t.dtype}")
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[p if p else None for p in ptrs])
+
+
+def _rows(t, k):
+    """Pointers of the k rows of a contiguous (k, n) tensor, or of a list of k 1-D tensors."""
+    if isinstance(t, (list, tuple)):
+        assert len(t) == k
+        n = t[0].numel()
+        for x in t:
+            if not x.is_contiguous() or x.numel() != n or x.dtype != t[0].dtype or x.device != t[0].device:
+                raise ValueError("planes must be contiguous, same length, dtype and device")
+        return [x.data_ptr() for x in t], n, t[0]
+    if t.dim() != 2 or t.shape[0] != k or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous ({k}, n) tensor, got shape {tuple(t.shape)}")
+    n = t.shape[1]
+    es = t.element_size()
+    base = t.data_ptr()
+    return [base + c * n * es for c in range(k)], n, t
+
+
+def _stream(t):
+    if not t.is_cuda:
+        raise ValueError("ksym works on device tensors (torch.device('cuda'))")
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _opts(dtype, opts, **kw):
+    if opts is None:
+        opts = tuned_opts(kw.pop("_kind", "eig3"), dtype)
+    else:
+        kw.pop("_kind", None)
+    if isinstance(opts, dict):
+        opts = Opts.defaults(dtype, **opts)
+    for k, v in kw.items():
+        if v is not None:
+            setattr(opts, k, v)
+    return opts
+
+
+_TUNED = None
+
+
+def tuned_opts(kind="eig3", dtype=F32):
+    """Options the autotuner recorded for (kind, dtype), else the library defaults."""
+    global _TUNED
+    if _TUNED is None:
+        _TUNED = {}
+        if os.path.exists(TUNED_PATH):
+            with open(TUNED_PATH) as f:
+                _TUNED = json.load(f)
+    key = f"{kind}/{'f32' if dtype == F32 else 'f64'}"
+    rec = _TUNED.get(key)
+    if rec:
+        return Opts.defaults(dtype, **rec["opts"])
+    return Opts.defaults(dtype)
+
+
+def workspace(device=None):
+    """A small device workspace (counters) for eig3: uint32[64]."""
+    nbytes = _lib.ksym_eig3_workspace_bytes(F32, 0)
+    return torch.zeros(nbytes // 4, dtype=torch.int32, device=device or "cuda")
+
+
+# ---------------------------------------------------------------- 2x2 -------
+def eig2(planes, opts=None, out=None):
+    """2x2 forward (paper §3).  planes: (3, n) tensor (A11, A22, A12).
+    Returns dict lam (2, n), D (4, n) = (D11, D12, D21, D22), phi (n,), flags (n,)."""
+    ptrs, n, ref = _rows(planes, 3)
+    dt = _dt(ref)
+    o = _opts(dt, opts, _kind="eig2")
+    if out is None:
+        out = {"lam": torch.empty((2, n), dtype=ref.dtype, device=ref.device),
+               "D": torch.empty((4, n), dtype=ref.dtype, device=ref.device),
+               "phi": torch.empty((n,), dtype=ref.dtype, device=ref.device),
+               "flags": torch.empty((n,), dtype=torch.uint8, device=ref.device)}
+    lam = _ptr_array(_rows(out["lam"], 2)[0]) if out.get("lam") is not None else None
+    D = _ptr_array(_rows(out["D"], 4)[0]) if out.get("D") is not None else None
+    phi = out["phi"].data_ptr() if out.get("phi") is not None else None
+    fl = out["flags"].data_ptr() if out.get("flags") is not None else None
+    _check(_lib.ksym_eig2(dt, n, _ptr_array(ptrs), lam, D, phi, fl, ctypes.byref(o), _stream(ref)))
+    return out
+
+
+# ---------------------------------------------------------------- 3x3 -------
+def _alloc3(n, ref, outputs):
+    kw = dict(dtype=ref.dtype, device=ref.device)
+    shapes = {"lam": (3, n), "D": (9, n), "phi": (3, n), "gap": (3, n)}
+    out = {k: torch.empty(shapes[k], **kw) for k in shapes if k in outputs}
+    if "flags" in outputs:
+        out["flags"] = torch.empty((n,), dtype=torch.uint8, device=ref.device)
+    return out
+
+
+def _out_ptrs3(out):
+    def arr(key, k):
+        t = out.get(key)
+        return _ptr_array(_rows(t, k)[0]) if t is not None else None
+    fl = out.get("flags")
+    return arr("lam", 3), arr("D", 9), arr("phi", 3), arr("gap", 3), (fl.data_ptr() if fl is not None else None)
+
+
+def eig3(planes, opts=None, path=None, outputs=("lam", "D", "phi", "flags"), out=None, ws=None):
+    """3x3 forward (paper §4-§5).  planes: (6, n) tensor or 6 plane tensors.
+    path: PATH_FP32_FIXUP (float32), PATH_FP64_PLAIN or PATH_FP64_FIXUP (float64).
+    ws: optional workspace() tensor; its words 0 and 1 accumulate the counts of
+    refined and non-finite matrices."""
+    ptrs, n, ref = _rows(planes, 6)
+    dt = _dt(ref)
+    o = _opts(dt, opts, path=path, _kind="eig3")
+    if out is None:
+        out = _alloc3(n, ref, outputs)
+    lam, D, phi, gap, fl = _out_ptrs3(out)
+    wsp, wsb = (ws.data_ptr(), ws.numel() * ws.element_size()) if ws is not None else (None, 0)
+    _check(_lib.ksym_eig3(dt, n, _ptr_array(ptrs), lam, D, phi, gap, fl, wsp, wsb, ctypes.byref(o),
+                          _stream(ref)))
+    return out
+
+
+def eig3_aos(records, opts=None, path=None, outputs=("lam", "D", "phi", "flags"), out=None, ws=None):
+    """3x3 forward on array-of-structures input: records (n, 6) contiguous with
+    columns A11, A22, A33, A12, A13, A23 (16-byte aligned base)."""
+    if records.dim() != 2 or records.shape[1] != 6 or not records.is_contiguous():
+        raise ValueError("records must be a contiguous (n, 6) tensor")
+    n = records.shape[0]
+    dt = _dt(records)
+    o = _opts(dt, opts, path=path, _kind="eig3_aos")
+    if out is None:
+        out = _alloc3(n, records, outputs)
+    lam, D, phi, gap, fl = _out_ptrs3(out)
+    wsp, wsb = (ws.data_ptr(), ws.numel() * ws.element_size()) if ws is not None else (None, 0)
+    _check(_lib.ksym_eig3_aos(dt, n, records.data_ptr(), lam, D, phi, gap, fl, wsp, wsb,
+                              ctypes.byref(o), _stream(records)))
+    return out
+
+
+def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None):
+    """Adjoint of eig3 for the plane gradients gA (6, n); see include/ksym.h."""
+    lp, n, ref = _rows(lam, 3)
+    dt = _dt(ref)
+    if eps_rel is None:
+        eps_rel = 1e-6 if dt == F32 else 1e-12
+    Dp = _rows(D, 9)[0]
+    gl = _ptr_array(_rows(glam, 3)[0]) if glam is not None else None
+    gd = _ptr_array(_rows(gD, 9)[0]) if gD is not None else None
+    gp = _ptr_array(_rows(gap, 3)[0]) if gap is not None else None
+    if out is None:
+        out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
+    _check(_lib.ksym_eig3_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gp, gl, gd,
+                                   _ptr_array(_rows(out, 6)[0]), float(eps_rel), _stream(ref)))
+    return out
+
+
+def zero_counters(ws):
+    _check(_lib.ksym_zero_counters(ws.data_ptr(), ws.numel() * ws.element_size(), _stream(ws)))
+
+
+# ------------------------------------------------------------ autograd ------
+class Eig3Function(torch.autograd.Function):
+    """lam, D = Eig3Function.apply(planes, eps_rel): differentiable in lam and D
+    through the hand-written adjoint kernel.  planes is a (6, n) tensor."""
+
+    @staticmethod
+    def forward(ctx, planes, eps_rel=None, opts=None):
+        out = eig3(planes.contiguous(), opts=opts, outputs=("lam", "D", "gap"))
+        ctx.save_for_backward(out["lam"], out["D"], out["gap"])
+        ctx.eps_rel = eps_rel
+        return out["lam"], out["D"]
+
+    @staticmethod
+    def backward(ctx, glam, gD):
+        lam, D, gap = ctx.saved_tensors
+        gA = eig3_backward(lam, D, glam.contiguous() if glam is not None else None,
+                           gD.contiguous() if gD is not None else None, gap=gap,
+                           eps_rel=ctx.eps_rel)
+        return gA, None, None
+
+
+def eig3_autograd(planes, eps_rel=None, opts=None):
+    return Eig3Function.apply(planes, eps_rel, opts)
+
+
+# ------------------------------------------------------- mixed plans --------
+class Plan:
+    """Mixed persistent batch of 2x2 and 3x3 groups (one kernel launch).
+    groups: list of (kind, planes, out) with planes a (3|6, n) tensor and out a
+    dict of preallocated outputs (lam, D, phi, flags; any may be missing)."""
+
+    def __init__(self, groups, opts=None):
+        ref = groups[0][1]
+        dt = _dt(ref)
+        self.dtype = dt
+        self.device = ref.device
+        self._keep = []
+        arr = (Group * len(groups))()
+        for g, (kind, planes, out) in enumerate(groups):
+            k = 3 if kind == 3 else 2
+            ptrs, n, t = _rows(planes, 6 if k == 3 else 3)
+            G = arr[g]
+            G.kind = k
+            G.n = n
+            for c, p in enumerate(ptrs):
+                G.in_[c] = p
+            nl, nd, nph = (3, 9, 3) if k == 3 else (2, 4, 1)
+            if out.get("lam") is not None:
+                for c, p in enumerate(_rows(out["lam"], nl)[0]):
+                    G.lam[c] = p
+            if out.get("D") is not None:
+                for c, p in enumerate(_rows(out["D"], nd)[0]):
+                    G.D[c] = p
+            if out.get("phi") is not None:
+                ph = out["phi"]
+                if k == 3:
+                    for c, p in enumerate(_rows(ph, 3)[0]):
+                        G.phi[c] = p
+                else:
+                    G.phi[0] = ph.data_ptr()
+            if out.get("flags") is not None:
+                G.flags = out["flags"].data_ptr()
+            self._keep.append((planes, out))
+        o = _opts(dt, opts, _kind="mixed")
+        self.opts = o
+        h = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
+        _check(_lib.ksym_plan_create(dt, len(groups), arr, ctypes.byref(o), ctypes.byref(h),
+                                     ctypes.byref(wsb)))
+        self._h = h
+        self.ws = torch.zeros(max(1, wsb.value // 4), dtype=torch.int32, device=self.device)
+
+    def info(self):
+        t = ctypes.c_int64()
+        g = ctypes.c_int32()
+        _check(_lib.ksym_plan_info(self._h, ctypes.byref(t), ctypes.byref(g)))
+        return {"tiles": t.value, "grid": g.value}
+
+    def _st(self, stream):
+        if stream is None:
+            return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def run(self, stream=None):
+        _check(_lib.ksym_plan_run(self._h, self.ws.data_ptr(), self._st(stream)))
+
+    def capture(self, stream):
+        _check(_lib.ksym_plan_capture(self._h, self.ws.data_ptr(), self._st(stream)))
+
+    def replay(self, stream=None):
+        _check(_lib.ksym_plan_replay(self._h, self._st(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ksym_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

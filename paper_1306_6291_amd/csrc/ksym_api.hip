@@ -1,0 +1,609 @@
+// C ABI of the ksym library (declared in include/ksym.h): argument checks,
+// launch-shape selection, kernel dispatch, plans and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ksym.h"
+#include "ksym_kernels.hpp"
+
+using namespace ksym;
+
+namespace {
+
+thread_local std::string g_err;
+
+ksym_status fail(ksym_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+ksym_status hip_fail(hipError_t e, const char *what) {
+    return fail(KSYM_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// per-device compute-unit count, cached after the first query
+std::atomic<int> g_cu[64];
+
+ksym_status cu_count(int *out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(KSYM_E_HIP, "device index %d out of range", dev);
+    int c = g_cu[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        if (c <= 0) c = 256;
+        g_cu[dev].store(c, std::memory_order_relaxed);
+    }
+    *out = c;
+    return KSYM_OK;
+}
+
+template <typename... Args>
+hipError_t launch(void (*k)(Args...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    void *argv[] = {(void *)&args...};
+    return hipLaunchKernel((const void *)k, grid, block, argv, 0, s);
+}
+
+struct Shape {
+    int block, mpl, grid_mult;
+};
+
+ksym_status resolve_opts(ksym_dtype dt, const ksym_opts *in, ksym_opts *out) {
+    ksym_opts_default(dt, out);
+    if (!in) return KSYM_OK;
+    ksym_opts o = *in;
+    if (o.path == KSYM_PATH_DEFAULT) o.path = out->path;
+    if (o.block == 0) o.block = out->block;
+    if (o.mats_per_lane == 0) o.mats_per_lane = out->mats_per_lane;
+    if (o.grid_mult == 0) o.grid_mult = out->grid_mult;
+    if (o.tau_gap < 0) o.tau_gap = out->tau_gap;
+    if (o.tau_res < 0) o.tau_res = out->tau_res;
+    if (o.tau_vec < 0) o.tau_vec = out->tau_vec;
+    if (o.tau_dbl < 0) o.tau_dbl = out->tau_dbl;
+    if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
+        return fail(KSYM_E_ARG, "block must be 64, 128, 256, 512 or 1024 (got %d)", o.block);
+    if (o.mats_per_lane != 1 && o.mats_per_lane != 2 && o.mats_per_lane != 4)
+        return fail(KSYM_E_ARG, "mats_per_lane must be 1, 2 or 4 (got %d)", o.mats_per_lane);
+    if (o.grid_mult < 1 || o.grid_mult > 64)
+        return fail(KSYM_E_ARG, "grid_mult must be in 1..64 (got %d)", o.grid_mult);
+    if (!(o.tau_res > 0) || !(o.tau_dbl >= 0) || !(o.tau_gap >= 0) || !(o.tau_vec >= 0))
+        return fail(KSYM_E_ARG, "thresholds must be finite and non-negative (tau_res > 0)");
+    *out = o;
+    return KSYM_OK;
+}
+
+ksym_status grid_for(int64_t n, int tile, int grid_mult, int *grid) {
+    int cus = 0;
+    ksym_status s = cu_count(&cus);
+    if (s != KSYM_OK) return s;
+    const int64_t tiles = (n + tile - 1) / tile;
+    int64_t g = (int64_t)grid_mult * cus;
+    if (g > tiles) g = tiles;
+    if (g < 1) g = 1;
+    *grid = (int)g;
+    return KSYM_OK;
+}
+
+// ------------------------------------------------------ kernel tables -----
+template <typename T, int PATH, bool AOS> using Eig3K = void (*)(Eig3Args<T>);
+
+#define KSYM_E3(T, P, A, B, M) \
+    if (bs == B && mpl == M) return &k_eig3<T, P, B, M, A>;
+
+template <typename T, int PATH, bool AOS> Eig3K<T, PATH, AOS> pick_eig3(int bs, int mpl);
+
+template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXUP, false>(int bs, int mpl) {
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 2)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 4)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 2)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 4)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 2)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 4)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 2)
+    return nullptr;
+}
+template <> Eig3K<float, PATH_FP32_FIXUP, true> pick_eig3<float, PATH_FP32_FIXUP, true>(int bs, int mpl) {
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 64, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 128, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 128, 2)
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 1)
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 2)
+    KSYM_E3(float, PATH_FP32_FIXUP, true, 512, 1)
+    return nullptr;
+}
+template <> Eig3K<double, PATH_FP64_PLAIN, false> pick_eig3<double, PATH_FP64_PLAIN, false>(int bs, int mpl) {
+    KSYM_E3(double, PATH_FP64_PLAIN, false, 64, 1)
+    KSYM_E3(double, PATH_FP64_PLAIN, false, 128, 1)
+    KSYM_E3(double, PATH_FP64_PLAIN, false, 256, 1)
+    KSYM_E3(double, PATH_FP64_PLAIN, false, 256, 2)
+    return nullptr;
+}
+template <> Eig3K<double, PATH_FP64_PLAIN, true> pick_eig3<double, PATH_FP64_PLAIN, true>(int bs, int mpl) {
+    KSYM_E3(double, PATH_FP64_PLAIN, true, 256, 1)
+    return nullptr;
+}
+template <> Eig3K<double, PATH_FP64_FIXUP, false> pick_eig3<double, PATH_FP64_FIXUP, false>(int bs, int mpl) {
+    KSYM_E3(double, PATH_FP64_FIXUP, false, 64, 1)
+    KSYM_E3(double, PATH_FP64_FIXUP, false, 128, 1)
+    KSYM_E3(double, PATH_FP64_FIXUP, false, 256, 1)
+    KSYM_E3(double, PATH_FP64_FIXUP, false, 256, 2)
+    return nullptr;
+}
+template <> Eig3K<double, PATH_FP64_FIXUP, true> pick_eig3<double, PATH_FP64_FIXUP, true>(int bs, int mpl) {
+    KSYM_E3(double, PATH_FP64_FIXUP, true, 256, 1)
+    return nullptr;
+}
+#undef KSYM_E3
+
+template <typename T> using Eig2K = void (*)(Eig2Ptrs<T>, int64_t);
+template <typename T> Eig2K<T> pick_eig2(int bs, int mpl) {
+#define KSYM_E2(B, M) \
+    if (bs == B && mpl == M) return &k_eig2<T, B, M>;
+    KSYM_E2(64, 1) KSYM_E2(128, 1) KSYM_E2(128, 2) KSYM_E2(256, 1) KSYM_E2(256, 2) KSYM_E2(256, 4)
+    KSYM_E2(512, 1) KSYM_E2(512, 2) KSYM_E2(1024, 1)
+#undef KSYM_E2
+    return nullptr;
+}
+
+template <typename T> using BwdK = void (*)(BwdPtrs<T>, int64_t, double);
+template <typename T> BwdK<T> pick_bwd(int bs, int mpl) {
+#define KSYM_B(B, M) \
+    if (bs == B && mpl == M) return &k_eig3_bwd<T, B, M>;
+    KSYM_B(64, 1) KSYM_B(128, 1) KSYM_B(256, 1) KSYM_B(256, 2) KSYM_B(512, 1)
+#undef KSYM_B
+    return nullptr;
+}
+
+template <typename T> using MixK = void (*)(MixedArgs<T>);
+template <typename T> MixK<T> pick_mixed(int bs, int mpl) {
+#define KSYM_M(B, M) \
+    if (bs == B && mpl == M) return &k_mixed<T, B, M>;
+    KSYM_M(128, 1) KSYM_M(256, 1) KSYM_M(256, 2) KSYM_M(512, 1)
+#undef KSYM_M
+    return nullptr;
+}
+
+// ------------------------------------------------------------- eig3 -------
+template <typename T, bool AOS>
+ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void *const lam[3],
+                      void *const D[9], void *const phi[3], void *const gap[3], uint8_t *flags,
+                      void *ws, size_t ws_bytes, const ksym_opts &o, hipStream_t stream) {
+    Eig3Args<T> a;
+    memset(&a, 0, sizeof a);
+    for (int c = 0; c < 6; ++c) a.p.in[c] = AOS ? nullptr : (const T *)in[c];
+    for (int c = 0; c < 3; ++c) a.p.lam[c] = lam ? (T *)lam[c] : nullptr;
+    for (int c = 0; c < 9; ++c) a.p.D[c] = D ? (T *)D[c] : nullptr;
+    for (int c = 0; c < 3; ++c) a.p.phi[c] = phi ? (T *)phi[c] : nullptr;
+    for (int c = 0; c < 3; ++c) a.p.gap[c] = gap ? (T *)gap[c] : nullptr;
+    a.p.flags = flags;
+    a.aos = (const T *)aos;
+    a.prm.n = n;
+    a.prm.tau_gap = o.tau_gap;
+    a.prm.tau_res = o.tau_res;
+    a.prm.tau_vec = o.tau_vec;
+    a.prm.tau_dbl = o.tau_dbl;
+    a.prm.counters = (unsigned *)ws;
+    (void)ws_bytes;
+    void (*k)(Eig3Args<T>) = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        k = pick_eig3<float, PATH_FP32_FIXUP, AOS>(o.block, o.mats_per_lane);
+    } else {
+        if (o.path == KSYM_PATH_FP64_PLAIN) k = pick_eig3<double, PATH_FP64_PLAIN, AOS>(o.block, o.mats_per_lane);
+        else k = pick_eig3<double, PATH_FP64_FIXUP, AOS>(o.block, o.mats_per_lane);
+    }
+    if (!k)
+        return fail(KSYM_E_UNSUPPORTED, "no compiled 3x3 kernel for block %d, mats_per_lane %d%s",
+                    o.block, o.mats_per_lane, AOS ? " (AoS)" : "");
+    int grid = 0;
+    ksym_status s = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
+    if (s != KSYM_OK) return s;
+    hipError_t e = launch(k, dim3(grid), dim3(o.block), stream, a);
+    if (e != hipSuccess) return hip_fail(e, "launch k_eig3");
+    return KSYM_OK;
+}
+
+ksym_status check_dtype_path(ksym_dtype dt, const ksym_opts &o) {
+    if (dt == KSYM_F32 && o.path != KSYM_PATH_FP32_FIXUP)
+        return fail(KSYM_E_DTYPE, "float32 input supports only KSYM_PATH_FP32_FIXUP");
+    if (dt == KSYM_F64 && o.path != KSYM_PATH_FP64_PLAIN && o.path != KSYM_PATH_FP64_FIXUP)
+        return fail(KSYM_E_DTYPE, "float64 input supports KSYM_PATH_FP64_PLAIN or KSYM_PATH_FP64_FIXUP");
+    return KSYM_OK;
+}
+
+size_t esize(ksym_dtype dt) { return dt == KSYM_F32 ? 4 : 8; }
+
+ksym_status check_outputs3(ksym_dtype dt, void *const lam[3], void *const D[9], void *const phi[3],
+                           void *const gap[3]) {
+    const size_t es = esize(dt);
+    for (int c = 0; c < 3; ++c)
+        if (lam && !aligned(lam[c], es)) return fail(KSYM_E_ARG, "lam[%d] misaligned", c);
+    for (int c = 0; c < 9; ++c)
+        if (D && !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] misaligned", c);
+    for (int c = 0; c < 3; ++c)
+        if (phi && !aligned(phi[c], es)) return fail(KSYM_E_ARG, "phi[%d] misaligned", c);
+    for (int c = 0; c < 3; ++c)
+        if (gap && !aligned(gap[c], es)) return fail(KSYM_E_ARG, "gap[%d] misaligned", c);
+    return KSYM_OK;
+}
+
+ksym_status check_ws(void *ws, size_t ws_bytes) {
+    if (ws && ws_bytes < 8) return fail(KSYM_E_WORKSPACE, "workspace of %zu bytes is too small (need 8)", ws_bytes);
+    if (ws && !aligned(ws, 4)) return fail(KSYM_E_WORKSPACE, "workspace must be 4-byte aligned");
+    return KSYM_OK;
+}
+
+}  // namespace
+
+struct ksym_plan {
+    ksym_dtype dtype;
+    ksym_opts opts;
+    int32_t ngroups;
+    int64_t ntiles;
+    int grid;
+    void *d_groups;
+    int64_t *d_tiles;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int ksym_version(void) { return KSYM_VERSION; }
+
+const char *ksym_last_error(void) { return g_err.c_str(); }
+
+void ksym_opts_default(ksym_dtype dtype, ksym_opts *o) {
+    if (!o) return;
+    o->path = dtype == KSYM_F64 ? KSYM_PATH_FP64_FIXUP : KSYM_PATH_FP32_FIXUP;
+    o->block = 256;
+    o->mats_per_lane = 1;
+    o->grid_mult = 16;
+    o->tau_gap = 0.0;
+    o->tau_dbl = 1e-6;
+    if (dtype == KSYM_F64) {
+        o->tau_res = 1e-11;
+        o->tau_vec = 0.0;
+    } else {
+        o->tau_res = 2e-6;
+        o->tau_vec = 0.0;
+    }
+}
+
+ksym_status ksym_eig2(ksym_dtype dtype, int64_t n, const void *const in[3], void *const lam[2],
+                      void *const D[4], void *phi, uint8_t *flags, const ksym_opts *opts, void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    ksym_opts o;
+    ksym_status s = resolve_opts(dtype, opts, &o);
+    if (s != KSYM_OK) return s;
+    if (n == 0) return KSYM_OK;
+    if (!in) return fail(KSYM_E_ARG, "in is NULL");
+    const size_t es = esize(dtype);
+    for (int c = 0; c < 3; ++c) {
+        if (!in[c]) return fail(KSYM_E_ARG, "in[%d] is NULL", c);
+        if (!aligned(in[c], es)) return fail(KSYM_E_ARG, "in[%d] misaligned", c);
+    }
+    for (int c = 0; c < 2; ++c)
+        if (lam && !aligned(lam[c], es)) return fail(KSYM_E_ARG, "lam[%d] misaligned", c);
+    for (int c = 0; c < 4; ++c)
+        if (D && !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] misaligned", c);
+    if (!aligned(phi, es)) return fail(KSYM_E_ARG, "phi misaligned");
+    int grid = 0;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        Eig2Ptrs<T> p;
+        for (int c = 0; c < 3; ++c) p.in[c] = (const T *)in[c];
+        for (int c = 0; c < 2; ++c) p.lam[c] = lam ? (T *)lam[c] : nullptr;
+        for (int c = 0; c < 4; ++c) p.D[c] = D ? (T *)D[c] : nullptr;
+        p.phi = (T *)phi;
+        p.flags = flags;
+        Eig2K<T> k = pick_eig2<T>(o.block, o.mats_per_lane);
+        if (!k)
+            return fail(KSYM_E_UNSUPPORTED, "no compiled 2x2 kernel for block %d, mats_per_lane %d",
+                        o.block, o.mats_per_lane);
+        ksym_status st = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
+        if (st != KSYM_OK) return st;
+        hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, n);
+        if (e != hipSuccess) return hip_fail(e, "launch k_eig2");
+        return KSYM_OK;
+    };
+    return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+size_t ksym_eig3_workspace_bytes(ksym_dtype dtype, int64_t n) {
+    (void)dtype;
+    (void)n;
+    return 256;
+}
+
+ksym_status ksym_zero_counters(void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!ws) return fail(KSYM_E_WORKSPACE, "workspace is NULL");
+    ksym_status s = check_ws(ws, ws_bytes);
+    if (s != KSYM_OK) return s;
+    hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), (hipStream_t)stream, (unsigned *)ws, 2);
+    if (e != hipSuccess) return hip_fail(e, "launch k_zero_u32");
+    return KSYM_OK;
+}
+
+static ksym_status eig3_common(bool aos_mode, ksym_dtype dtype, int64_t n, const void *const in[6],
+                               const void *a_aos, void *const lam[3], void *const D[9],
+                               void *const phi[3], void *const gap[3], uint8_t *flags, void *ws,
+                               size_t ws_bytes, const ksym_opts *opts, void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (n >= ((int64_t)1 << 40)) return fail(KSYM_E_ARG, "n too large");
+    ksym_opts o;
+    ksym_status s = resolve_opts(dtype, opts, &o);
+    if (s != KSYM_OK) return s;
+    s = check_dtype_path(dtype, o);
+    if (s != KSYM_OK) return s;
+    if (n == 0) return KSYM_OK;
+    const size_t es = esize(dtype);
+    if (aos_mode) {
+        if (!a_aos) return fail(KSYM_E_ARG, "a_aos is NULL");
+        if (!aligned(a_aos, 16)) return fail(KSYM_E_ARG, "a_aos must be 16-byte aligned");
+    } else {
+        if (!in) return fail(KSYM_E_ARG, "in is NULL");
+        for (int c = 0; c < 6; ++c) {
+            if (!in[c]) return fail(KSYM_E_ARG, "in[%d] is NULL", c);
+            if (!aligned(in[c], es)) return fail(KSYM_E_ARG, "in[%d] misaligned", c);
+        }
+    }
+    s = check_outputs3(dtype, lam, D, phi, gap);
+    if (s != KSYM_OK) return s;
+    s = check_ws(ws, ws_bytes);
+    if (s != KSYM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == KSYM_F32)
+        return aos_mode ? eig3_impl<float, true>(n, in, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, o, st)
+                        : eig3_impl<float, false>(n, in, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, o, st);
+    return aos_mode ? eig3_impl<double, true>(n, in, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, o, st)
+                    : eig3_impl<double, false>(n, in, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, o, st);
+}
+
+ksym_status ksym_eig3(ksym_dtype dtype, int64_t n, const void *const in[6], void *const lam[3],
+                      void *const D[9], void *const phi[3], void *const gap[3], uint8_t *flags,
+                      void *ws, size_t ws_bytes, const ksym_opts *opts, void *stream) {
+    return eig3_common(false, dtype, n, in, nullptr, lam, D, phi, gap, flags, ws, ws_bytes, opts, stream);
+}
+
+ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos, void *const lam[3],
+                          void *const D[9], void *const phi[3], void *const gap[3], uint8_t *flags,
+                          void *ws, size_t ws_bytes, const ksym_opts *opts, void *stream) {
+    return eig3_common(true, dtype, n, nullptr, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, opts, stream);
+}
+
+ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                               const void *const D[9], const void *const gap[3],
+                               const void *const glam[3], const void *const gD[9], void *const gA[6],
+                               double eps_rel, void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (!(eps_rel >= 0.0) || eps_rel > 1e30) return fail(KSYM_E_ARG, "eps_rel must be finite and >= 0");
+    if (n == 0) return KSYM_OK;
+    const size_t es = esize(dtype);
+    if (!lam || !D || !gA) return fail(KSYM_E_ARG, "lam, D and gA are required");
+    for (int c = 0; c < 3; ++c)
+        if (!lam[c] || !aligned(lam[c], es)) return fail(KSYM_E_ARG, "lam[%d] NULL or misaligned", c);
+    for (int c = 0; c < 9; ++c)
+        if (!D[c] || !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] NULL or misaligned", c);
+    for (int c = 0; c < 6; ++c)
+        if (!gA[c] || !aligned(gA[c], es)) return fail(KSYM_E_ARG, "gA[%d] NULL or misaligned", c);
+    if (gap)
+        for (int c = 0; c < 3; ++c)
+            if (!gap[c] || !aligned(gap[c], es)) return fail(KSYM_E_ARG, "gap[%d] NULL or misaligned", c);
+    if (glam)
+        for (int c = 0; c < 3; ++c)
+            if (!glam[c] || !aligned(glam[c], es)) return fail(KSYM_E_ARG, "glam[%d] NULL or misaligned", c);
+    if (gD)
+        for (int c = 0; c < 9; ++c)
+            if (!gD[c] || !aligned(gD[c], es)) return fail(KSYM_E_ARG, "gD[%d] NULL or misaligned", c);
+    ksym_opts o;
+    ksym_opts_default(dtype, &o);
+    o.mats_per_lane = 1;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        BwdPtrs<T> p;
+        for (int c = 0; c < 3; ++c) p.lam[c] = (const T *)lam[c];
+        for (int c = 0; c < 9; ++c) p.D[c] = (const T *)D[c];
+        for (int c = 0; c < 3; ++c) p.gap[c] = gap ? (const T *)gap[c] : nullptr;
+        for (int c = 0; c < 3; ++c) p.glam[c] = glam ? (const T *)glam[c] : nullptr;
+        for (int c = 0; c < 9; ++c) p.gD[c] = gD ? (const T *)gD[c] : nullptr;
+        for (int c = 0; c < 6; ++c) p.gA[c] = (T *)gA[c];
+        BwdK<T> k = pick_bwd<T>(o.block, o.mats_per_lane);
+        if (!k) return fail(KSYM_E_UNSUPPORTED, "no compiled backward kernel");
+        int grid = 0;
+        ksym_status st = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
+        if (st != KSYM_OK) return st;
+        hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, n, eps_rel);
+        if (e != hipSuccess) return hip_fail(e, "launch k_eig3_bwd");
+        return KSYM_OK;
+    };
+    return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+// ------------------------------------------------------------- plans ------
+ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
+                             const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes) {
+    g_err.clear();
+    if (!plan) return fail(KSYM_E_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (ngroups <= 0 || !groups) return fail(KSYM_E_ARG, "need ngroups > 0 and a group array");
+    ksym_opts o;
+    ksym_status s = resolve_opts(dtype, opts, &o);
+    if (s != KSYM_OK) return s;
+    if (dtype == KSYM_F32) o.path = KSYM_PATH_FP32_FIXUP;
+    else o.path = KSYM_PATH_FP64_FIXUP;
+    const size_t es = esize(dtype);
+    const int tile = o.block * o.mats_per_lane;
+    const bool f32 = dtype == KSYM_F32;
+    if (f32 ? !pick_mixed<float>(o.block, o.mats_per_lane) : !pick_mixed<double>(o.block, o.mats_per_lane))
+        return fail(KSYM_E_UNSUPPORTED, "no compiled mixed kernel for block %d, mats_per_lane %d",
+                    o.block, o.mats_per_lane);
+    std::vector<int64_t> tb(ngroups + 1, 0);
+    const size_t dsz = f32 ? sizeof(GroupDesc<float>) : sizeof(GroupDesc<double>);
+    std::vector<unsigned char> desc(dsz * ngroups, 0);
+    for (int g = 0; g < ngroups; ++g) {
+        const ksym_group &G = groups[g];
+        if (G.kind != 2 && G.kind != 3) return fail(KSYM_E_ARG, "group %d: kind must be 2 or 3", g);
+        if (G.n < 0) return fail(KSYM_E_ARG, "group %d: n < 0", g);
+        const int nin = G.kind == 3 ? 6 : 3;
+        if (G.n > 0)
+            for (int c = 0; c < nin; ++c)
+                if (!G.in[c] || !aligned(G.in[c], es)) return fail(KSYM_E_ARG, "group %d: in[%d] NULL or misaligned", g, c);
+        for (int c = 0; c < 3; ++c)
+            if (!aligned(G.lam[c], es) || !aligned(G.phi[c], es)) return fail(KSYM_E_ARG, "group %d: output misaligned", g);
+        for (int c = 0; c < 9; ++c)
+            if (!aligned(G.D[c], es)) return fail(KSYM_E_ARG, "group %d: D[%d] misaligned", g, c);
+        tb[g + 1] = tb[g] + (G.n + tile - 1) / tile;
+        auto fill = [&](auto tag) {
+            using T = decltype(tag);
+            GroupDesc<T> d;
+            memset(&d, 0, sizeof d);
+            d.n = G.n;
+            d.kind = G.kind;
+            const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
+            for (int c = 0; c < nin; ++c) d.p3.in[c] = (const T *)G.in[c];
+            for (int c = 0; c < nl; ++c) d.p3.lam[c] = (T *)G.lam[c];
+            for (int c = 0; c < nd; ++c) d.p3.D[c] = (T *)G.D[c];
+            for (int c = 0; c < np; ++c) d.p3.phi[c] = (T *)G.phi[c];
+            d.p3.flags = G.flags;
+            memcpy(desc.data() + g * sizeof d, &d, sizeof d);
+        };
+        if (f32) fill(float()); else fill(double());
+    }
+    ksym_plan *p = new (std::nothrow) ksym_plan();
+    if (!p) return fail(KSYM_E_ARG, "out of host memory");
+    p->dtype = dtype;
+    p->opts = o;
+    p->ngroups = ngroups;
+    p->ntiles = tb[ngroups];
+    int cus = 0;
+    s = cu_count(&cus);
+    if (s != KSYM_OK) { delete p; return s; }
+    int64_t grid = (int64_t)o.grid_mult * cus;
+    if (grid > p->ntiles) grid = p->ntiles;
+    if (grid < 1) grid = 1;
+    p->grid = (int)grid;
+    const size_t tb_bytes = (ngroups + 1) * sizeof(int64_t);
+    const size_t total = desc.size() + 256 + tb_bytes;
+    hipError_t e = hipMalloc(&p->d_groups, total);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc plan descriptors"); }
+    p->d_tiles = (int64_t *)((char *)p->d_groups + ((desc.size() + 255) / 256) * 256);
+    e = hipMemcpy(p->d_groups, desc.data(), desc.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tb.data(), tb_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->d_groups);
+        delete p;
+        return hip_fail(e, "hipMemcpy plan descriptors");
+    }
+    *plan = p;
+    if (ws_bytes) *ws_bytes = 256;
+    return KSYM_OK;
+}
+
+ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
+    g_err.clear();
+    if (!p) return fail(KSYM_E_ARG, "plan is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (ws) {
+        hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), st, (unsigned *)ws, 2);
+        if (e != hipSuccess) return hip_fail(e, "launch k_zero_u32");
+    }
+    if (p->ntiles == 0) return KSYM_OK;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        MixedArgs<T> a;
+        memset(&a, 0, sizeof a);
+        a.groups = (const GroupDesc<T> *)p->d_groups;
+        a.tile_begin = p->d_tiles;
+        a.ngroups = p->ngroups;
+        a.ntiles = p->ntiles;
+        a.prm.n = 0;
+        a.prm.tau_gap = p->opts.tau_gap;
+        a.prm.tau_res = p->opts.tau_res;
+        a.prm.tau_vec = p->opts.tau_vec;
+        a.prm.tau_dbl = p->opts.tau_dbl;
+        a.prm.counters = (unsigned *)ws;
+        MixK<T> k = pick_mixed<T>(p->opts.block, p->opts.mats_per_lane);
+        hipError_t e = launch(k, dim3(p->grid), dim3(p->opts.block), st, a);
+        if (e != hipSuccess) return hip_fail(e, "launch k_mixed");
+        return KSYM_OK;
+    };
+    return p->dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+ksym_status ksym_plan_capture(ksym_plan *p, void *ws, void *stream) {
+    g_err.clear();
+    if (!p) return fail(KSYM_E_ARG, "plan is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return fail(KSYM_E_ARG, "capture needs a non-default stream");
+    if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    ksym_status s = ksym_plan_run(p, ws, stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (s != KSYM_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    p->graph = g;
+    p->exec = x;
+    return KSYM_OK;
+}
+
+ksym_status ksym_plan_replay(ksym_plan *p, void *stream) {
+    g_err.clear();
+    if (!p) return fail(KSYM_E_ARG, "plan is NULL");
+    if (!p->exec) return fail(KSYM_E_ARG, "plan has no captured graph (call ksym_plan_capture)");
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return KSYM_OK;
+}
+
+ksym_status ksym_plan_info(const ksym_plan *p, int64_t *tiles, int32_t *grid) {
+    g_err.clear();
+    if (!p) return fail(KSYM_E_ARG, "plan is NULL");
+    if (tiles) *tiles = p->ntiles;
+    if (grid) *grid = p->grid;
+    return KSYM_OK;
+}
+
+void ksym_plan_destroy(ksym_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_groups) (void)hipFree(p->d_groups);
+    delete p;
+}
+
+}  // extern "C"

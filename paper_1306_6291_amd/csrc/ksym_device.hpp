@@ -1,0 +1,474 @@
+// Device-side arithmetic for batched 2x2 / 3x3 symmetric eigendecomposition on
+// gfx950.  One lane owns one matrix; nothing here touches memory except through
+// the arguments.  Method: Kronenburg, arXiv:1306.6291 (§3 for 2x2, §4-§5 for
+// 3x3, §6 for the meaning of the angles).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ksym {
+
+constexpr int FLAG_GENERAL = 0, FLAG_DOUBLE = 1, FLAG_TRIPLE = 2, FLAG_FIXUP = 4,
+              FLAG_NONFINITE = 8;
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrt3 = 1.73205080756887729353;
+constexpr double kInvSqrt3 = 0.57735026918962576451;
+
+// ---------------------------------------------------------------- math -----
+// float uses the hardware approximations (v_sqrt_f32, v_rsq_f32, v_rcp_f32:
+// about 1 ulp); double uses the correctly rounded sequences.
+template <typename T> struct Mth;
+
+template <> struct Mth<float> {
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float atan2(float y, float x) { return ::atan2f(y, x); }
+    static __device__ __forceinline__ float fabs(float x) { return __builtin_fabsf(x); }
+};
+
+template <> struct Mth<double> {
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    static __device__ __forceinline__ double fabs(double x) { return __builtin_fabs(x); }
+};
+
+template <typename T> __device__ __forceinline__ T clamp01(T x) {
+    return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
+}
+
+template <typename T> __device__ __forceinline__ bool finite(T x) { return __builtin_isfinite(x); }
+
+// Power-of-two scale that brings max|a| into [0.5, 1): exact, so every
+// product below stays clear of underflow and overflow; eigenvalues are scaled
+// back at the end.  Returns the exponent e with max|a| = m * 2^e.
+__device__ __forceinline__ int scale_exponent(double amax) {
+    int e = 0;
+    if (amax > 0.0 && __builtin_isfinite(amax)) (void)__builtin_frexp(amax, &e);
+    return e;
+}
+
+// ----------------------------------------------------- 3x3 cubic stage -----
+// Paper §4, in float64.  b (4.2) and p (4.7) as printed; q through the
+// shift-invariant form q = 27 det(A - (b/3) I), which equals (4.8) in exact
+// arithmetic and avoids its O(||A||^3) cancellation.  Delta (4.9) with the
+// argument clamped to [-1, 1]; the eigenvalues (4.10)-(4.12) rewritten with
+// cos(x +- 2pi/3) = -cos(x)/2 -+ (sqrt3/2) sin(x), so one sincos(Delta/3) gives
+// all three, and the three gaps in closed form (no subtraction of nearly equal
+// eigenvalues):
+//   lam1 - lam2 = sqrt(p) (cos t + sin t / sqrt3)     (max - min)
+//   lam1 - lam3 = sqrt(p) (cos t - sin t / sqrt3)     (max - mid)
+//   lam3 - lam2 = (2 / sqrt3) sqrt(p) sin t           (mid - min),   t = Delta/3.
+struct Cubic {
+    double l1, l2, l3;      // max, min, mid
+    double g12, g13, g32;   // max-min, max-mid, mid-min (>= 0)
+    double sp;              // sqrt(p)
+    bool triple;            // p == 0
+};
+
+__device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33, double a12,
+                                             double a13, double a23) {
+    Cubic c;
+    const double b = a11 + a22 + a33;
+    const double m = b * (1.0 / 3.0);
+    const double d1 = a11 - m, d2 = a22 - m, d3 = a33 - m;
+    const double off = a12 * a12 + a13 * a13 + a23 * a23;
+    const double x12 = a11 - a22, x13 = a11 - a33, x23 = a22 - a33;
+    const double p = 0.5 * (x12 * x12 + x13 * x13 + x23 * x23) + 3.0 * off;
+    const double det = d1 * (d2 * d3 - a23 * a23) - a12 * (a12 * d3 - a13 * a23) +
+                       a13 * (a12 * a23 - a13 * d2);
+    const double q = 27.0 * det;
+    c.triple = (p == 0.0);
+    const double sp = ::sqrt(p);
+    double r = c.triple ? 0.0 : q / (2.0 * p * sp);
+    r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
+    const double Delta = ::acos(r);
+    double st, ct;
+    ::sincos(Delta * (1.0 / 3.0), &st, &ct);
+    const double spc = sp * ct, sps = sp * st * kInvSqrt3;
+    c.l1 = m + (2.0 / 3.0) * spc;
+    c.l2 = m - (spc + 3.0 * sps) * (1.0 / 3.0);
+    c.l3 = m - (spc - 3.0 * sps) * (1.0 / 3.0);
+    c.g12 = spc + sps;
+    c.g13 = spc - sps;
+    c.g32 = 2.0 * sps;
+    if (c.g13 < 0.0) c.g13 = 0.0;
+    c.sp = sp;
+    return c;
+}
+
+// ------------------------------------------------ 3x3 angle solve (§5) -----
+// Given the labelled eigenvalue differences G12 = lam1 - lam2 and
+// G32 = lam3 - lam2, and v = cos^2 phi2, w = cos^2 phi3 (5.1)-(5.2), choose the
+// signs of phi2 = +-acos(sqrt v), phi3 = +-acos(sqrt w) (5.3)-(5.4) and phi1,
+// and build D = R1 R2 R3 (2.6).
+//
+// Trig-free form of the selection.  Writing 2-vectors as complex numbers, a
+// sign combination only flips signs inside g1 = (s3*alpha, s2*beta) and
+// g2 = (gamma, s2*s3*delta) of (5.7)-(5.8).  phi1(1) = arg(conj(f1) g1) and
+// 2 phi1(2) = arg(conj(f2) g2) (the angle from f to g, (5.11)-(5.14)), so
+// e^{i phi1(2)} is the principal square root of conj(f2) g2 / |.|.  The
+// combination with the smallest circular distance |phi1(1) - phi1(2)| is the
+// one with the largest Re(z1 conj(sqrt z2)), where the norms |z1| = |f1||g1|,
+// |z2| = |f2||g2| do not depend on the signs.  Ties keep the first of
+// (+,+), (+,-), (-,+), (-,-).  phi1 is phi1(1) when |f1| >= |f2| and phi1(2)
+// otherwise (5.15); its cosine and sine come from normalising z1 or sqrt z2.
+template <typename T>
+__device__ __forceinline__ void csqrt_principal(T x, T y, T& rx, T& ry) {
+    using M = Mth<T>;
+    const T m = M::sqrt(x * x + y * y);
+    if (m == T(0)) { rx = T(0); ry = T(0); return; }
+    if (x >= T(0)) {
+        rx = M::sqrt(T(0.5) * (m + x));
+        ry = M::div(T(0.5) * y, rx);
+    } else {
+        const T t = M::sqrt(T(0.5) * (m - x));
+        ry = (y >= T(0)) ? t : -t;   // y = +-0 on the negative axis -> +i: arg = +pi
+        rx = M::div(T(0.5) * y, ry);
+    }
+}
+
+template <typename T> struct Rot {
+    T c1, s1, c2, s2, c3, s3;   // cos/sin of phi1, phi2, phi3
+};
+
+template <typename T>
+__device__ __forceinline__ Rot<T> select_angles(T a12, T a13, T a22, T a33, T a23, T G12, T G32,
+                                                T v, T w) {
+    using M = Mth<T>;
+    Rot<T> R;
+    const T c2 = M::sqrt(v), s2 = M::sqrt(T(1) - v);
+    const T c3 = M::sqrt(w), s3 = M::sqrt(T(1) - w);
+    // g1 = (s3 al, s2 be), g2 = (ga, s2 s3 de), from (5.7)-(5.8) with
+    // sin(2 phi) = 2 sin(phi) cos(phi)
+    const T al = G12 * c2 * s3 * c3;
+    const T be = (G12 * w - G32) * s2 * c2;
+    const T ga = G12 * (T(1) + (v - T(2)) * w) - G32 * v;
+    const T de = T(2) * G12 * s2 * s3 * c3;
+    // conj(f1) = (a12, a13), conj(f2) = (a22 - a33, 2 a23), from (5.5)-(5.6)
+    const T e = a22 - a33, f = T(2) * a23;
+    const T P1x = al * a12, P1y = al * a13;     // conj(f1) * al
+    const T Q1x = -be * a13, Q1y = be * a12;    // conj(f1) * i be
+    const T P2x = ga * e, P2y = ga * f;         // conj(f2) * ga
+    const T Q2x = -de * f, Q2y = de * e;        // conj(f2) * i de
+    T Rpx, Rpy, Rmx, Rmy;
+    csqrt_principal<T>(P2x + Q2x, P2y + Q2y, Rpx, Rpy);   // s2 s3 = +1
+    csqrt_principal<T>(P2x - Q2x, P2y - Q2y, Rmx, Rmy);   // s2 s3 = -1
+    const T sa = P1x * Rpx + P1y * Rpy, sb = Q1x * Rpx + Q1y * Rpy;
+    const T sc = P1x * Rmx + P1y * Rmy, sd = Q1x * Rmx + Q1y * Rmy;
+    const T Spp = sa + sb, Spm = sd - sc;   // S(-,+) = -Spm, S(-,-) = -Spp
+    int sel = 0;
+    T best = Spp;
+    if (Spm > best) { best = Spm; sel = 1; }
+    if (-Spm > best) { best = -Spm; sel = 2; }
+    if (-Spp > best) { sel = 3; }
+    const T sg2 = (sel >= 2) ? T(-1) : T(1);
+    const T sg3 = (sel & 1) ? T(-1) : T(1);
+    const bool plus = (sel == 0) || (sel == 3);
+    const T f1sq = a12 * a12 + a13 * a13, f2sq = e * e + f * f;
+    T ux, uy;
+    if (f1sq >= f2sq) {
+        ux = sg3 * P1x + sg2 * Q1x;
+        uy = sg3 * P1y + sg2 * Q1y;
+    } else {
+        ux = plus ? Rpx : Rmx;
+        uy = plus ? Rpy : Rmy;
+    }
+    const T nn = ux * ux + uy * uy;
+    if (nn > T(0)) {
+        const T inv = M::rsqrt(nn);
+        R.c1 = ux * inv;
+        R.s1 = uy * inv;
+    } else {
+        R.c1 = T(1);
+        R.s1 = T(0);
+    }
+    R.c2 = c2; R.s2 = sg2 * s2;
+    R.c3 = c3; R.s3 = sg3 * s3;
+    return R;
+}
+
+// D = R1(phi1) R2(phi2) R3(phi3), eq. (2.6), multiplied out (row-major).
+template <typename T> __device__ __forceinline__ void build_D(const Rot<T>& R, T D[9]) {
+    const T s2c3 = R.s2 * R.c3, s2s3 = R.s2 * R.s3;
+    D[0] = R.c2 * R.c3;
+    D[1] = -R.c2 * R.s3;
+    D[2] = R.s2;
+    D[3] = R.c1 * R.s3 + R.s1 * s2c3;
+    D[4] = R.c1 * R.c3 - R.s1 * s2s3;
+    D[5] = -R.s1 * R.c2;
+    D[6] = R.s1 * R.s3 - R.c1 * s2c3;
+    D[7] = R.s1 * R.c3 + R.c1 * s2s3;
+    D[8] = R.c1 * R.c2;
+}
+
+template <typename T> __device__ __forceinline__ void angles_of(const Rot<T>& R, T phi[3]) {
+    using M = Mth<T>;
+    phi[0] = M::atan2(R.s1, R.c1);
+    phi[1] = M::atan2(R.s2, R.c2);
+    phi[2] = M::atan2(R.s3, R.c3);
+}
+
+// Angles of a rotation D (det +1) with D = R1 R2 R3: phi1 from the third
+// column's (D23, D33) = cos(phi2) (-sin phi1, cos phi1); then R1(phi1)^T D =
+// R2 R3, whose second row is (sin phi3, cos phi3, 0) and whose (1,3), (3,3)
+// entries are (sin phi2, cos phi2).  Computing phi3 and phi2 from R1^T D keeps
+// D = R1 R2 R3 accurate also near cos(phi2) = 0.  If |phi3| > pi/2, columns 1
+// and 2 of D are negated (still eigenvectors, det unchanged) and phi3 moves by
+// pi, so phi2, phi3 land in [-pi/2, pi/2] like the general branch.
+template <typename T> __device__ __forceinline__ void extract_angles(T D[9], T phi[3]) {
+    using M = Mth<T>;
+    T c1 = D[8], s1 = -D[5];
+    const T h = c1 * c1 + s1 * s1;
+    if (h > T(0)) {
+        const T inv = M::rsqrt(h);
+        c1 *= inv;
+        s1 *= inv;
+    } else {
+        c1 = T(1);
+        s1 = T(0);
+    }
+    T p3s = c1 * D[3] + s1 * D[6];
+    T p3c = c1 * D[4] + s1 * D[7];
+    if (p3c < T(0)) {
+        for (int r = 0; r < 3; ++r) {
+            D[3 * r] = -D[3 * r];
+            D[3 * r + 1] = -D[3 * r + 1];
+        }
+        p3s = -p3s;
+        p3c = -p3c;
+    }
+    phi[0] = M::atan2(s1, c1);
+    phi[1] = M::atan2(D[2], c1 * D[8] - s1 * D[5]);
+    phi[2] = M::atan2(p3s, p3c);
+}
+
+// ------------------------------------------ float64 a-posteriori check -----
+// With A and the eigenvalues in float64 and D as stored (type T, promoted),
+// B = D^T A D should be diag(lam).  Fails when an off-diagonal |B_jk| exceeds
+// tau_res ||A||_F (a residual bound: ||A d_k - lam_k d_k||^2 is the sum of the
+// squares of column k of B - Lambda), when |B_jk| / |lam_j - lam_k| exceeds
+// tau_vec (the first-order angle by which d_k leans towards d_j), or when a
+// diagonal entry misses its eigenvalue by more than tau_res ||A||_F.
+template <typename T>
+__device__ __forceinline__ bool check_fails(double a11, double a22, double a33, double a12,
+                                            double a13, double a23, const Cubic& c, const T Dt[9],
+                                            double fro, double tau_res, double tau_vec) {
+    double d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = (double)Dt[i];
+    double Ad[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double x = d[k], y = d[3 + k], z = d[6 + k];
+        Ad[k] = a11 * x + a12 * y + a13 * z;
+        Ad[3 + k] = a12 * x + a22 * y + a23 * z;
+        Ad[6 + k] = a13 * x + a23 * y + a33 * z;
+    }
+    auto dot = [&](int j, int k) { return d[j] * Ad[k] + d[3 + j] * Ad[3 + k] + d[6 + j] * Ad[6 + k]; };
+    const double B01 = dot(0, 1), B02 = dot(0, 2), B12 = dot(1, 2);
+    const double B00 = dot(0, 0), B11 = dot(1, 1), B22 = dot(2, 2);
+    const double lim = tau_res * fro;
+    bool bad = !(__builtin_fabs(B01) <= lim && __builtin_fabs(B02) <= lim && __builtin_fabs(B12) <= lim);
+    bad |= !(__builtin_fabs(B00 - c.l1) <= lim && __builtin_fabs(B11 - c.l2) <= lim &&
+             __builtin_fabs(B22 - c.l3) <= lim);
+    if (tau_vec > 0.0) {
+        bad |= !(__builtin_fabs(B01) <= tau_vec * c.g12 && __builtin_fabs(B02) <= tau_vec * c.g13 &&
+                 __builtin_fabs(B12) <= tau_vec * c.g32);
+    }
+    return bad;
+}
+
+// ------------------------------------------------- float64 refinement ------
+// For matrices routed off the closed form (not in the paper): take the
+// eigenvalue lc farther from the middle one (it is separated from the other
+// two by at least half the spread), find its eigenvector u as the largest
+// cross product of two rows of A - lc I, complete u to a right-handed
+// orthonormal basis (x, y, u), diagonalise the 2x2 block [x y]^T A [x y] with
+// one rotation -- the paper's 2x2 method, §3 -- and read the eigenvalues as
+// Rayleigh quotients.  Columns are then sorted into the slots (max, min, mid),
+// one column negated if that permutation was odd, and the angles re-extracted.
+struct Refined {
+    double lam[3];
+    double D[9];
+};
+
+__device__ __forceinline__ Refined refine3(double a11, double a22, double a33, double a12,
+                                           double a13, double a23, double lc) {
+    const double r1x = a11 - lc, r1y = a12, r1z = a13;
+    const double r2x = a12, r2y = a22 - lc, r2z = a23;
+    const double r3x = a13, r3y = a23, r3z = a33 - lc;
+    // cross products of row pairs
+    double cx = r1y * r2z - r1z * r2y, cy = r1z * r2x - r1x * r2z, cz = r1x * r2y - r1y * r2x;
+    double n = cx * cx + cy * cy + cz * cz;
+    {
+        const double tx = r1y * r3z - r1z * r3y, ty = r1z * r3x - r1x * r3z, tz = r1x * r3y - r1y * r3x;
+        const double tn = tx * tx + ty * ty + tz * tz;
+        if (tn > n) { cx = tx; cy = ty; cz = tz; n = tn; }
+    }
+    {
+        const double tx = r2y * r3z - r2z * r3y, ty = r2z * r3x - r2x * r3z, tz = r2x * r3y - r2y * r3x;
+        const double tn = tx * tx + ty * ty + tz * tz;
+        if (tn > n) { cx = tx; cy = ty; cz = tz; n = tn; }
+    }
+    double ux, uy, uz;
+    if (n > 0.0) {
+        const double inv = 1.0 / ::sqrt(n);
+        ux = cx * inv; uy = cy * inv; uz = cz * inv;
+    } else {
+        ux = 0.0; uy = 0.0; uz = 1.0;   // A - lc I = 0: any basis diagonalises A
+    }
+    // x = normalise(u x e_k) with e_k the axis least aligned with u; y = u x x
+    const double ax = __builtin_fabs(ux), ay = __builtin_fabs(uy), az = __builtin_fabs(uz);
+    double xx, xy, xz;
+    if (ax <= ay && ax <= az) {        // u x e1 = (0, uz, -uy)
+        xx = 0.0; xy = uz; xz = -uy;
+    } else if (ay <= az) {             // u x e2 = (-uz, 0, ux)
+        xx = -uz; xy = 0.0; xz = ux;
+    } else {                           // u x e3 = (uy, -ux, 0)
+        xx = uy; xy = -ux; xz = 0.0;
+    }
+    {
+        const double inv = 1.0 / ::sqrt(xx * xx + xy * xy + xz * xz);
+        xx *= inv; xy *= inv; xz *= inv;
+    }
+    const double yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
+    // A x, A y, A u
+    const double Axx = a11 * xx + a12 * xy + a13 * xz, Axy = a12 * xx + a22 * xy + a23 * xz,
+                 Axz = a13 * xx + a23 * xy + a33 * xz;
+    const double Ayx = a11 * yx + a12 * yy + a13 * yz, Ayy = a12 * yx + a22 * yy + a23 * yz,
+                 Ayz = a13 * yx + a23 * yy + a33 * yz;
+    const double Aux = a11 * ux + a12 * uy + a13 * uz, Auy = a12 * ux + a22 * uy + a23 * uz,
+                 Auz = a13 * ux + a23 * uy + a33 * uz;
+    const double b11 = xx * Axx + xy * Axy + xz * Axz;
+    const double b22 = yx * Ayx + yy * Ayy + yz * Ayz;
+    const double b12 = xx * Ayx + xy * Ayy + xz * Ayz;
+    const double lu = ux * Aux + uy * Auy + uz * Auz;
+    // one rotation of the 2x2 block by the paper's 2x2 closed form (§3)
+    const double dd = b11 - b22;
+    const double sg = dd >= 0.0 ? 1.0 : -1.0;
+    const double rr = ::sqrt(dd * dd + 4.0 * b12 * b12);
+    double cphi = 1.0, sphi = 0.0;
+    if (rr > 0.0) {
+        cphi = ::sqrt(0.5 * (1.0 + __builtin_fabs(dd) / rr));
+        sphi = (b12 * sg / rr) / cphi;
+    }
+    const double mu1 = 0.5 * (b11 + b22 + sg * rr), mu2 = 0.5 * (b11 + b22 - sg * rr);
+    // columns: v0 = c x + s y (mu1), v1 = -s x + c y (mu2), v2 = u (lu)
+    double val[3] = {mu1, mu2, lu};
+    double V[3][3] = {{cphi * xx + sphi * yx, cphi * xy + sphi * yy, cphi * xz + sphi * yz},
+                      {-sphi * xx + cphi * yx, -sphi * xy + cphi * yy, -sphi * xz + cphi * yz},
+                      {ux, uy, uz}};
+    // sort descending with a 3-element network, tracking the parity
+    int odd = 0;
+    auto cswap = [&](int i, int j) {
+        if (val[j] > val[i]) {
+            const double t = val[i]; val[i] = val[j]; val[j] = t;
+            for (int r = 0; r < 3; ++r) { const double s = V[i][r]; V[i][r] = V[j][r]; V[j][r] = s; }
+            odd ^= 1;
+        }
+    };
+    cswap(0, 1);
+    cswap(1, 2);
+    cswap(0, 1);
+    // slots (max, min, mid) = sorted (0, 2, 1): one more transposition
+    odd ^= 1;
+    const double sgn = odd ? -1.0 : 1.0;
+    Refined out;
+    out.lam[0] = val[0];
+    out.lam[1] = val[2];
+    out.lam[2] = val[1];
+    for (int r = 0; r < 3; ++r) {
+        out.D[3 * r + 0] = V[0][r];
+        out.D[3 * r + 1] = V[2][r];
+        out.D[3 * r + 2] = sgn * V[1][r];
+    }
+    return out;
+}
+
+// -------------------------------------------------------- 2x2 (§3) ---------
+// lam1,2 = (t +- sign(d) r) / 2 with d = A11 - A22, r = sqrt(d^2 + 4 A12^2)
+// (3.2)-(3.3), sign(0) = +1.  phi = 1/2 atan2(2 A12 sign(d), |d|) equals
+// 1/2 arctan(2 A12 / d) of (3.5) wherever d != 0 and lies in [-pi/4, pi/4];
+// D = R(phi) (2.5) is built from the half-angle identities without trig:
+// cos(2 phi) = |d| / r, cos(phi) = sqrt((1 + cos 2phi) / 2),
+// sin(phi) = sin(2 phi) / (2 cos phi).
+template <typename T> struct Eig2 {
+    T l1, l2, c, s, phi;
+};
+
+template <typename T> __device__ __forceinline__ Eig2<T> eig2_one(T a11, T a22, T a12) {
+    using M = Mth<T>;
+    Eig2<T> o;
+    const T d = a11 - a22;
+    const T sg = d >= T(0) ? T(1) : T(-1);
+    const T ad = M::fabs(d);
+    const T y = T(2) * a12 * sg;
+    const T r = M::sqrt(d * d + y * y);
+    const T t = a11 + a22;
+    o.l1 = T(0.5) * (t + sg * r);
+    o.l2 = T(0.5) * (t - sg * r);
+    if (r > T(0)) {
+        const T ir = M::rcp(r);
+        o.c = M::sqrt(T(0.5) + T(0.5) * ad * ir);
+        o.s = M::div(T(0.5) * y * ir, o.c);
+    } else {
+        o.c = T(1);
+        o.s = T(0);
+    }
+    o.phi = T(0.5) * M::atan2(y, ad);
+    return o;
+}
+
+// ------------------------------------------------------- 3x3 adjoint -------
+// Abar = D [diag(glam) + F o (D^T gD)] D^T with F_ij = (lam_j - lam_i) /
+// ((lam_j - lam_i)^2 + eps^2).  Only the symmetric part of Abar matters for the
+// six planes: with S = M + M^T, S_ii = 2 glam_i and, because F is
+// antisymmetric, S_ij = F_ij (E_ij - E_ji) for E = D^T gD; then gA_ij =
+// (D S D^T)_ij off the diagonal and gA_ii = (D S D^T)_ii / 2.
+// Slots: 0 = max, 1 = min, 2 = mid; gaps g12 = lam0 - lam1, g13 = lam0 - lam2,
+// g32 = lam2 - lam1.
+template <typename T>
+__device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD[9], T g12, T g13,
+                                         T g32, T eps2, T gA[6]) {
+    using M = Mth<T>;
+    // K_ij = E_ij - E_ji = sum_r (D_ri gD_rj - D_rj gD_ri)
+    T K01 = T(0), K02 = T(0), K12 = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        K01 += D[3 * r] * gD[3 * r + 1] - D[3 * r + 1] * gD[3 * r];
+        K02 += D[3 * r] * gD[3 * r + 2] - D[3 * r + 2] * gD[3 * r];
+        K12 += D[3 * r + 1] * gD[3 * r + 2] - D[3 * r + 2] * gD[3 * r + 1];
+    }
+    // F_01 = (lam1 - lam0)/(..) = -g12/(g12^2+eps2); F_02 = -g13/(..); F_12 = (lam2 - lam1)/(..) = g32/(..)
+    const T S01 = -M::div(g12, g12 * g12 + eps2) * K01;
+    const T S02 = -M::div(g13, g13 * g13 + eps2) * K02;
+    const T S12 = M::div(g32, g32 * g32 + eps2) * K12;
+    const T S00 = T(2) * gl[0], S11 = T(2) * gl[1], S22 = T(2) * gl[2];
+    // Tm = D S (row-major)
+    T Tm[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T x = D[3 * i], y = D[3 * i + 1], z = D[3 * i + 2];
+        Tm[3 * i + 0] = x * S00 + y * S01 + z * S02;
+        Tm[3 * i + 1] = x * S01 + y * S11 + z * S12;
+        Tm[3 * i + 2] = x * S02 + y * S12 + z * S22;
+    }
+    auto G = [&](int i, int j) {
+        return Tm[3 * i] * D[3 * j] + Tm[3 * i + 1] * D[3 * j + 1] + Tm[3 * i + 2] * D[3 * j + 2];
+    };
+    gA[0] = T(0.5) * G(0, 0);
+    gA[1] = T(0.5) * G(1, 1);
+    gA[2] = T(0.5) * G(2, 2);
+    gA[3] = G(0, 1);
+    gA[4] = G(0, 2);
+    gA[5] = G(1, 2);
+}
+
+}  // namespace ksym

@@ -1,0 +1,226 @@
+"""GPU parity of the 3x3 forward (paper §4-§5) against the CPU oracle, through
+the C ABI.  Every input is seeded and synthetic (synth.py)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import helpers as H
+from tests.gpu_common import (LAM_TOL_F64, RES_TOL_F64, VEC_TOL_F64, certified_reference,
+                              check_f32_result, to_dev, to_np)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ksym():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_6291_amd as k
+    return k
+
+
+def _run(ksym, P, dtype, path=None, outputs=("lam", "D", "phi", "gap", "flags"), **opt):
+    t = to_dev(P, dtype)
+    o = ksym.Opts.defaults(ksym.F32 if dtype == torch.float32 else ksym.F64, **opt)
+    if path is not None:
+        o.path = path
+    ws = ksym.workspace()
+    out = ksym.eig3(t, opts=o, outputs=outputs, ws=ws)
+    torch.cuda.synchronize()
+    r = to_np(out)
+    r["ws"] = ws.cpu().numpy()
+    return r
+
+
+def _f64_parity(P, g, ref):
+    lam_err = H.sorted_lam_err(P, g["lam"], ref["lam"])
+    assert np.all(lam_err <= LAM_TOL_F64), lam_err.max()
+    res = H.residual3(P, g["lam"], g["D"])
+    assert res.max() <= RES_TOL_F64, res.max()
+    # same slots as the oracle: column-wise agreement up to sign
+    Dg, Do = H.as_mats(g["D"]), H.as_mats(ref["D"])
+    dcol = np.minimum(np.abs(Dg - Do).max(axis=1), np.abs(Dg + Do).max(axis=1))
+    assert dcol.max() <= VEC_TOL_F64, dcol.max()
+    assert np.abs(H.rot_from_angles(g["phi"]) - Dg).max() < 1e-13
+    assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
+
+
+@pytest.mark.parametrize("path_name", ["PATH_FP64_PLAIN", "PATH_FP64_FIXUP"])
+def test_plain_uniform_f64_matches_oracle(ksym, path_name):
+    """4096 matrices with U[-1,1] entries, float64: |dlam| <= 1e-12 ||A||_F,
+    residual <= 1e-10 ||A||_F, D equal to the oracle's column by column up to
+    sign (1e-8), angles reproduce D."""
+    P = synth.make_plain(4096, 16)["planes3"]
+    ref = oracle.eig3(P)
+    g = _run(ksym, P, torch.float64, path=getattr(ksym, path_name))
+    _f64_parity(P, g, ref)
+    # the general branch everywhere, like the oracle
+    assert np.all((g["flags"] & 3) == 0)
+    # angles agree with the oracle's up to the symmetry of D's columns
+    if path_name == "PATH_FP64_PLAIN":
+        assert np.all(g["flags"] == 0)
+
+
+def test_plain_f64_ragged_sizes_and_launch_shapes(ksym):
+    """Sizes that leave ragged tails, several launch shapes: bitwise identical
+    outputs, all matching the oracle."""
+    P = synth.make_plain(5000, 16, seed=77)["planes3"]
+    ref = None
+    for n in (1, 63, 64, 65, 1000, 4999):
+        Pn = np.ascontiguousarray(P[:, :n])
+        ref = oracle.eig3(Pn)
+        g = _run(ksym, Pn, torch.float64, path=ksym.PATH_FP64_PLAIN)
+        _f64_parity(Pn, g, ref)
+    base = _run(ksym, P, torch.float64, path=ksym.PATH_FP64_FIXUP)
+    for block, mpl, gm in ((64, 1, 1), (128, 1, 3), (256, 2, 1), (256, 1, 64)):
+        g = _run(ksym, P, torch.float64, path=ksym.PATH_FP64_FIXUP, block=block,
+                 mats_per_lane=mpl, grid_mult=gm)
+        for k in ("lam", "D", "phi", "gap", "flags"):
+            assert np.array_equal(g[k], base[k]), (block, mpl, gm, k)
+
+
+def test_f64_double_and_triple_branches(ksym):
+    """Exact double and triple spectra: the plain path takes the paper's
+    special cases (5.20)-(5.25) and p = 0; slots, det and residual hold."""
+    rng = np.random.default_rng(91)
+    n = 2000
+    a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    keep = np.abs(a - c) > 0.1
+    a, c = a[keep], c[keep]
+    P = np.zeros((6, a.size))
+    P[0], P[1], P[2] = a, a, c
+    P2 = np.zeros((6, a.size))
+    P2[0], P2[1], P2[2] = c, a, a
+    Pt = np.zeros((6, 64))
+    Pt[0:3] = np.linspace(-2, 2, 64)
+    for Q in (P, P2):
+        ref = oracle.eig3(Q)
+        for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
+            g = _run(ksym, Q, torch.float64, path=path)
+            assert np.all(g["flags"] & 1), path
+            assert H.sorted_lam_err(Q, g["lam"], ref["lam"]).max() < 1e-14
+            assert H.residual3(Q, g["lam"], g["D"]).max() < (1e-7 if path == ksym.PATH_FP64_PLAIN else 1e-14)
+            assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
+            L = g["lam"]
+            assert np.all(L[0] >= L[2]) and np.all(L[2] >= L[1])
+            assert np.abs(H.rot_from_angles(g["phi"]) - H.as_mats(g["D"])).max() < 1e-13
+    g = _run(ksym, Pt, torch.float64, path=ksym.PATH_FP64_PLAIN)
+    assert np.all(g["flags"] == 2)
+    assert np.array_equal(g["lam"], np.stack([Pt[0]] * 3))
+    assert np.array_equal(H.as_mats(g["D"]), np.broadcast_to(np.eye(3), (64, 3, 3)))
+    assert np.all(g["phi"] == 0)
+
+
+def test_precision_workload_f32_small(ksym):
+    """The precision workload's recipe at 2^17 + 77 matrices (ragged tail):
+    float32 in and out, float64 cubic step, refinement of flagged matrices."""
+    n = (1 << 17) + 77
+    P32 = synth.make_precision(n, seed=1306630)
+    P64 = P32.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    g = _run(ksym, P32, torch.float32)
+    stats = check_f32_result(P64, g, lam_ref, V_ref, "precision-f32")
+    flags = g["flags"]
+    nfix = int(np.sum((flags & 4) != 0))
+    assert int(g["ws"][0]) == nfix
+    assert int(g["ws"][1]) == 0
+    print("precision f32:", stats, "refined fraction", nfix / n)
+
+
+def test_plain_uniform_f32(ksym):
+    """U[-1,1] float32 matrices through the float32 path."""
+    P32 = synth.make_plain(1 << 16, 16, seed=55, dtype=np.float32)["planes3"]
+    P64 = P32.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    g = _run(ksym, P32, torch.float32)
+    check_f32_result(P64, g, lam_ref, V_ref, "uniform-f32")
+
+
+def test_f32_launch_shapes_bitwise(ksym):
+    """Every compiled launch shape gives bitwise-identical float32 results, and
+    two runs of the same shape agree bitwise (the refinement queue order does
+    not leak into the results)."""
+    P32 = synth.make_precision(50000, seed=4242)
+    base = _run(ksym, P32, torch.float32)
+    again = _run(ksym, P32, torch.float32)
+    for k in ("lam", "D", "phi", "gap", "flags"):
+        assert np.array_equal(base[k], again[k], equal_nan=True), k
+    for block, mpl in ((64, 1), (64, 4), (128, 2), (256, 1), (256, 2), (256, 4), (512, 1), (512, 2)):
+        for gm in (1, 16):
+            g = _run(ksym, P32, torch.float32, block=block, mats_per_lane=mpl, grid_mult=gm)
+            for k in ("lam", "D", "phi", "gap", "flags"):
+                assert np.array_equal(g[k], base[k], equal_nan=True), (block, mpl, gm, k)
+
+
+def test_special_inputs_f32(ksym):
+    """Zero, isotropic, diagonal, exact doubles, tiny and huge scales, and
+    non-finite entries."""
+    rng = np.random.default_rng(5)
+    cols = []
+    cols.append(np.zeros(6))
+    cols.append(np.array([2.5, 2.5, 2.5, 0, 0, 0]))
+    cols.append(np.array([1, 1, 3, 0, 0, 0.0]))
+    cols.append(np.array([3, 1, 2, 0, 0, 0.0]))
+    cols.append(np.array([2, 2, 2, 1, 1, 1.0]))
+    for s in (1e-30, 1e-12, 1e12, 1e30):
+        cols.append(rng.uniform(-1, 1, 6) * s)
+    P = np.stack(cols, 1).astype(np.float32)
+    P64 = P.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    g = _run(ksym, P, torch.float32)
+    check_f32_result(P64, g, lam_ref, V_ref, "special")
+    assert np.all(g["flags"][:2] == 2)
+    bad = np.array([[np.nan, 0, 0, 0, 0, 0], [0, np.inf, 0, 0, 0, 0], [1, 1, 1, 0, -np.inf, 0]],
+                   dtype=np.float32).T
+    g = _run(ksym, np.ascontiguousarray(bad), torch.float32)
+    assert np.all(g["flags"] == 8)
+    assert np.all(np.isnan(g["lam"])) and np.all(np.isnan(g["D"]))
+    assert int(g["ws"][1]) == 3
+
+
+def test_all_matrices_refined_f32(ksym):
+    """A batch where every matrix takes the refinement (exact doubles):
+    the on-chip queue fills completely at every launch shape."""
+    rng = np.random.default_rng(6)
+    n = 20000
+    a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    Q = synth.haar_rotations(rng, n)
+    P32 = synth._sandwich(Q, np.stack([a, a, c], 1)).astype(np.float32)
+    P64 = P32.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    for block, mpl in ((64, 1), (256, 4), (512, 2)):
+        g = _run(ksym, P32, torch.float32, block=block, mats_per_lane=mpl, tau_gap=1.0)
+        assert np.all(g["flags"] & 4)
+        check_f32_result(P64, g, lam_ref, V_ref, f"all-refined {block}x{mpl}")
+
+
+def test_optional_outputs(ksym):
+    P32 = synth.make_plain(3000, 16, seed=8, dtype=np.float32)["planes3"]
+    full = _run(ksym, P32, torch.float32)
+    part = _run(ksym, P32, torch.float32, outputs=("lam",))
+    assert set(part) == {"lam", "ws"}
+    assert np.array_equal(part["lam"], full["lam"])
+
+
+def test_aos_matches_soa(ksym):
+    """Array-of-structures input (records of six) gives bitwise the SoA result."""
+    P32 = synth.make_precision(70001, seed=99)
+    soa = _run(ksym, P32, torch.float32)
+    rec = to_dev(np.ascontiguousarray(P32.T), torch.float32)
+    for block, mpl in ((64, 1), (128, 2), (256, 1), (256, 2), (512, 1)):
+        o = ksym.Opts.defaults(ksym.F32, block=block, mats_per_lane=mpl)
+        out = ksym.eig3_aos(rec, opts=o, outputs=("lam", "D", "phi", "gap", "flags"))
+        torch.cuda.synchronize()
+        out = to_np(out)
+        for k in ("lam", "D", "phi", "gap", "flags"):
+            assert np.array_equal(out[k], soa[k]), (block, mpl, k)
+    P64 = synth.make_plain(3001, 16, seed=3)["planes3"]
+    soa = _run(ksym, P64, torch.float64, path=ksym.PATH_FP64_FIXUP)
+    out = to_np(ksym.eig3_aos(to_dev(np.ascontiguousarray(P64.T), torch.float64),
+                              outputs=("lam", "D", "phi", "gap", "flags")))
+    for k in ("lam", "D", "phi", "gap", "flags"):
+        assert np.array_equal(out[k], soa[k]), k
