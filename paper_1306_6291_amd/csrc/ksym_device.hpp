@@ -55,29 +55,50 @@ __device__ __forceinline__ int scale_exponent(double amax) {
 }
 
 // ----------------------------------------------------- 3x3 cubic stage -----
-// Paper §4, in float64.  b (4.2) and p (4.7) as printed; q through the
-// shift-invariant form q = 27 det(A - (b/3) I), which equals (4.8) in exact
-// arithmetic and avoids its O(||A||^3) cancellation.  Delta (4.9) with the
-// argument clamped to [-1, 1]; the eigenvalues (4.10)-(4.12) rewritten with
-// cos(x +- 2pi/3) = -cos(x)/2 -+ (sqrt3/2) sin(x), so one sincos(Delta/3) gives
-// all three, and the three gaps in closed form (no subtraction of nearly equal
-// eigenvalues):
+// Paper §4, in float64, on the trace-free part B = A - m I with m = b/3.
+// The shift is computed so that B's diagonal is exact when A is close to
+// isotropic: m0 = A11 + ((A22 - A11) + (A33 - A11)) / 3, d_i = A_ii - m0
+// (exact there by Sterbenz' lemma), then the rounding left in the trace is
+// removed, d_i -= (d1 + d2 + d3) / 3, and m = m0 + that amount.  Every
+// eigenvalue is carried as its deviation mu_k = lam_k - m, so quantities such
+// as A11 - lam_k = d1 - mu_k keep their relative accuracy even when the spread
+// of the spectrum is far below the last digit of m.
+//   b (4.2) enters only through m; p (4.7) as printed (it uses only the
+//   differences A_ii - A_jj); q through q = 27 det(B), which equals (4.8) in
+//   exact arithmetic and avoids its O(||A||^3) cancellation; Delta (4.9) with
+//   its argument clamped to [-1, 1]; (4.10)-(4.12) rewritten with
+//   cos(x +- 2pi/3) = -cos(x)/2 -+ (sqrt3/2) sin(x), so one sincos(Delta/3)
+//   gives all three, and the gaps in closed form:
 //   lam1 - lam2 = sqrt(p) (cos t + sin t / sqrt3)     (max - min)
 //   lam1 - lam3 = sqrt(p) (cos t - sin t / sqrt3)     (max - mid)
 //   lam3 - lam2 = (2 / sqrt3) sqrt(p) sin t           (mid - min),   t = Delta/3.
 struct Cubic {
-    double l1, l2, l3;      // max, min, mid
-    double g12, g13, g32;   // max-min, max-mid, mid-min (>= 0)
-    double sp;              // sqrt(p)
-    bool triple;            // p == 0
+    double m;                 // centre: lam_k = m + mu_k
+    double d1, d2, d3;        // diagonal of B = A - m I (trace 0 up to rounding)
+    double mu1, mu2, mu3;     // deviations of max, min, mid
+    double g12, g13, g32;     // max-min, max-mid, mid-min (>= 0)
+    double sp;                // sqrt(p)
+    bool triple;              // p == 0
 };
+
+__device__ __forceinline__ void center3(double a11, double a22, double a33, double &m, double &d1,
+                                        double &d2, double &d3) {
+    const double m0 = a11 + ((a22 - a11) + (a33 - a11)) * (1.0 / 3.0);
+    d1 = a11 - m0;
+    d2 = a22 - m0;
+    d3 = a33 - m0;
+    const double t = (d1 + d2 + d3) * (1.0 / 3.0);
+    d1 -= t;
+    d2 -= t;
+    d3 -= t;
+    m = m0 + t;
+}
 
 __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33, double a12,
                                              double a13, double a23) {
     Cubic c;
-    const double b = a11 + a22 + a33;
-    const double m = b * (1.0 / 3.0);
-    const double d1 = a11 - m, d2 = a22 - m, d3 = a33 - m;
+    center3(a11, a22, a33, c.m, c.d1, c.d2, c.d3);
+    const double d1 = c.d1, d2 = c.d2, d3 = c.d3;
     const double off = a12 * a12 + a13 * a13 + a23 * a23;
     const double x12 = a11 - a22, x13 = a11 - a33, x23 = a22 - a33;
     const double p = 0.5 * (x12 * x12 + x13 * x13 + x23 * x23) + 3.0 * off;
@@ -92,9 +113,9 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
     double st, ct;
     ::sincos(Delta * (1.0 / 3.0), &st, &ct);
     const double spc = sp * ct, sps = sp * st * kInvSqrt3;
-    c.l1 = m + (2.0 / 3.0) * spc;
-    c.l2 = m - (spc + 3.0 * sps) * (1.0 / 3.0);
-    c.l3 = m - (spc - 3.0 * sps) * (1.0 / 3.0);
+    c.mu1 = (2.0 / 3.0) * spc;
+    c.mu2 = -(spc + 3.0 * sps) * (1.0 / 3.0);
+    c.mu3 = -(spc - 3.0 * sps) * (1.0 / 3.0);
     c.g12 = spc + sps;
     c.g13 = spc - sps;
     c.g32 = 2.0 * sps;
@@ -251,33 +272,34 @@ template <typename T> __device__ __forceinline__ void extract_angles(T D[9], T p
 
 // ------------------------------------------ float64 a-posteriori check -----
 // With A and the eigenvalues in float64 and D as stored (type T, promoted),
-// B = D^T A D should be diag(lam).  Fails when an off-diagonal |B_jk| exceeds
+// D^T A D should be diag(lam).  Fails when an off-diagonal |B_jk| exceeds
 // tau_res ||A||_F (a residual bound: ||A d_k - lam_k d_k||^2 is the sum of the
 // squares of column k of B - Lambda), when |B_jk| / |lam_j - lam_k| exceeds
 // tau_vec (the first-order angle by which d_k leans towards d_j), or when a
 // diagonal entry misses its eigenvalue by more than tau_res ||A||_F.
 template <typename T>
-__device__ __forceinline__ bool check_fails(double a11, double a22, double a33, double a12,
-                                            double a13, double a23, const Cubic& c, const T Dt[9],
-                                            double fro, double tau_res, double tau_vec) {
+__device__ __forceinline__ bool check_fails(const Cubic &c, double a12, double a13, double a23,
+                                            const T Dt[9], double fro, double tau_res, double tau_vec) {
     double d[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = (double)Dt[i];
+    // B d_k with B = A - m I; off-diagonal entries of D^T B D equal those of
+    // D^T A D, the diagonal ones are compared with the deviations mu_k
     double Ad[9];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double x = d[k], y = d[3 + k], z = d[6 + k];
-        Ad[k] = a11 * x + a12 * y + a13 * z;
-        Ad[3 + k] = a12 * x + a22 * y + a23 * z;
-        Ad[6 + k] = a13 * x + a23 * y + a33 * z;
+        Ad[k] = c.d1 * x + a12 * y + a13 * z;
+        Ad[3 + k] = a12 * x + c.d2 * y + a23 * z;
+        Ad[6 + k] = a13 * x + a23 * y + c.d3 * z;
     }
     auto dot = [&](int j, int k) { return d[j] * Ad[k] + d[3 + j] * Ad[3 + k] + d[6 + j] * Ad[6 + k]; };
     const double B01 = dot(0, 1), B02 = dot(0, 2), B12 = dot(1, 2);
     const double B00 = dot(0, 0), B11 = dot(1, 1), B22 = dot(2, 2);
     const double lim = tau_res * fro;
     bool bad = !(__builtin_fabs(B01) <= lim && __builtin_fabs(B02) <= lim && __builtin_fabs(B12) <= lim);
-    bad |= !(__builtin_fabs(B00 - c.l1) <= lim && __builtin_fabs(B11 - c.l2) <= lim &&
-             __builtin_fabs(B22 - c.l3) <= lim);
+    bad |= !(__builtin_fabs(B00 - c.mu1) <= lim && __builtin_fabs(B11 - c.mu2) <= lim &&
+             __builtin_fabs(B22 - c.mu3) <= lim);
     if (tau_vec > 0.0) {
         bad |= !(__builtin_fabs(B01) <= tau_vec * c.g12 && __builtin_fabs(B02) <= tau_vec * c.g13 &&
                  __builtin_fabs(B12) <= tau_vec * c.g32);
@@ -299,6 +321,8 @@ struct Refined {
     double D[9];
 };
 
+// Input: the shifted diagonal (a11, a22, a33) = diag(A - m I), the
+// off-diagonal entries and lc as a deviation from m; outputs are deviations.
 __device__ __forceinline__ Refined refine3(double a11, double a22, double a33, double a12,
                                            double a13, double a23, double lc) {
     const double r1x = a11 - lc, r1y = a12, r1z = a13;

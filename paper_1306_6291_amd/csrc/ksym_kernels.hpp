@@ -87,11 +87,12 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
         const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
         const T A12 = (T)a12, A13 = (T)a13, A22 = (T)a22, A33 = (T)a33, A23 = (T)a23;
         if (PATH == PATH_FP64_PLAIN && dbl) {
-            // double root: labels (lam, lam, lam_s), s = cos^2 phi2 (5.21), phi3 = 0
+            // double root: labels (lam, lam, lam_s), s = cos^2 phi2 (5.21), phi3 = 0;
+            // deviations from the centre m keep s accurate when the spread is tiny
             double lm, ls;
-            if (cu.g13 < cu.g32) { lm = 0.5 * (cu.l1 + cu.l3); ls = cu.l2; }
-            else { lm = 0.5 * (cu.l3 + cu.l2); ls = cu.l1; }
-            const T s = clamp01((T)((a11 - ls) / (lm - ls)));
+            if (cu.g13 < cu.g32) { lm = 0.5 * (cu.mu1 + cu.mu3); ls = cu.mu2; }
+            else { lm = 0.5 * (cu.mu3 + cu.mu2); ls = cu.mu1; }
+            const T s = clamp01((T)((cu.d1 - ls) / (lm - ls)));
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, T(0), (T)(ls - lm), s, T(1));
             T Di[9];
             build_D(R, Di);
@@ -108,7 +109,7 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
                 L[0] = lm; L[1] = ls; L[2] = lm;
             }
             extract_angles<T>(o.D, o.phi);
-            for (int k = 0; k < 3; ++k) o.lam[k] = (T)(L[k] * isc);
+            for (int k = 0; k < 3; ++k) o.lam[k] = (T)((cu.m + L[k]) * isc);
             o.gap[0] = (T)((L[0] - L[1]) * isc);
             o.gap[1] = (T)((L[0] - L[2]) * isc);
             o.gap[2] = (T)((L[2] - L[1]) * isc);
@@ -117,15 +118,15 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             // general branch (5.1)-(5.15): v, w with the eigenvalue
             // differences taken from the float64 stage
             const T G12 = (T)cu.g12, G13 = (T)cu.g13, G32 = (T)cu.g32;
-            const T e1 = (T)(a11 - cu.l1), e3 = (T)(a11 - cu.l3);
+            const T e1 = (T)(cu.d1 - cu.mu1), e3 = (T)(cu.d1 - cu.mu3);   // A11 - lam1, A11 - lam3
             const T v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
             const T w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G32, v, w);
             build_D(R, o.D);
             angles_of(R, o.phi);
-            o.lam[0] = (T)(cu.l1 * isc);
-            o.lam[1] = (T)(cu.l2 * isc);
-            o.lam[2] = (T)(cu.l3 * isc);
+            o.lam[0] = (T)((cu.m + cu.mu1) * isc);
+            o.lam[1] = (T)((cu.m + cu.mu2) * isc);
+            o.lam[2] = (T)((cu.m + cu.mu3) * isc);
             o.gap[0] = (T)(cu.g12 * isc);
             o.gap[1] = (T)(cu.g13 * isc);
             o.gap[2] = (T)(cu.g32 * isc);
@@ -133,12 +134,11 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             if (PATH != PATH_FP64_PLAIN) {
                 const double fro = ::sqrt(a11 * a11 + a22 * a22 + a33 * a33 +
                                           2.0 * (a12 * a12 + a13 * a13 + a23 * a23));
-                const double lmax = fmax(__builtin_fabs(cu.l1), __builtin_fabs(cu.l2));
+                const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
                 bool bad = dbl || (split < prm.tau_gap * lmax);
-                bad = bad || check_fails<T>(a11, a22, a33, a12, a13, a23, cu, o.D, fro, prm.tau_res,
-                                            prm.tau_vec);
+                bad = bad || check_fails<T>(cu, a12, a13, a23, o.D, fro, prm.tau_res, prm.tau_vec);
                 o.refine = bad;
-                o.lc = (cu.g13 >= cu.g32) ? cu.l1 : cu.l2;
+                o.lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
             }
         }
     }
@@ -171,7 +171,8 @@ __device__ __forceinline__ void store3(const Eig3Ptrs<T> &p, int64_t i, const Ou
 }
 
 // The refinement of one queued matrix (original entries ain, isolated
-// eigenvalue lc in the scaled units eig3_one used).
+// eigenvalue lc as a deviation from the centre, in the scaled units eig3_one
+// used; the centre is recomputed here with the same arithmetic).
 template <typename T>
 __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, Out3<T> &o) {
     double amax = 0.0;
@@ -179,13 +180,15 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
     for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs((double)ain[c]));
     const int ex = scale_exponent(amax);
     const double sc = pow2(-ex), isc = pow2(ex);
-    const Refined rf = refine3((double)ain[0] * sc, (double)ain[1] * sc, (double)ain[2] * sc,
-                               (double)ain[3] * sc, (double)ain[4] * sc, (double)ain[5] * sc, lc);
+    double m, d1, d2, d3;
+    center3((double)ain[0] * sc, (double)ain[1] * sc, (double)ain[2] * sc, m, d1, d2, d3);
+    const Refined rf = refine3(d1, d2, d3, (double)ain[3] * sc, (double)ain[4] * sc,
+                               (double)ain[5] * sc, lc);
 #pragma unroll
     for (int i = 0; i < 9; ++i) o.D[i] = (T)rf.D[i];
     extract_angles<T>(o.D, o.phi);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) o.lam[k] = (T)(rf.lam[k] * isc);
+    for (int k = 0; k < 3; ++k) o.lam[k] = (T)((m + rf.lam[k]) * isc);
     o.gap[0] = (T)(fmax(rf.lam[0] - rf.lam[1], 0.0) * isc);
     o.gap[1] = (T)(fmax(rf.lam[0] - rf.lam[2], 0.0) * isc);
     o.gap[2] = (T)(fmax(rf.lam[2] - rf.lam[1], 0.0) * isc);

@@ -224,3 +224,59 @@ def test_aos_matches_soa(ksym):
                               outputs=("lam", "D", "phi", "gap", "flags")))
     for k in ("lam", "D", "phi", "gap", "flags"):
         assert np.array_equal(out[k], soa[k]), k
+
+
+def test_f64_paths_on_precision_recipe(ksym):
+    """Both float64 paths on the precision recipe (float32-rounded matrices
+    promoted): no NaN; orthonormal D with det +1; the refining path meets
+    residual <= 1e-11 ||A||_F everywhere; the plain path meets the float32
+    tolerances away from its known weak spot (relative gaps below 1e-3, where
+    the closed-form angle solve loses accuracy even in float64)."""
+    import os
+    n = (1 << 16) + 5
+    P32, kinds = synth.make_precision(n, seed=1306631, return_kinds=True)
+    P64 = P32.astype(np.float64)
+    for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
+        g = _run(ksym, P64, torch.float64, path=path)
+        bad = ~np.isfinite(g["D"]).all(0) | ~np.isfinite(g["lam"]).all(0) | ~np.isfinite(g["phi"]).all(0)
+        if bad.any():
+            os.makedirs("gpurun_out", exist_ok=True)
+            idx = np.nonzero(bad)[0][:50]
+            np.savetxt(f"gpurun_out/nan_inputs_path{path}.txt", P64[:, idx].T, fmt="%.17g")
+            np.savetxt(f"gpurun_out/nan_kinds_path{path}.txt", kinds[idx], fmt="%d")
+        assert not bad.any(), (path, int(bad.sum()), np.bincount(kinds[bad], minlength=6))
+        assert H.orth_err(g["D"]).max() < 1e-14
+        assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
+        res = H.residual3(P64, g["lam"], g["D"])
+        if path == ksym.PATH_FP64_FIXUP:
+            assert res.max() < 2e-11, res.max()   # each |B_jk| <= 1e-11 ||A||_F: sqrt(3) x
+        else:
+            lam_ref, _ = certified_reference(P64)
+            g_rel = H.rel_gaps(lam_ref).min(0)
+            ok = g_rel >= 1e-3
+            assert res[ok].max() < 1e-5, res[ok].max()
+
+
+@pytest.mark.parametrize("spread", [0.0, 1e-12, 1e-9, 1e-6])
+def test_near_isotropic_all_paths(ksym, spread):
+    """a I rotated by Haar matrices (rounding leaves off-diagonals around 1e-17)
+    plus perturbations of relative size `spread`: every path returns finite,
+    orthonormal D with det +1 and residual at the level of float rounding."""
+    rng = np.random.default_rng(int(spread * 1e15) + 17)
+    n = 20000
+    a = rng.uniform(-1, 1, n)
+    Q = synth.haar_rotations(rng, n)
+    lam = a[:, None] + spread * rng.standard_normal((n, 3))
+    P32 = synth._sandwich(Q, lam).astype(np.float32)
+    P64 = P32.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    g = _run(ksym, P32, torch.float32)
+    check_f32_result(P64, g, lam_ref, V_ref, f"near-iso f32 {spread}")
+    for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
+        g = _run(ksym, P64, torch.float64, path=path)
+        assert np.isfinite(g["D"]).all() and np.isfinite(g["lam"]).all() and np.isfinite(g["phi"]).all()
+        assert H.orth_err(g["D"]).max() < 1e-14
+        assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
+        jac = oracle.jacobi3(P64)["lam"]
+        assert H.sorted_lam_err(P64, g["lam"], jac).max() < 1e-14
+        assert H.residual3(P64, g["lam"], g["D"]).max() < 1e-13
