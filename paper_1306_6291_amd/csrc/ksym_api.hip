@@ -192,10 +192,10 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     Eig3Args<T> a;
     memset(&a, 0, sizeof a);
     for (int c = 0; c < 6; ++c) a.p.in[c] = AOS ? nullptr : (const T *)in[c];
-    for (int c = 0; c < 3; ++c) a.p.lam[c] = lam ? (T *)lam[c] : nullptr;
-    for (int c = 0; c < 9; ++c) a.p.D[c] = D ? (T *)D[c] : nullptr;
-    for (int c = 0; c < 3; ++c) a.p.phi[c] = phi ? (T *)phi[c] : nullptr;
-    for (int c = 0; c < 3; ++c) a.p.gap[c] = gap ? (T *)gap[c] : nullptr;
+    for (int c = 0; c < 3; ++c) a.p.out[O_LAM + c] = lam ? (T *)lam[c] : nullptr;
+    for (int c = 0; c < 9; ++c) a.p.out[O_D + c] = D ? (T *)D[c] : nullptr;
+    for (int c = 0; c < 3; ++c) a.p.out[O_PHI + c] = phi ? (T *)phi[c] : nullptr;
+    for (int c = 0; c < 3; ++c) a.p.out[O_GAP + c] = gap ? (T *)gap[c] : nullptr;
     a.p.flags = flags;
     a.aos = (const T *)aos;
     a.prm.n = n;
@@ -490,9 +490,9 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
             d.kind = G.kind;
             const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
             for (int c = 0; c < nin; ++c) d.p3.in[c] = (const T *)G.in[c];
-            for (int c = 0; c < nl; ++c) d.p3.lam[c] = (T *)G.lam[c];
-            for (int c = 0; c < nd; ++c) d.p3.D[c] = (T *)G.D[c];
-            for (int c = 0; c < np; ++c) d.p3.phi[c] = (T *)G.phi[c];
+            for (int c = 0; c < nl; ++c) d.p3.out[O_LAM + c] = (T *)G.lam[c];
+            for (int c = 0; c < nd; ++c) d.p3.out[O_D + c] = (T *)G.D[c];
+            for (int c = 0; c < np; ++c) d.p3.out[O_PHI + c] = (T *)G.phi[c];
             d.p3.flags = G.flags;
             memcpy(desc.data() + g * sizeof d, &d, sizeof d);
         };

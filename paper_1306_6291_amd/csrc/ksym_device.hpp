@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ksym_poly.hpp"
+
 namespace ksym {
 
 constexpr int FLAG_GENERAL = 0, FLAG_DOUBLE = 1, FLAG_TRIPLE = 2, FLAG_FIXUP = 4,
@@ -15,6 +17,8 @@ constexpr int FLAG_GENERAL = 0, FLAG_DOUBLE = 1, FLAG_TRIPLE = 2, FLAG_FIXUP = 4
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt3 = 1.73205080756887729353;
 constexpr double kInvSqrt3 = 0.57735026918962576451;
+
+__device__ __forceinline__ float atan2_fast(float y, float x);
 
 // ---------------------------------------------------------------- math -----
 // float uses the hardware approximations (v_sqrt_f32, v_rsq_f32, v_rcp_f32:
@@ -26,7 +30,7 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-    static __device__ __forceinline__ float atan2(float y, float x) { return ::atan2f(y, x); }
+    static __device__ __forceinline__ float atan2(float y, float x) { return atan2_fast(y, x); }
     static __device__ __forceinline__ float fabs(float x) { return __builtin_fabsf(x); }
 };
 
@@ -52,6 +56,117 @@ __device__ __forceinline__ int scale_exponent(double amax) {
     int e = 0;
     if (amax > 0.0 && __builtin_isfinite(amax)) (void)__builtin_frexp(amax, &e);
     return e;
+}
+
+// ------------------------------------------------ polynomial kernels -----
+// Coefficients and their derivation: ksym_poly.hpp / gen_poly.py.
+
+// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+// sqrt(z) for z in [0, 1/4]: sqrt = z / sqrt(z) with one correction step.
+__device__ __forceinline__ double sqrt_small64(double z) {
+    const double y = rsqrt64(z);
+    double s = z * y;
+    const double d = __builtin_fma(-s, s, z);
+    s = __builtin_fma(0.5 * y, d, s);
+    return z > 0.0 ? s : 0.0;
+}
+
+// arccos(r) for r in [-1, 1] through asin: |r| <= 1/2 uses
+// acos r = pi/2 - asin r; otherwise acos |r| = 2 asin(sqrt((1 - |r|)/2)),
+// and acos(-x) = pi - acos(x).
+__device__ __forceinline__ double acos64(double r) {
+    const double ar = __builtin_fabs(r);
+    const bool small = ar <= 0.5;
+    const double z = small ? ar * ar : 0.5 * (1.0 - ar);
+    const double x = small ? ar : sqrt_small64(z);
+    double P = poly::ASIN[11];
+#pragma unroll
+    for (int k = 10; k >= 0; --k) P = __builtin_fma(P, z, poly::ASIN[k]);
+    const double a = __builtin_fma(x * z, P, x);   // asin(x)
+    const double big = 2.0 * a;                     // acos(|r|) for |r| > 1/2
+    if (small) return 0.5 * kPi - (r < 0.0 ? -a : a);
+    return r < 0.0 ? kPi - big : big;
+}
+
+// sin and cos of t in [0, pi/3] (Taylor series, no argument reduction).
+__device__ __forceinline__ void sincos_third(double t, double &s, double &c) {
+    const double t2 = t * t;
+    double ps = poly::S[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) ps = __builtin_fma(ps, t2, poly::S[k]);
+    double pc = poly::C[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) pc = __builtin_fma(pc, t2, poly::C[k]);
+    s = t * ps;
+    c = pc;
+}
+
+// Float32-tail versions for the float32 path: the leading terms are formed in
+// float64 and only the small correction (at most 5-18 % of the result) in
+// float32, with coefficients that are literal operands.  Relative accuracy
+// about 1e-8, which is what float32 results need, while the float64 argument
+// keeps the sqrt(eps) amplification of arccos near |r| = 1 at float64 level.
+__device__ __forceinline__ float tail_poly(const float *c, int deg, float t) {
+    float p = c[deg];
+#pragma unroll
+    for (int k = deg - 1; k >= 0; --k) p = __builtin_fmaf(p, t, c[k]);
+    return p;
+}
+
+// arccos(r) and pi - arccos(r), each formed without cancellation.
+__device__ __forceinline__ void acos_pair_fast(double r, double &D, double &Dc) {
+    const double ar = __builtin_fabs(r);
+    const bool small = ar <= 0.5;
+    const double z = small ? ar * ar : 0.5 * (1.0 - ar);
+    const double x = small ? ar : sqrt_small64(z);
+    const float P = tail_poly(poly::AT, 6, (float)z);
+    const double a = __builtin_fma(x * z, (double)P, x);   // asin(x)
+    if (small) {
+        const double sa = r < 0.0 ? -a : a;                  // asin(r)
+        D = 0.5 * kPi - sa;
+        Dc = 0.5 * kPi + sa;
+    } else {
+        const double b = 2.0 * a;                            // acos(|r|)
+        D = r < 0.0 ? kPi - b : b;
+        Dc = r < 0.0 ? b : kPi - b;
+    }
+}
+
+__device__ __forceinline__ double sin_fast(double t) {
+    const double t2 = t * t;
+    const float S = tail_poly(poly::ST, 4, (float)t2);
+    return __builtin_fma(t * t2, (double)S, t);
+}
+
+__device__ __forceinline__ double cos_fast(double t) {
+    const double t2 = t * t;
+    const float C = tail_poly(poly::CT, 4, (float)t2);
+    return __builtin_fma(t2 * t2, (double)C, __builtin_fma(t2, -0.5, 1.0));
+}
+
+// atan2(y, x) in float32: reduce to t = min(|x|,|y|)/max(|x|,|y|) in [0, 1],
+// atan t = t + t^3 Q(t^2), then fold the octant; y = -0 counts as +0, so the
+// result lies in (-pi, pi].
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+    const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+    const float mn = __builtin_fminf(ax, ay), mx = __builtin_fmaxf(ax, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t2 = t * t;
+    float Q = poly::ATAN[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) Q = __builtin_fmaf(Q, t2, poly::ATAN[k]);
+    float a = __builtin_fmaf(t * t2, Q, t);
+    a = (ay > ax) ? 1.57079632679489662f - a : a;
+    a = (x < 0.0f) ? 3.14159265358979324f - a : a;
+    return (y < 0.0f) ? -a : a;
 }
 
 // ----------------------------------------------------- 3x3 cubic stage -----
@@ -105,13 +220,17 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
     const double det = d1 * (d2 * d3 - a23 * a23) - a12 * (a12 * d3 - a13 * a23) +
                        a13 * (a12 * a23 - a13 * d2);
     const double q = 27.0 * det;
-    c.triple = (p == 0.0);
-    const double sp = ::sqrt(p);
-    double r = c.triple ? 0.0 : q / (2.0 * p * sp);
+    // p == 0 is the paper's triple root; below 1e-280 (the matrix is scaled
+    // to max |A_ij| in [1/2, 1)) B is so small against m that A is isotropic
+    // to working precision, and 1/sqrt(p) would leave the normal range
+    c.triple = !(p >= 1e-280);
+    const double ip = rsqrt64(c.triple ? 1.0 : p);   // 1 / sqrt(p)
+    const double sp = c.triple ? 0.0 : p * ip;
+    double r = 0.5 * q * (ip * ip * ip);              // q / (2 sqrt(p)^3)
     r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
-    const double Delta = ::acos(r);
+    const double Delta = acos64(r);
     double st, ct;
-    ::sincos(Delta * (1.0 / 3.0), &st, &ct);
+    sincos_third(Delta * (1.0 / 3.0), st, ct);
     const double spc = sp * ct, sps = sp * st * kInvSqrt3;
     c.mu1 = (2.0 / 3.0) * spc;
     c.mu2 = -(spc + 3.0 * sps) * (1.0 / 3.0);
@@ -120,6 +239,41 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
     c.g13 = spc - sps;
     c.g32 = 2.0 * sps;
     if (c.g13 < 0.0) c.g13 = 0.0;
+    c.sp = sp;
+    return c;
+}
+
+// The cubic stage of the float32 path: the same quantities as cubic_stage,
+// with the float32-tail arccos / sin / cos.  The three gaps come from sines of
+// t = Delta/3 and of pi/3 - t = (pi - Delta)/3, so each is accurate to ~1e-8
+// relative even when two eigenvalues nearly coincide:
+//   lam3 - lam2 = (2/sqrt3) sqrt(p) sin t,  lam1 - lam3 = (2/sqrt3) sqrt(p) sin(pi/3 - t),
+//   lam1 - lam2 = their sum;  mu1 = (2/3) sqrt(p) cos t, mu2 = mu1 - g12, mu3 = mu1 - g13.
+__device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double a33, double a12,
+                                                  double a13, double a23) {
+    Cubic c;
+    center3(a11, a22, a33, c.m, c.d1, c.d2, c.d3);
+    const double d1 = c.d1, d2 = c.d2, d3 = c.d3;
+    const double off = a12 * a12 + a13 * a13 + a23 * a23;
+    const double x12 = a11 - a22, x13 = a11 - a33, x23 = a22 - a33;
+    const double p = 0.5 * (x12 * x12 + x13 * x13 + x23 * x23) + 3.0 * off;
+    const double det = d1 * (d2 * d3 - a23 * a23) - a12 * (a12 * d3 - a13 * a23) +
+                       a13 * (a12 * a23 - a13 * d2);
+    c.triple = !(p >= 1e-280);
+    const double ip = rsqrt64(c.triple ? 1.0 : p);
+    const double sp = c.triple ? 0.0 : p * ip;
+    double r = 13.5 * det * (ip * ip * ip);        // 27 det / (2 sqrt(p)^3)
+    r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
+    double D, Dc;
+    acos_pair_fast(r, D, Dc);
+    const double t = D * (1.0 / 3.0), tc = Dc * (1.0 / 3.0);
+    const double k = (2.0 * kInvSqrt3) * sp;
+    c.g32 = k * sin_fast(t);
+    c.g13 = k * sin_fast(tc);
+    c.g12 = c.g13 + c.g32;
+    c.mu1 = (2.0 / 3.0) * sp * cos_fast(t);
+    c.mu2 = c.mu1 - c.g12;
+    c.mu3 = c.mu1 - c.g13;
     c.sp = sp;
     return c;
 }
@@ -270,39 +424,36 @@ template <typename T> __device__ __forceinline__ void extract_angles(T D[9], T p
     phi[2] = M::atan2(p3s, p3c);
 }
 
-// ------------------------------------------ float64 a-posteriori check -----
-// With A and the eigenvalues in float64 and D as stored (type T, promoted),
-// D^T A D should be diag(lam).  Fails when an off-diagonal |B_jk| exceeds
-// tau_res ||A||_F (a residual bound: ||A d_k - lam_k d_k||^2 is the sum of the
-// squares of column k of B - Lambda), when |B_jk| / |lam_j - lam_k| exceeds
-// tau_vec (the first-order angle by which d_k leans towards d_j), or when a
-// diagonal entry misses its eigenvalue by more than tau_res ||A||_F.
-template <typename T>
-__device__ __forceinline__ bool check_fails(const Cubic &c, double a12, double a13, double a23,
-                                            const T Dt[9], double fro, double tau_res, double tau_vec) {
-    double d[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)Dt[i];
-    // B d_k with B = A - m I; off-diagonal entries of D^T B D equal those of
-    // D^T A D, the diagonal ones are compared with the deviations mu_k
-    double Ad[9];
+// ------------------------------------------------- a-posteriori check -----
+// With B = A - m I (its diagonal d1, d2, d3 and the off-diagonal entries), the
+// deviations mu_k = lam_k - m and the computed D, D^T B D should be diag(mu).
+// Fails when an off-diagonal |(D^T B D)_jk| exceeds lim = tau_res ||A||_F (a
+// residual bound: ||A d_k - lam_k d_k||^2 is the sum of the squares of column
+// k of D^T B D - diag(mu)), when a diagonal entry misses its mu_k by more than
+// lim, or (tau_vec > 0) when |(D^T B D)_jk| / |lam_j - lam_k|, the first-order
+// angle by which d_k leans towards d_j, exceeds tau_vec.  C is the arithmetic
+// type of the check; in float32 its rounding noise is about 1e-7 ||A||_F.
+template <typename C>
+__device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a23, const C d[9],
+                                            C mu1, C mu2, C mu3, C g12, C g13, C g32, C lim,
+                                            C tau_vec) {
+    C Bd[9];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double x = d[k], y = d[3 + k], z = d[6 + k];
-        Ad[k] = c.d1 * x + a12 * y + a13 * z;
-        Ad[3 + k] = a12 * x + c.d2 * y + a23 * z;
-        Ad[6 + k] = a13 * x + a23 * y + c.d3 * z;
+        const C x = d[k], y = d[3 + k], z = d[6 + k];
+        Bd[k] = d1 * x + a12 * y + a13 * z;
+        Bd[3 + k] = a12 * x + d2 * y + a23 * z;
+        Bd[6 + k] = a13 * x + a23 * y + d3 * z;
     }
-    auto dot = [&](int j, int k) { return d[j] * Ad[k] + d[3 + j] * Ad[3 + k] + d[6 + j] * Ad[6 + k]; };
-    const double B01 = dot(0, 1), B02 = dot(0, 2), B12 = dot(1, 2);
-    const double B00 = dot(0, 0), B11 = dot(1, 1), B22 = dot(2, 2);
-    const double lim = tau_res * fro;
-    bool bad = !(__builtin_fabs(B01) <= lim && __builtin_fabs(B02) <= lim && __builtin_fabs(B12) <= lim);
-    bad |= !(__builtin_fabs(B00 - c.mu1) <= lim && __builtin_fabs(B11 - c.mu2) <= lim &&
-             __builtin_fabs(B22 - c.mu3) <= lim);
-    if (tau_vec > 0.0) {
-        bad |= !(__builtin_fabs(B01) <= tau_vec * c.g12 && __builtin_fabs(B02) <= tau_vec * c.g13 &&
-                 __builtin_fabs(B12) <= tau_vec * c.g32);
+    auto dot = [&](int j, int k) { return d[j] * Bd[k] + d[3 + j] * Bd[3 + k] + d[6 + j] * Bd[6 + k]; };
+    const C B01 = dot(0, 1), B02 = dot(0, 2), B12 = dot(1, 2);
+    const C B00 = dot(0, 0), B11 = dot(1, 1), B22 = dot(2, 2);
+    using M = Mth<C>;
+    bool bad = !(M::fabs(B01) <= lim && M::fabs(B02) <= lim && M::fabs(B12) <= lim);
+    bad |= !(M::fabs(B00 - mu1) <= lim && M::fabs(B11 - mu2) <= lim && M::fabs(B22 - mu3) <= lim);
+    if (tau_vec > C(0)) {
+        bad |= !(M::fabs(B01) <= tau_vec * g12 && M::fabs(B02) <= tau_vec * g13 &&
+                 M::fabs(B12) <= tau_vec * g32);
     }
     return bad;
 }

@@ -14,18 +14,22 @@
 // HBM, and every output element is written exactly once.
 #pragma once
 
+#include <stddef.h>
+
 #include "ksym_device.hpp"
 
 namespace ksym {
 
 enum { PATH_FP32_FIXUP = 0, PATH_FP64_PLAIN = 1, PATH_FP64_FIXUP = 2 };
 
+// Output planes of the 3x3 forward, in this order: lam (3), D (9, row-major),
+// phi (3), gap (3).
+constexpr int NOUT3 = 18;
+constexpr int O_LAM = 0, O_D = 3, O_PHI = 12, O_GAP = 15;
+
 template <typename T> struct Eig3Ptrs {
     const T *in[6];
-    T *lam[3];
-    T *D[9];
-    T *phi[3];
-    T *gap[3];
+    T *out[NOUT3];   // any entry may be null
     uint8_t *flags;
 };
 
@@ -33,6 +37,7 @@ struct Eig3Params {
     int64_t n;
     double tau_gap, tau_res, tau_vec, tau_dbl;
     unsigned *counters;   // [0] refined, [1] non-finite; may be null
+    int32_t zero;         // always 0; see store_tile3
 };
 
 template <typename T> struct Eig3Args {
@@ -42,10 +47,7 @@ template <typename T> struct Eig3Args {
 };
 
 template <typename T> struct Out3 {
-    T lam[3];
-    T D[9];
-    T phi[3];
-    T gap[3];
+    T v[NOUT3];  // lam, D, phi, gap at O_LAM, O_D, O_PHI, O_GAP
     int flag;
     bool refine;
     double lc;   // isolated eigenvalue (scaled units) handed to the refinement
@@ -77,10 +79,10 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     if (cu.triple) {
         // §5, p = 0: A = lam I with lam = A11; D = I, angles 0.
 #pragma unroll
-        for (int i = 0; i < 9; ++i) o.D[i] = (i % 4 == 0) ? T(1) : T(0);
-        o.lam[0] = o.lam[1] = o.lam[2] = ain[0];
-        o.phi[0] = o.phi[1] = o.phi[2] = T(0);
-        o.gap[0] = o.gap[1] = o.gap[2] = T(0);
+        for (int i = 0; i < 9; ++i) o.v[O_D + i] = (i % 4 == 0) ? T(1) : T(0);
+        o.v[O_LAM] = o.v[O_LAM + 1] = o.v[O_LAM + 2] = (T)(cu.m * isc);
+        o.v[O_PHI] = o.v[O_PHI + 1] = o.v[O_PHI + 2] = T(0);
+        o.v[O_GAP] = o.v[O_GAP + 1] = o.v[O_GAP + 2] = T(0);
         o.flag = FLAG_TRIPLE;
     } else {
         const double split = fmin(cu.g13, cu.g32);
@@ -99,20 +101,20 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             double L[3];
             if (ls > lm) {   // (ls, lm, lm): columns (3, 1, 2), even permutation
                 for (int r = 0; r < 3; ++r) {
-                    o.D[3 * r] = Di[3 * r + 2]; o.D[3 * r + 1] = Di[3 * r]; o.D[3 * r + 2] = Di[3 * r + 1];
+                    o.v[O_D + 3 * r] = Di[3 * r + 2]; o.v[O_D + 3 * r + 1] = Di[3 * r]; o.v[O_D + 3 * r + 2] = Di[3 * r + 1];
                 }
                 L[0] = ls; L[1] = lm; L[2] = lm;
             } else {         // (lm, ls, lm): columns (1, 3, -2), odd permutation + sign
                 for (int r = 0; r < 3; ++r) {
-                    o.D[3 * r] = Di[3 * r]; o.D[3 * r + 1] = Di[3 * r + 2]; o.D[3 * r + 2] = -Di[3 * r + 1];
+                    o.v[O_D + 3 * r] = Di[3 * r]; o.v[O_D + 3 * r + 1] = Di[3 * r + 2]; o.v[O_D + 3 * r + 2] = -Di[3 * r + 1];
                 }
                 L[0] = lm; L[1] = ls; L[2] = lm;
             }
-            extract_angles<T>(o.D, o.phi);
-            for (int k = 0; k < 3; ++k) o.lam[k] = (T)((cu.m + L[k]) * isc);
-            o.gap[0] = (T)((L[0] - L[1]) * isc);
-            o.gap[1] = (T)((L[0] - L[2]) * isc);
-            o.gap[2] = (T)((L[2] - L[1]) * isc);
+            extract_angles<T>(o.v + O_D, o.v + O_PHI);
+            for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)((cu.m + L[k]) * isc);
+            o.v[O_GAP] = (T)((L[0] - L[1]) * isc);
+            o.v[O_GAP + 1] = (T)((L[0] - L[2]) * isc);
+            o.v[O_GAP + 2] = (T)((L[2] - L[1]) * isc);
             o.flag = FLAG_DOUBLE;
         } else {
             // general branch (5.1)-(5.15): v, w with the eigenvalue
@@ -122,21 +124,26 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             const T v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
             const T w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G32, v, w);
-            build_D(R, o.D);
-            angles_of(R, o.phi);
-            o.lam[0] = (T)((cu.m + cu.mu1) * isc);
-            o.lam[1] = (T)((cu.m + cu.mu2) * isc);
-            o.lam[2] = (T)((cu.m + cu.mu3) * isc);
-            o.gap[0] = (T)(cu.g12 * isc);
-            o.gap[1] = (T)(cu.g13 * isc);
-            o.gap[2] = (T)(cu.g32 * isc);
+            build_D(R, o.v + O_D);
+            angles_of(R, o.v + O_PHI);
+            o.v[O_LAM] = (T)((cu.m + cu.mu1) * isc);
+            o.v[O_LAM + 1] = (T)((cu.m + cu.mu2) * isc);
+            o.v[O_LAM + 2] = (T)((cu.m + cu.mu3) * isc);
+            o.v[O_GAP] = (T)(cu.g12 * isc);
+            o.v[O_GAP + 1] = (T)(cu.g13 * isc);
+            o.v[O_GAP + 2] = (T)(cu.g32 * isc);
             o.flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
             if (PATH != PATH_FP64_PLAIN) {
                 const double fro = ::sqrt(a11 * a11 + a22 * a22 + a33 * a33 +
                                           2.0 * (a12 * a12 + a13 * a13 + a23 * a23));
                 const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
                 bool bad = dbl || (split < prm.tau_gap * lmax);
-                bad = bad || check_fails<T>(cu, a12, a13, a23, o.D, fro, prm.tau_res, prm.tau_vec);
+                double dd[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) dd[i] = (double)o.v[O_D + i];
+                bad = bad || check_fails<double>(cu.d1, cu.d2, cu.d3, a12, a13, a23, dd, cu.mu1, cu.mu2,
+                                                 cu.mu3, cu.g12, cu.g13, cu.g32, prm.tau_res * fro,
+                                                 prm.tau_vec);
                 o.refine = bad;
                 o.lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
             }
@@ -145,29 +152,164 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     if (!fin) {
         const T nan = T(__builtin_nan(""));
 #pragma unroll
-        for (int i = 0; i < 9; ++i) o.D[i] = nan;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { o.lam[k] = nan; o.phi[k] = nan; o.gap[k] = nan; }
+        for (int i = 0; i < NOUT3; ++i) o.v[i] = nan;
         o.flag = FLAG_NONFINITE;
         o.refine = false;
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void store3(const Eig3Ptrs<T> &p, int64_t i, const Out3<T> &o) {
+// Per-workgroup staging of a tile's outputs in LDS: the main pass and the
+// refinement both write here, then the tile leaves with one coalesced store per
+// plane, so every output element is written to HBM exactly once.
+template <typename T, int TILE> struct Stage3 {
+    T v[NOUT3][TILE];
+    uint8_t flag[TILE];
+};
+
+template <typename T, int TILE>
+__device__ __forceinline__ void stage_put(Stage3<T, TILE> *st, int slot, const Out3<T> &o) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (p.lam[k]) p.lam[k][i] = o.lam[k];
+    for (int k = 0; k < NOUT3; ++k) st->v[k][slot] = o.v[k];
+    st->flag[slot] = (uint8_t)o.flag;
+}
+
+// The float32 path for one matrix, written for a small register footprint:
+// everything after the float64 cubic stage is float32, results go to the LDS
+// staging slot as soon as they exist (eigenvalues and gaps first, then the
+// angles, then D after the check), and the a-posteriori check runs in float32
+// on B = A - m I.  Sets `refine` (and the isolated eigenvalue lc for the
+// refinement, a float64 deviation in scaled units) and returns the flag.
+template <int TILE>
+__device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &prm,
+                                        Stage3<float, TILE> *st, int slot, bool &refine, double &lc) {
+    const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
+                     finite(ain[4]) && finite(ain[5]);
+    float amax = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[0]), __builtin_fabsf(ain[1])),
+                                 __builtin_fabsf(ain[2]));
+    amax = __builtin_fmaxf(amax, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[3]),
+                                                                 __builtin_fabsf(ain[4])),
+                                                 __builtin_fabsf(ain[5])));
+    const int ex = fin ? scale_exponent((double)amax) : 0;
+    const double sc = pow2(-ex), isc = pow2(ex);
+    double a[6];
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-        if (p.D[k]) p.D[k][i] = o.D[k];
+    for (int c = 0; c < 6; ++c) a[c] = fin ? (double)ain[c] * sc : 0.0;
+    const Cubic cu = cubic_stage_fast(a[0], a[1], a[2], a[3], a[4], a[5]);
+    refine = false;
+    lc = 0.0;
+    int flag;
+    if (cu.triple || !fin) {
+        // §5, p = 0: A = lam I, D = I, angles 0 (non-finite input: all NaN)
+        const float nan = __builtin_nanf("");
+        const float lam = fin ? (float)(cu.m * isc) : nan;
+        st->v[O_LAM][slot] = lam; st->v[O_LAM + 1][slot] = lam; st->v[O_LAM + 2][slot] = lam;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (p.phi[k]) p.phi[k][i] = o.phi[k];
+        for (int i = 0; i < 9; ++i) st->v[O_D + i][slot] = fin ? ((i % 4 == 0) ? 1.0f : 0.0f) : nan;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (p.gap[k]) p.gap[k][i] = o.gap[k];
-    if (p.flags) p.flags[i] = (uint8_t)o.flag;
+        for (int k = 0; k < 3; ++k) {
+            st->v[O_PHI + k][slot] = fin ? 0.0f : nan;
+            st->v[O_GAP + k][slot] = fin ? 0.0f : nan;
+        }
+        flag = fin ? FLAG_TRIPLE : FLAG_NONFINITE;
+        st->flag[slot] = (uint8_t)flag;
+        return flag;
+    }
+    st->v[O_LAM][slot] = (float)((cu.m + cu.mu1) * isc);
+    st->v[O_LAM + 1][slot] = (float)((cu.m + cu.mu2) * isc);
+    st->v[O_LAM + 2][slot] = (float)((cu.m + cu.mu3) * isc);
+    st->v[O_GAP][slot] = (float)(cu.g12 * isc);
+    st->v[O_GAP + 1][slot] = (float)(cu.g13 * isc);
+    st->v[O_GAP + 2][slot] = (float)(cu.g32 * isc);
+    const double split = fmin(cu.g13, cu.g32);
+    const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
+    const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
+    bool bad = dbl || (split < prm.tau_gap * lmax);
+    lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
+    // float32 operands of the angle solve and the check (scaled units)
+    const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
+    const float A22 = (float)a[1], A33 = (float)a[2];
+    const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
+    const float e1 = (float)(cu.d1 - cu.mu1), e3 = (float)(cu.d1 - cu.mu3);
+    const float d1 = (float)cu.d1, d2 = (float)cu.d2, d3 = (float)cu.d3;
+    const float m1 = (float)cu.mu1, m2 = (float)cu.mu2, m3 = (float)cu.mu3;
+    const float fro = __builtin_sqrtf((float)(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] +
+                                              2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5])));
+    // general branch (5.1)-(5.15)
+    const float v = clamp01(Mth<float>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
+    const float w = (v == 0.0f) ? 1.0f : clamp01(Mth<float>::div(e3 + G32 * v, G12 * v));
+    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G32, v, w);
+    float phi[3];
+    angles_of(R, phi);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st->v[O_PHI + k][slot] = phi[k];
+    float D[9];
+    build_D(R, D);
+    bad = bad || check_fails<float>(d1, d2, d3, A12, A13, A23, D, m1, m2, m3, G12, G13, G32,
+                                    (float)prm.tau_res * fro, (float)prm.tau_vec);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st->v[O_D + i][slot] = D[i];
+    flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
+    st->flag[slot] = (uint8_t)flag;
+    refine = bad;
+    return flag;
+}
+
+// Output plane pointers read from the kernel-argument segment with a
+// plane-dependent offset: the store loop fetches each pointer with one scalar
+// load when it needs it instead of holding all of them in registers.
+template <typename T> struct KernargPlanes {
+    uint32_t out_off, flags_off;   // byte offsets inside the argument segment
+    __device__ __forceinline__ T *out(int k) const {
+        typedef __attribute__((address_space(4))) const char *kptr;
+        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+        return *(T *const __attribute__((address_space(4))) *)(ka + out_off + 8 * k);
+    }
+    __device__ __forceinline__ uint8_t *flags(int salt = 0) const {
+        typedef __attribute__((address_space(4))) const char *kptr;
+        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+        return *(uint8_t *const __attribute__((address_space(4))) *)(ka + flags_off + 8 * salt);
+    }
+};
+
+// Output plane pointers of a group descriptor in device memory.
+template <typename T> struct TablePlanes {
+    const Eig3Ptrs<T> *p;
+    __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
+    __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
+};
+
+// Store a staged tile.  The plane pointers are fetched here, for this tile: the
+// plane index is offset by salt = tile * zero, which is 0 at run time but not
+// known to the compiler, so the fully unrolled loop issues all pointer loads
+// together without hoisting them out of the tile loop (where they would pin
+// 38 scalar registers for the whole kernel).
+template <typename T, int BS, int MPL, int TILE, typename Planes>
+__device__ __forceinline__ void store_tile3(const Planes &pl, const Stage3<T, TILE> *st, int64_t n,
+                                            int64_t base, int salt) {
+    const int tid = threadIdx.x;
+    T *dst[NOUT3];
+#pragma unroll
+    for (int k = 0; k < NOUT3; ++k) dst[k] = pl.out(k + salt);
+    uint8_t *fl = pl.flags(salt);
+#pragma unroll
+    for (int m = 0; m < MPL; ++m) {
+        const int64_t i = base + m * BS + tid;
+        T val[NOUT3];   // all LDS reads first, then the stores
+#pragma unroll
+        for (int k = 0; k < NOUT3; ++k) val[k] = st->v[k][m * BS + tid];
+        if (i < n) {
+#pragma unroll
+            for (int k = 0; k < NOUT3; ++k)
+                if (dst[k]) dst[k][i] = val[k];
+        }
+    }
+    if (fl) {
+#pragma unroll
+        for (int m = 0; m < MPL; ++m) {
+            const int64_t i = base + m * BS + tid;
+            if (i < n) fl[i] = st->flag[m * BS + tid];
+        }
+    }
 }
 
 // The refinement of one queued matrix (original entries ain, isolated
@@ -185,20 +327,23 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
     const Refined rf = refine3(d1, d2, d3, (double)ain[3] * sc, (double)ain[4] * sc,
                                (double)ain[5] * sc, lc);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o.D[i] = (T)rf.D[i];
-    extract_angles<T>(o.D, o.phi);
+    for (int i = 0; i < 9; ++i) o.v[O_D + i] = (T)rf.D[i];
+    extract_angles<T>(o.v + O_D, o.v + O_PHI);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) o.lam[k] = (T)((m + rf.lam[k]) * isc);
-    o.gap[0] = (T)(fmax(rf.lam[0] - rf.lam[1], 0.0) * isc);
-    o.gap[1] = (T)(fmax(rf.lam[0] - rf.lam[2], 0.0) * isc);
-    o.gap[2] = (T)(fmax(rf.lam[2] - rf.lam[1], 0.0) * isc);
+    for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)((m + rf.lam[k]) * isc);
+    o.v[O_GAP] = (T)(fmax(rf.lam[0] - rf.lam[1], 0.0) * isc);
+    o.v[O_GAP + 1] = (T)(fmax(rf.lam[0] - rf.lam[2], 0.0) * isc);
+    o.v[O_GAP + 2] = (T)(fmax(rf.lam[2] - rf.lam[1], 0.0) * isc);
     o.flag = flag | FLAG_FIXUP;
 }
 
-// On-chip queue for one workgroup.
+// On-chip refinement queue of one workgroup.  Entries accumulate over tiles;
+// the queue is drained when it holds at least one entry per lane, so the
+// float64 refinement always runs on full wavefronts.
 template <typename T, int CAP> struct Queue {
     int n;
-    int off[CAP];       // in-tile offset | flag << 24
+    int64_t idx[CAP];   // matrix index within its group
+    int grp[CAP];       // group (mixed batches; 0 otherwise) | flag << 24
     T a[6][CAP];
     double lc[CAP];
 };
@@ -207,94 +352,206 @@ __device__ __forceinline__ unsigned lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// Process one tile of BS*MPL 3x3 matrices starting at `base`.  Block-uniform
-// control flow; contains workgroup barriers when PATH != PLAIN or AOS.
-template <typename T, int PATH, int BS, int MPL, bool AOS, int CAP>
-__device__ __forceinline__ void tile_eig3(const Eig3Ptrs<T> &p, const Eig3Params &prm, const T *aos,
-                                          int64_t n, int64_t base, Queue<T, CAP> *q, T *stage,
-                                          unsigned &refined, unsigned &nonfinite) {
-    constexpr int TILE = BS * MPL;
+// Inputs of one tile held in registers.  SoA: each lane's MPL matrices.
+// AoS: the lane's share of the tile's contiguous records as 16-byte vectors,
+// transposed through LDS when the tile is processed.
+template <typename T, int BS, int MPL, bool AOS> struct TileIn {
+    static constexpr int VEC = 16 / sizeof(T);
+    static constexpr int NV = BS * MPL * 6 / VEC;          // 16-byte vectors per tile
+    static constexpr int NVL = (NV + BS - 1) / BS;         // per lane
+    T a[AOS ? 1 : MPL][6];
+    T v[AOS ? NVL : 1][AOS ? VEC : 1];
+};
+
+template <typename T, int BS, int MPL, bool AOS>
+__device__ __forceinline__ void load_tile3(TileIn<T, BS, MPL, AOS> &in, const T *const *planes,
+                                           const T *aos, int64_t n, int64_t base) {
     const int tid = threadIdx.x;
-    T A[MPL][6];
     if constexpr (AOS) {
-        // stage the tile's records (TILE x 6 contiguous elements) with 16-byte
-        // loads, then each lane picks its own records out of LDS
-        constexpr int VEC = 16 / sizeof(T);
-        constexpr int NV = TILE * 6 / VEC;
+        using TI = TileIn<T, BS, MPL, AOS>;
+        constexpr int VEC = TI::VEC;
         const int64_t lim = (n - base) * 6;   // valid elements in this tile
         const T *src = aos + base * 6;
-        for (int j = tid; j < NV; j += BS) {
+#pragma unroll
+        for (int u = 0; u < TI::NVL; ++u) {
+            const int j = u * BS + tid;
             const int64_t e0 = (int64_t)j * VEC;
-            if (e0 + VEC <= lim) {
+            if (j < TI::NV && e0 + VEC <= lim) {
                 if constexpr (sizeof(T) == 4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(src + e0);
-                    *reinterpret_cast<float4 *>(stage + e0) = v;
+                    const float4 x = *reinterpret_cast<const float4 *>(src + e0);
+                    in.v[u][0] = x.x; in.v[u][1] = x.y; in.v[u][2] = x.z; in.v[u][3] = x.w;
                 } else {
-                    const double2 v = *reinterpret_cast<const double2 *>(src + e0);
-                    *reinterpret_cast<double2 *>(stage + e0) = v;
+                    const double2 x = *reinterpret_cast<const double2 *>(src + e0);
+                    in.v[u][0] = x.x; in.v[u][1] = x.y;
                 }
             } else {
-                for (int t = 0; t < VEC; ++t) stage[e0 + t] = (e0 + t < lim) ? src[e0 + t] : T(0);
+#pragma unroll
+                for (int t = 0; t < VEC; ++t)
+                    in.v[u][t] = (j < TI::NV && e0 + t < lim) ? src[e0 + t] : T(0);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < MPL; ++k)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) A[k][c] = stage[(k * BS + tid) * 6 + c];
-        __syncthreads();
     } else {
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int64_t i = base + k * BS + tid;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) A[k][c] = (i < n) ? p.in[c][i] : T(0);
+            for (int c = 0; c < 6; ++c) in.a[k][c] = (i < n) ? planes[c][i] : T(0);
         }
+    }
+}
+
+// Write one matrix's outputs (a refined result) to the output planes.
+template <typename T, typename Planes>
+__device__ __forceinline__ void write_out3(const Planes &pl, int64_t i, const Out3<T> &o) {
+#pragma nounroll
+    for (int k = 0; k < NOUT3; ++k) {
+        T *dst = pl.out(k);
+        if (dst) dst[i] = o.v[k];
+    }
+    uint8_t *fl = pl.flags();
+    if (fl) fl[i] = (uint8_t)o.flag;
+}
+
+// Drain the first `cnt` queue entries: entry j goes to lane j (mod BS), each
+// result is written straight to its output planes.  The tile store that wrote
+// the provisional values happened before the workgroup barrier (with its
+// release fence) that precedes every call.
+template <typename T, int BS, int CAP, typename PlanesOf>
+__device__ __forceinline__ void drain_queue(Queue<T, CAP> *q, int cnt, const PlanesOf &planes_of) {
+    for (int j = threadIdx.x; j < cnt; j += BS) {
+        T a[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] = q->a[c][j];
+        const int g = q->grp[j];
+        Out3<T> o;
+        refine_one<T>(a, q->lc[j], g >> 24, o);
+        write_out3(planes_of(g & 0xffffff), q->idx[j], o);
+    }
+}
+
+// Workgroup-shared memory of the 3x3 kernels.
+template <typename T, int BS, int TILE, bool QUEUE, bool AOS> struct Smem3 {
+    Queue<T, QUEUE ? BS + TILE : 1> q;
+    Stage3<T, TILE> st;
+    __align__(16) T rec[AOS ? TILE * 6 : 1];
+};
+
+// Process one tile of BS*MPL 3x3 matrices starting at `base` from inputs
+// already in registers, store it, and drain the refinement queue when it holds
+// at least BS entries.  Block-uniform control flow.  The staging slots are
+// written and read only by their own lane, so the tile store needs no barrier;
+// two barriers per tile make the queue length consistent, two more surround a
+// drain.  The AoS record buffer is last read before the first barrier (an
+// extra barrier closes the tile when there is no queue).
+template <typename T, int PATH, int BS, int MPL, bool AOS, typename Planes, typename PlanesOf>
+__device__ __forceinline__ void tile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
+                                          const Eig3Params &prm, TileIn<T, BS, MPL, AOS> &in,
+                                          int64_t n, int64_t base,
+                                          Smem3<T, BS, BS * MPL, PATH != PATH_FP64_PLAIN, AOS> *sm,
+                                          unsigned &refined, unsigned &nonfinite) {
+    constexpr int TILE = BS * MPL;
+    const int tid = threadIdx.x;
+    if constexpr (AOS) {
+        using TI = TileIn<T, BS, MPL, AOS>;
+#pragma unroll
+        for (int u = 0; u < TI::NVL; ++u) {
+            const int j = u * BS + tid;
+            if (j < TI::NV) {
+#pragma unroll
+                for (int t = 0; t < TI::VEC; ++t) sm->rec[j * TI::VEC + t] = in.v[u][t];
+            }
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
-        const int64_t i = base + k * BS + tid;
-        const bool valid = i < n;
-        Out3<T> o;
-        eig3_one<T, PATH>(A[k], prm, o);
-        if (o.flag == FLAG_NONFINITE) nonfinite += valid ? 1u : 0u;
-        const bool r = valid && o.refine;
-        if (valid && !r) store3(p, i, o);
+        const int slot = k * BS + tid;
+        const bool valid = base + slot < n;
+        T A[6];
+        if constexpr (AOS) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A[c] = sm->rec[slot * 6 + c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A[c] = in.a[k][c];
+        }
+        bool refine;
+        double lc;
+        int flag;
+        if constexpr (PATH == PATH_FP32_FIXUP) {
+            flag = eig3_f32<TILE>(A, prm, &sm->st, slot, refine, lc);
+        } else {
+            Out3<T> o;
+            eig3_one<T, PATH>(A, prm, o);
+            stage_put(&sm->st, slot, o);
+            refine = o.refine;
+            lc = o.lc;
+            flag = o.flag;
+        }
+        if (flag == FLAG_NONFINITE) nonfinite += valid ? 1u : 0u;
         if constexpr (PATH != PATH_FP64_PLAIN) {
+            const bool r = valid && refine;
             const uint64_t mask = __ballot(r);
             if (mask) {
                 int off = 0;
-                if ((tid & 63) == 0) off = atomicAdd(&q->n, (int)__popcll(mask));
+                if ((tid & 63) == 0) off = atomicAdd(&sm->q.n, (int)__popcll(mask));
                 off = __builtin_amdgcn_readfirstlane(off);
                 if (r) {
                     const int pos = off + (int)lane_rank(mask);
-                    q->off[pos] = (k * BS + tid) | (o.flag << 24);
+                    sm->q.idx[pos] = base + slot;
+                    sm->q.grp[pos] = grp | (flag << 24);
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) q->a[c][pos] = A[k][c];
-                    q->lc[pos] = o.lc;
+                    for (int c = 0; c < 6; ++c) sm->q.a[c][pos] = A[c];
+                    sm->q.lc[pos] = lc;
                 }
             }
         }
     }
+    store_tile3<T, BS, MPL, TILE>(pl, &sm->st, n, base, (int)(base * prm.zero));
     if constexpr (PATH != PATH_FP64_PLAIN) {
         __syncthreads();
-        const int cnt = q->n;
+        const int cnt = sm->q.n;
         __syncthreads();
-        if (cnt > 0) {
-            for (int j = tid; j < cnt; j += BS) {
-                const int packed = q->off[j];
+        if (cnt >= BS) {
+            // drain whole rounds only, then move the remainder to the front
+            const int nfull = cnt - cnt % BS;
+            drain_queue<T, BS>(&sm->q, nfull, planes_of);
+            refined += (tid == 0) ? (unsigned)nfull : 0u;
+            __syncthreads();
+            const int rest = cnt - nfull;   // < BS
+            if (tid < rest) {
+                const int j = nfull + tid;
+                const int64_t ix = sm->q.idx[j];
+                const int gf = sm->q.grp[j];
+                const double l = sm->q.lc[j];
                 T a[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) a[c] = q->a[c][j];
-                Out3<T> o;
-                refine_one<T>(a, q->lc[j], packed >> 24, o);
-                store3(p, base + (packed & 0xffffff), o);
+                for (int c = 0; c < 6; ++c) a[c] = sm->q.a[c][j];
+                sm->q.idx[tid] = ix;
+                sm->q.grp[tid] = gf;
+                sm->q.lc[tid] = l;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sm->q.a[c][tid] = a[c];
             }
-            if (tid == 0) {
-                q->n = 0;
-                refined += (unsigned)cnt;
-            }
+            if (tid == 0) sm->q.n = rest;
             __syncthreads();
+        }
+    } else if constexpr (AOS) {
+        __syncthreads();
+    }
+}
+
+// Drain what is left in the queue at the end of a workgroup's work.
+template <typename T, int PATH, int BS, int TILE, bool AOS, typename PlanesOf>
+__device__ __forceinline__ void final_drain(const PlanesOf &planes_of,
+                                            Smem3<T, BS, TILE, PATH != PATH_FP64_PLAIN, AOS> *sm,
+                                            unsigned &refined) {
+    if constexpr (PATH != PATH_FP64_PLAIN) {
+        __syncthreads();
+        const int cnt = sm->q.n;
+        if (cnt > 0) {
+            drain_queue<T, BS>(&sm->q, cnt, planes_of);
+            refined += (threadIdx.x == 0) ? (unsigned)cnt : 0u;
         }
     }
 }
@@ -302,26 +559,32 @@ __device__ __forceinline__ void tile_eig3(const Eig3Ptrs<T> &p, const Eig3Params
 template <typename T, int PATH, int BS, int MPL, bool AOS>
 __global__ __launch_bounds__(BS) void k_eig3(Eig3Args<T> args) {
     constexpr int TILE = BS * MPL;
-    constexpr int CAP = (PATH == PATH_FP64_PLAIN) ? 1 : TILE;
-    __shared__ Queue<T, CAP> q;
-    __shared__ __align__(16) T stage[AOS ? TILE * 6 : 1];
-    if (threadIdx.x == 0) q.n = 0;
+    __shared__ Smem3<T, BS, TILE, PATH != PATH_FP64_PLAIN, AOS> sm;
+    if (threadIdx.x == 0) sm.q.n = 0;
     __syncthreads();
     const int64_t n = args.prm.n;
     const int64_t ntiles = (n + TILE - 1) / TILE;
+    KernargPlanes<T> pl;
+    pl.out_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, out));
+    pl.flags_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, flags));
+    auto planes_of = [&](int) { return pl; };
     unsigned refined = 0, nonfinite = 0;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        tile_eig3<T, PATH, BS, MPL, AOS, CAP>(args.p, args.prm, args.aos, n, t * TILE, &q, stage,
-                                              refined, nonfinite);
+    TileIn<T, BS, MPL, AOS> cur, nxt;
+    int64_t t = blockIdx.x;
+    if (t < ntiles) load_tile3<T, BS, MPL, AOS>(cur, args.p.in, args.aos, n, t * TILE);
+    for (; t < ntiles; t += gridDim.x) {
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntiles) load_tile3<T, BS, MPL, AOS>(nxt, args.p.in, args.aos, n, tn * TILE);
+        tile_eig3<T, PATH, BS, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * TILE, &sm, refined,
+                                         nonfinite);
+        cur = nxt;
+    }
+    final_drain<T, PATH, BS, TILE, AOS>(planes_of, &sm, refined);
     if (args.prm.counters) {
         if (threadIdx.x == 0 && refined) atomicAdd(&args.prm.counters[0], refined);
-        const uint64_t m = __ballot(nonfinite != 0);
-        if (m) {
-            // sum per wave with a shuffle-free scalar loop over the few lanes
-            unsigned s = nonfinite;
-            for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-            if ((threadIdx.x & 63) == 0) atomicAdd(&args.prm.counters[1], s);
-        }
+        unsigned s = nonfinite;
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        if ((threadIdx.x & 63) == 0 && s) atomicAdd(&args.prm.counters[1], s);
     }
 }
 
@@ -432,7 +695,7 @@ template <typename T> struct GroupDesc {
     int64_t n;
     int32_t kind;
     int32_t pad;
-    Eig3Ptrs<T> p3;   // for kind 2: in[0..2], lam[0..1], D[0..3], phi[0], flags
+    Eig3Ptrs<T> p3;   // kind 2 uses in[0..2] and out[O_LAM..+1], out[O_D..+3], out[O_PHI], flags
 };
 
 template <typename T> struct MixedArgs {
@@ -446,9 +709,11 @@ template <typename T> struct MixedArgs {
 template <typename T, int BS, int MPL>
 __global__ __launch_bounds__(BS) void k_mixed(MixedArgs<T> a) {
     constexpr int TILE = BS * MPL;
-    __shared__ Queue<T, TILE> q;
-    if (threadIdx.x == 0) q.n = 0;
+    constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
+    __shared__ Smem3<T, BS, TILE, true, false> sm;
+    if (threadIdx.x == 0) sm.q.n = 0;
     __syncthreads();
+    auto planes_of = [&](int g) { return TablePlanes<T>{&a.groups[g].p3}; };
     unsigned refined = 0, nonfinite = 0;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         // binary search: last g with tile_begin[g] <= t (block-uniform)
@@ -460,19 +725,21 @@ __global__ __launch_bounds__(BS) void k_mixed(MixedArgs<T> a) {
         const GroupDesc<T> &g = a.groups[lo];
         const int64_t base = (t - a.tile_begin[lo]) * TILE;
         if (g.kind == 3) {
-            constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
-            tile_eig3<T, PATH, BS, MPL, false, TILE>(g.p3, a.prm, nullptr, g.n, base, &q, nullptr,
-                                                     refined, nonfinite);
+            TileIn<T, BS, MPL, false> in;
+            load_tile3<T, BS, MPL, false>(in, g.p3.in, nullptr, g.n, base);
+            tile_eig3<T, PATH, BS, MPL, false>(planes_of(lo), planes_of, lo, a.prm, in, g.n, base, &sm,
+                                               refined, nonfinite);
         } else {
             Eig2Ptrs<T> p2;
             for (int c = 0; c < 3; ++c) p2.in[c] = g.p3.in[c];
-            p2.lam[0] = g.p3.lam[0]; p2.lam[1] = g.p3.lam[1];
-            for (int c = 0; c < 4; ++c) p2.D[c] = g.p3.D[c];
-            p2.phi = g.p3.phi[0];
+            p2.lam[0] = g.p3.out[O_LAM]; p2.lam[1] = g.p3.out[O_LAM + 1];
+            for (int c = 0; c < 4; ++c) p2.D[c] = g.p3.out[O_D + c];
+            p2.phi = g.p3.out[O_PHI];
             p2.flags = g.p3.flags;
             tile_eig2<T, BS, MPL>(p2, g.n, base);
         }
     }
+    final_drain<T, PATH, BS, TILE, false>(planes_of, &sm, refined);
     if (a.prm.counters) {
         if (threadIdx.x == 0 && refined) atomicAdd(&a.prm.counters[0], refined);
         unsigned s = nonfinite;
