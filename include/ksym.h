@@ -102,8 +102,11 @@ typedef enum {
 /*
  * Launch and threshold options.  Fill with ksym_opts_default() and change
  * fields; a NULL ksym_opts* means the defaults.
- *   block          threads per workgroup: 64, 128, 256, 512 or 1024.
- *   mats_per_lane  matrices each lane handles per tile: 1, 2 or 4.
+ *   block          threads per workgroup: 64, 128, 256, 512 or 1024 (each
+ *                  kernel is compiled for a subset; others give
+ *                  KSYM_E_UNSUPPORTED).
+ *   mats_per_lane  matrices each lane handles per tile: 1, 2 or 4 (3x3
+ *                  kernels: 1 or 2).
  *   grid_mult      workgroups per compute unit of the grid-stride launch
  *                  (the grid is min(tiles, grid_mult * CUs)); 1..64.
  *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
@@ -113,10 +116,19 @@ typedef enum {
  *   tau_vec        refinement if some |d_j^T A d_k| / |lam_k - lam_j| exceeds
  *                  tau_vec (first-order angle error of the eigenvectors;
  *                  0 = off).
+ *   drain_tiles    refinement queue age limit: each wavefront refines its
+ *                  queued matrices once 64 are waiting or once the oldest has
+ *                  waited this many of the wave's tiles, whichever comes
+ *                  first (0 = only full waves).  Refined outputs overwrite
+ *                  provisional ones; a short wait keeps those lines in cache.
  *   tau_dbl        relative split (min distance of the middle eigenvalue to
  *                  the others, divided by sqrt(p)) below which the computed
- *                  eigenvalues are taken as a double root.
- * Negative thresholds select the dtype's default.
+ *                  eigenvalues are taken as a double root: the plain path
+ *                  takes the paper's double-root branch, the checked paths
+ *                  route the matrix to the refinement.  Default 1e-6 for
+ *                  F64; 1e-9 for F32, whose angle solve takes its squared
+ *                  cosines from float64 quotients and is checked anyway.
+ * Negative thresholds (and drain_tiles < 0) select the dtype's default.
  */
 typedef struct {
     int32_t path;
@@ -127,6 +139,8 @@ typedef struct {
     double  tau_res;
     double  tau_vec;
     double  tau_dbl;
+    int32_t drain_tiles;
+    int32_t reserved;   /* set to 0 */
 } ksym_opts;
 
 /* Library version (KSYM_VERSION of the build). */

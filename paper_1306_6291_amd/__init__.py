@@ -49,7 +49,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("mats_per_lane", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
                 ("tau_gap", ctypes.c_double), ("tau_res", ctypes.c_double),
-                ("tau_vec", ctypes.c_double), ("tau_dbl", ctypes.c_double)]
+                ("tau_vec", ctypes.c_double), ("tau_dbl", ctypes.c_double),
+                ("drain_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     @classmethod
     def defaults(cls, dtype=F32, **kw):

@@ -77,12 +77,14 @@ ksym_status resolve_opts(ksym_dtype dt, const ksym_opts *in, ksym_opts *out) {
     if (o.tau_res < 0) o.tau_res = out->tau_res;
     if (o.tau_vec < 0) o.tau_vec = out->tau_vec;
     if (o.tau_dbl < 0) o.tau_dbl = out->tau_dbl;
+    if (o.drain_tiles < 0) o.drain_tiles = out->drain_tiles;
     if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
         return fail(KSYM_E_ARG, "block must be 64, 128, 256, 512 or 1024 (got %d)", o.block);
     if (o.mats_per_lane != 1 && o.mats_per_lane != 2 && o.mats_per_lane != 4)
         return fail(KSYM_E_ARG, "mats_per_lane must be 1, 2 or 4 (got %d)", o.mats_per_lane);
     if (o.grid_mult < 1 || o.grid_mult > 64)
         return fail(KSYM_E_ARG, "grid_mult must be in 1..64 (got %d)", o.grid_mult);
+    if (o.drain_tiles > (1 << 20)) return fail(KSYM_E_ARG, "drain_tiles must be in 0..2^20");
     if (!(o.tau_res > 0) || !(o.tau_dbl >= 0) || !(o.tau_gap >= 0) || !(o.tau_vec >= 0))
         return fail(KSYM_E_ARG, "thresholds must be finite and non-negative (tau_res > 0)");
     *out = o;
@@ -112,13 +114,10 @@ template <typename T, int PATH, bool AOS> Eig3K<T, PATH, AOS> pick_eig3(int bs, 
 template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXUP, false>(int bs, int mpl) {
     KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 2)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 4)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 2)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 4)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 2)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 4)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 2)
     return nullptr;
@@ -126,7 +125,6 @@ template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXU
 template <> Eig3K<float, PATH_FP32_FIXUP, true> pick_eig3<float, PATH_FP32_FIXUP, true>(int bs, int mpl) {
     KSYM_E3(float, PATH_FP32_FIXUP, true, 64, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 128, 1)
-    KSYM_E3(float, PATH_FP32_FIXUP, true, 128, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 512, 1)
@@ -156,7 +154,7 @@ template <> Eig3K<double, PATH_FP64_FIXUP, true> pick_eig3<double, PATH_FP64_FIX
 }
 #undef KSYM_E3
 
-template <typename T> using Eig2K = void (*)(Eig2Ptrs<T>, int64_t);
+template <typename T> using Eig2K = void (*)(Eig2Ptrs<T>, uint32_t);
 template <typename T> Eig2K<T> pick_eig2(int bs, int mpl) {
 #define KSYM_E2(B, M) \
     if (bs == B && mpl == M) return &k_eig2<T, B, M>;
@@ -166,7 +164,7 @@ template <typename T> Eig2K<T> pick_eig2(int bs, int mpl) {
     return nullptr;
 }
 
-template <typename T> using BwdK = void (*)(BwdPtrs<T>, int64_t, double);
+template <typename T> using BwdK = void (*)(BwdPtrs<T>, uint32_t, double);
 template <typename T> BwdK<T> pick_bwd(int bs, int mpl) {
 #define KSYM_B(B, M) \
     if (bs == B && mpl == M) return &k_eig3_bwd<T, B, M>;
@@ -179,7 +177,7 @@ template <typename T> using MixK = void (*)(MixedArgs<T>);
 template <typename T> MixK<T> pick_mixed(int bs, int mpl) {
 #define KSYM_M(B, M) \
     if (bs == B && mpl == M) return &k_mixed<T, B, M>;
-    KSYM_M(128, 1) KSYM_M(256, 1) KSYM_M(256, 2) KSYM_M(512, 1)
+    KSYM_M(64, 1) KSYM_M(128, 1) KSYM_M(256, 1) KSYM_M(256, 2) KSYM_M(512, 1)
 #undef KSYM_M
     return nullptr;
 }
@@ -203,6 +201,7 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     a.prm.tau_res = o.tau_res;
     a.prm.tau_vec = o.tau_vec;
     a.prm.tau_dbl = o.tau_dbl;
+    a.prm.drain_tiles = o.drain_tiles;
     a.prm.counters = (unsigned *)ws;
     (void)ws_bytes;
     void (*k)(Eig3Args<T>) = nullptr;
@@ -215,11 +214,21 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     if (!k)
         return fail(KSYM_E_UNSUPPORTED, "no compiled 3x3 kernel for block %d, mats_per_lane %d%s",
                     o.block, o.mats_per_lane, AOS ? " (AoS)" : "");
-    int grid = 0;
-    ksym_status s = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
-    if (s != KSYM_OK) return s;
-    hipError_t e = launch(k, dim3(grid), dim3(o.block), stream, a);
-    if (e != hipSuccess) return hip_fail(e, "launch k_eig3");
+    // one launch per KSYM_CHUNK matrices, every pointer advanced by the chunk start
+    for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
+        const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+        Eig3Args<T> c = a;
+        c.prm.n = len;
+        for (int k = 0; k < 6; ++k) c.p.in[k] = a.p.in[k] ? a.p.in[k] + start : nullptr;
+        for (int k = 0; k < NOUT3; ++k) c.p.out[k] = a.p.out[k] ? a.p.out[k] + start : nullptr;
+        c.p.flags = a.p.flags ? a.p.flags + start : nullptr;
+        c.aos = a.aos ? a.aos + start * 6 : nullptr;
+        int grid = 0;
+        ksym_status s = grid_for(len, o.block * o.mats_per_lane, o.grid_mult, &grid);
+        if (s != KSYM_OK) return s;
+        hipError_t e = launch(k, dim3(grid), dim3(o.block), stream, c);
+        if (e != hipSuccess) return hip_fail(e, "launch k_eig3");
+    }
     return KSYM_OK;
 }
 
@@ -280,7 +289,9 @@ void ksym_opts_default(ksym_dtype dtype, ksym_opts *o) {
     o->mats_per_lane = 1;
     o->grid_mult = 16;
     o->tau_gap = 0.0;
-    o->tau_dbl = 1e-6;
+    o->tau_dbl = dtype == KSYM_F64 ? 1e-6 : 1e-9;
+    o->drain_tiles = 8;
+    o->reserved = 0;
     if (dtype == KSYM_F64) {
         o->tau_res = 1e-11;
         o->tau_vec = 0.0;
@@ -310,23 +321,26 @@ ksym_status ksym_eig2(ksym_dtype dtype, int64_t n, const void *const in[3], void
     for (int c = 0; c < 4; ++c)
         if (D && !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] misaligned", c);
     if (!aligned(phi, es)) return fail(KSYM_E_ARG, "phi misaligned");
-    int grid = 0;
     auto go = [&](auto tag) -> ksym_status {
         using T = decltype(tag);
-        Eig2Ptrs<T> p;
-        for (int c = 0; c < 3; ++c) p.in[c] = (const T *)in[c];
-        for (int c = 0; c < 2; ++c) p.lam[c] = lam ? (T *)lam[c] : nullptr;
-        for (int c = 0; c < 4; ++c) p.D[c] = D ? (T *)D[c] : nullptr;
-        p.phi = (T *)phi;
-        p.flags = flags;
         Eig2K<T> k = pick_eig2<T>(o.block, o.mats_per_lane);
         if (!k)
             return fail(KSYM_E_UNSUPPORTED, "no compiled 2x2 kernel for block %d, mats_per_lane %d",
                         o.block, o.mats_per_lane);
-        ksym_status st = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
-        if (st != KSYM_OK) return st;
-        hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, n);
-        if (e != hipSuccess) return hip_fail(e, "launch k_eig2");
+        for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
+            const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+            Eig2Ptrs<T> p;
+            for (int c = 0; c < 3; ++c) p.in[c] = (const T *)in[c] + start;
+            for (int c = 0; c < 2; ++c) p.lam[c] = lam ? (T *)lam[c] + start : nullptr;
+            for (int c = 0; c < 4; ++c) p.D[c] = D ? (T *)D[c] + start : nullptr;
+            p.phi = phi ? (T *)phi + start : nullptr;
+            p.flags = flags ? flags + start : nullptr;
+            int grid = 0;
+            ksym_status st = grid_for(len, o.block * o.mats_per_lane, o.grid_mult, &grid);
+            if (st != KSYM_OK) return st;
+            hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, (uint32_t)len);
+            if (e != hipSuccess) return hip_fail(e, "launch k_eig2");
+        }
         return KSYM_OK;
     };
     return dtype == KSYM_F32 ? go(float()) : go(double());
@@ -428,20 +442,24 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
     o.mats_per_lane = 1;
     auto go = [&](auto tag) -> ksym_status {
         using T = decltype(tag);
-        BwdPtrs<T> p;
-        for (int c = 0; c < 3; ++c) p.lam[c] = (const T *)lam[c];
-        for (int c = 0; c < 9; ++c) p.D[c] = (const T *)D[c];
-        for (int c = 0; c < 3; ++c) p.gap[c] = gap ? (const T *)gap[c] : nullptr;
-        for (int c = 0; c < 3; ++c) p.glam[c] = glam ? (const T *)glam[c] : nullptr;
-        for (int c = 0; c < 9; ++c) p.gD[c] = gD ? (const T *)gD[c] : nullptr;
-        for (int c = 0; c < 6; ++c) p.gA[c] = (T *)gA[c];
         BwdK<T> k = pick_bwd<T>(o.block, o.mats_per_lane);
         if (!k) return fail(KSYM_E_UNSUPPORTED, "no compiled backward kernel");
-        int grid = 0;
-        ksym_status st = grid_for(n, o.block * o.mats_per_lane, o.grid_mult, &grid);
-        if (st != KSYM_OK) return st;
-        hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, n, eps_rel);
-        if (e != hipSuccess) return hip_fail(e, "launch k_eig3_bwd");
+        for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
+            const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+            BwdPtrs<T> p;
+            for (int c = 0; c < 3; ++c) p.lam[c] = (const T *)lam[c] + start;
+            for (int c = 0; c < 9; ++c) p.D[c] = (const T *)D[c] + start;
+            for (int c = 0; c < 3; ++c) p.gap[c] = gap ? (const T *)gap[c] + start : nullptr;
+            for (int c = 0; c < 3; ++c) p.glam[c] = glam ? (const T *)glam[c] + start : nullptr;
+            for (int c = 0; c < 9; ++c) p.gD[c] = gD ? (const T *)gD[c] + start : nullptr;
+            for (int c = 0; c < 6; ++c) p.gA[c] = (T *)gA[c] + start;
+            int grid = 0;
+            ksym_status st = grid_for(len, o.block * o.mats_per_lane, o.grid_mult, &grid);
+            if (st != KSYM_OK) return st;
+            hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, (uint32_t)len,
+                                  eps_rel);
+            if (e != hipSuccess) return hip_fail(e, "launch k_eig3_bwd");
+        }
         return KSYM_OK;
     };
     return dtype == KSYM_F32 ? go(float()) : go(double());
@@ -461,14 +479,11 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
     if (dtype == KSYM_F32) o.path = KSYM_PATH_FP32_FIXUP;
     else o.path = KSYM_PATH_FP64_FIXUP;
     const size_t es = esize(dtype);
-    const int tile = o.block * o.mats_per_lane;
+    const int tile = 64 * o.mats_per_lane;   // one wave tile
     const bool f32 = dtype == KSYM_F32;
     if (f32 ? !pick_mixed<float>(o.block, o.mats_per_lane) : !pick_mixed<double>(o.block, o.mats_per_lane))
         return fail(KSYM_E_UNSUPPORTED, "no compiled mixed kernel for block %d, mats_per_lane %d",
                     o.block, o.mats_per_lane);
-    std::vector<int64_t> tb(ngroups + 1, 0);
-    const size_t dsz = f32 ? sizeof(GroupDesc<float>) : sizeof(GroupDesc<double>);
-    std::vector<unsigned char> desc(dsz * ngroups, 0);
     for (int g = 0; g < ngroups; ++g) {
         const ksym_group &G = groups[g];
         if (G.kind != 2 && G.kind != 3) return fail(KSYM_E_ARG, "group %d: kind must be 2 or 3", g);
@@ -481,37 +496,54 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
             if (!aligned(G.lam[c], es) || !aligned(G.phi[c], es)) return fail(KSYM_E_ARG, "group %d: output misaligned", g);
         for (int c = 0; c < 9; ++c)
             if (!aligned(G.D[c], es)) return fail(KSYM_E_ARG, "group %d: D[%d] misaligned", g, c);
-        tb[g + 1] = tb[g] + (G.n + tile - 1) / tile;
-        auto fill = [&](auto tag) {
-            using T = decltype(tag);
-            GroupDesc<T> d;
-            memset(&d, 0, sizeof d);
-            d.n = G.n;
-            d.kind = G.kind;
-            const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
-            for (int c = 0; c < nin; ++c) d.p3.in[c] = (const T *)G.in[c];
-            for (int c = 0; c < nl; ++c) d.p3.out[O_LAM + c] = (T *)G.lam[c];
-            for (int c = 0; c < nd; ++c) d.p3.out[O_D + c] = (T *)G.D[c];
-            for (int c = 0; c < np; ++c) d.p3.out[O_PHI + c] = (T *)G.phi[c];
-            d.p3.flags = G.flags;
-            memcpy(desc.data() + g * sizeof d, &d, sizeof d);
-        };
-        if (f32) fill(float()); else fill(double());
     }
+    // one descriptor per KSYM_CHUNK matrices of a group (offsets stay 32-bit)
+    std::vector<int64_t> tb(1, 0);
+    std::vector<unsigned char> desc;
+    const size_t dsz = f32 ? sizeof(GroupDesc<float>) : sizeof(GroupDesc<double>);
+    for (int g = 0; g < ngroups; ++g) {
+        const ksym_group &G = groups[g];
+        for (int64_t start = 0; start == 0 || start < G.n; start += KSYM_CHUNK) {
+            const int64_t len = G.n - start < KSYM_CHUNK ? G.n - start : KSYM_CHUNK;
+            auto fill = [&](auto tag) {
+                using T = decltype(tag);
+                GroupDesc<T> d;
+                memset(&d, 0, sizeof d);
+                d.n = len;
+                d.kind = G.kind;
+                const int nin = G.kind == 3 ? 6 : 3;
+                const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
+                auto adv = [&](const void *q) { return q ? (T *)q + start : nullptr; };
+                for (int c = 0; c < nin; ++c) d.p3.in[c] = adv(G.in[c]);
+                for (int c = 0; c < nl; ++c) d.p3.out[O_LAM + c] = adv(G.lam[c]);
+                for (int c = 0; c < nd; ++c) d.p3.out[O_D + c] = adv(G.D[c]);
+                for (int c = 0; c < np; ++c) d.p3.out[O_PHI + c] = adv(G.phi[c]);
+                d.p3.flags = G.flags ? G.flags + start : nullptr;
+                const size_t at = desc.size();
+                desc.resize(at + sizeof d);
+                memcpy(desc.data() + at, &d, sizeof d);
+            };
+            if (f32) fill(float()); else fill(double());
+            tb.push_back(tb.back() + (len + tile - 1) / tile);
+        }
+    }
+    const int64_t ndesc = (int64_t)(desc.size() / dsz);
+    if (ndesc >= (1 << 24)) return fail(KSYM_E_ARG, "too many groups (%lld descriptors)", (long long)ndesc);
     ksym_plan *p = new (std::nothrow) ksym_plan();
     if (!p) return fail(KSYM_E_ARG, "out of host memory");
     p->dtype = dtype;
     p->opts = o;
-    p->ngroups = ngroups;
-    p->ntiles = tb[ngroups];
+    p->ngroups = (int32_t)ndesc;
+    p->ntiles = tb.back();
     int cus = 0;
     s = cu_count(&cus);
     if (s != KSYM_OK) { delete p; return s; }
     int64_t grid = (int64_t)o.grid_mult * cus;
-    if (grid > p->ntiles) grid = p->ntiles;
+    const int64_t need = (p->ntiles + o.block / 64 - 1) / (o.block / 64);   // workgroups of block/64 waves
+    if (grid > need) grid = need;
     if (grid < 1) grid = 1;
     p->grid = (int)grid;
-    const size_t tb_bytes = (ngroups + 1) * sizeof(int64_t);
+    const size_t tb_bytes = tb.size() * sizeof(int64_t);
     const size_t total = desc.size() + 256 + tb_bytes;
     hipError_t e = hipMalloc(&p->d_groups, total);
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc plan descriptors"); }
@@ -550,6 +582,7 @@ ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
         a.prm.tau_res = p->opts.tau_res;
         a.prm.tau_vec = p->opts.tau_vec;
         a.prm.tau_dbl = p->opts.tau_dbl;
+        a.prm.drain_tiles = p->opts.drain_tiles;
         a.prm.counters = (unsigned *)ws;
         MixK<T> k = pick_mixed<T>(p->opts.block, p->opts.mats_per_lane);
         hipError_t e = launch(k, dim3(p->grid), dim3(p->opts.block), st, a);

@@ -279,10 +279,62 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
 }
 
 // ------------------------------------------------ 3x3 angle solve (§5) -----
-// Given the labelled eigenvalue differences G12 = lam1 - lam2 and
-// G32 = lam3 - lam2, and v = cos^2 phi2, w = cos^2 phi3 (5.1)-(5.2), choose the
-// signs of phi2 = +-acos(sqrt v), phi3 = +-acos(sqrt w) (5.3)-(5.4) and phi1,
-// and build D = R1 R2 R3 (2.6).
+// 1/x for positive normal x: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// The squared direction cosines of the first row of D, each as its own
+// quotient.  With A = D diag(lam) D^T, u_k = D_1k^2 satisfies sum u_k = 1,
+// sum u_k lam_k = A11 and sum u_k lam_k^2 = (A^2)_11, whose solution is
+//   u_k = n_k / ((lam_k - lam_i)(lam_k - lam_j)),
+//   n_k = A12^2 + A13^2 + (A11 - lam_i)(A11 - lam_j).
+// Then v = cos^2 phi2 = u1 + u2 (this is (5.1)), 1 - v = u3, w = cos^2 phi3 =
+// u1 / (u1 + u2) (this is (5.2)) and 1 - w = u2 / (u1 + u2).  Each pair is
+// formed as p / (p + q), q / (p + q) from two non-negative numerators, so both
+// members keep their relative accuracy (no 1 - x cancellation when x is close
+// to 1) and still sum to 1 to rounding, which keeps D orthogonal; the float64
+// numerators keep the quotients accurate when two eigenvalues are close.
+// Labels: 1 = max, 2 = min, 3 = mid; e_k = A11 - lam_k; gaps as in Cubic.
+//   v : 1 - v = n_v : -n_3 with n_v = (u1 + u2) g13 g32 = A12^2 + A13^2 + e3 (e1 + g32)
+//   w : 1 - w = n_1 g32 : n_2 g13
+struct URow {
+    double v, s2sq, w, cw;   // cos^2 phi2, sin^2 phi2, cos^2 phi3, sin^2 phi3
+};
+
+__device__ __forceinline__ void split_unit(double p, double q, double &x, double &y) {
+    p = p > 0.0 ? p : 0.0;
+    q = q > 0.0 ? q : 0.0;
+    const double t = p + q;
+    if (t > 0.0) {
+        const double r = rcp64(t);
+        x = p * r;
+        y = q * r;
+    } else {
+        x = 1.0;
+        y = 0.0;
+    }
+}
+
+__device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, double mu3, double g13,
+                                            double g32, double a12, double a13) {
+    const double F = a12 * a12 + a13 * a13;
+    const double e1 = d1 - mu1, e2 = d1 - mu2, e3 = d1 - mu3;
+    URow u;
+    split_unit(F + e3 * (e1 + g32), -(F + e1 * e2), u.v, u.s2sq);
+    // v = 0 gives w = 1, the paper's convention
+    split_unit((F + e2 * e3) * g32, (F + e1 * e3) * g13, u.w, u.cw);
+    return u;
+}
+
+// Given the labelled eigenvalue differences G12 = lam1 - lam2, G13 = lam1 -
+// lam3, G32 = lam3 - lam2 and the squared cosines and sines of phi2, phi3,
+// choose the signs of phi2 = +-acos(sqrt v), phi3 = +-acos(sqrt w) (5.3)-(5.4)
+// and phi1, and build D = R1 R2 R3 (2.6).
 //
 // Trig-free form of the selection.  Writing 2-vectors as complex numbers, a
 // sign combination only flips signs inside g1 = (s3*alpha, s2*beta) and
@@ -294,6 +346,10 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
 // |z2| = |f2||g2| do not depend on the signs.  Ties keep the first of
 // (+,+), (+,-), (-,+), (-,-).  phi1 is phi1(1) when |f1| >= |f2| and phi1(2)
 // otherwise (5.15); its cosine and sine come from normalising z1 or sqrt z2.
+// The brackets of (5.7)-(5.8) are rearranged with w + (1 - w) = 1 and
+// v + (1 - v) = 1 so that no difference of nearly equal terms is formed:
+//   (lam1 - lam2) w + lam2 - lam3 = G13 w - G32 (1 - w),
+//   1 + (v - 2) w = (1 - w) - w (1 - v).
 template <typename T>
 __device__ __forceinline__ void csqrt_principal(T x, T y, T& rx, T& ry) {
     using M = Mth<T>;
@@ -314,17 +370,17 @@ template <typename T> struct Rot {
 };
 
 template <typename T>
-__device__ __forceinline__ Rot<T> select_angles(T a12, T a13, T a22, T a33, T a23, T G12, T G32,
-                                                T v, T w) {
+__device__ __forceinline__ Rot<T> select_angles(T a12, T a13, T a22, T a33, T a23, T G12, T G13, T G32,
+                                                T v, T s2sq, T w, T cw) {
     using M = Mth<T>;
     Rot<T> R;
-    const T c2 = M::sqrt(v), s2 = M::sqrt(T(1) - v);
-    const T c3 = M::sqrt(w), s3 = M::sqrt(T(1) - w);
+    const T c2 = M::sqrt(v), s2 = M::sqrt(s2sq);
+    const T c3 = M::sqrt(w), s3 = M::sqrt(cw);
     // g1 = (s3 al, s2 be), g2 = (ga, s2 s3 de), from (5.7)-(5.8) with
     // sin(2 phi) = 2 sin(phi) cos(phi)
     const T al = G12 * c2 * s3 * c3;
-    const T be = (G12 * w - G32) * s2 * c2;
-    const T ga = G12 * (T(1) + (v - T(2)) * w) - G32 * v;
+    const T be = (G13 * w - G32 * cw) * s2 * c2;
+    const T ga = G12 * (cw - w * s2sq) - G32 * v;
     const T de = T(2) * G12 * s2 * s3 * c3;
     // conj(f1) = (a12, a13), conj(f2) = (a22 - a33, 2 a23), from (5.5)-(5.6)
     const T e = a22 - a33, f = T(2) * a23;

@@ -1,17 +1,21 @@
 // Tile processors and __global__ kernels for the ksym C ABI (gfx950, wave64).
 //
-// Work decomposition: a workgroup of BS lanes owns tiles of BS * MPL matrices
-// (MPL = matrices per lane) and walks them grid-stride.  Within a tile, matrix
-// k*BS + lane belongs to `lane`, so every plane load and store of a wave is one
-// contiguous 64-element run.
+// Work decomposition: every wavefront works on its own tiles of 64 * MPL
+// matrices (MPL = matrices per lane) and walks them grid-stride; matrix
+// k*64 + lane of a tile belongs to `lane`, so every plane load and store is one
+// contiguous 64-element run and needs no staging.  The waves of a workgroup
+// never wait for each other: there is no workgroup barrier in the 3x3 kernels.
 //
 // Refinement routing (3x3 float32 and float64 check paths): a lane whose
-// matrix fails the float64 check does not store; it appends the matrix to an
-// on-chip queue with one LDS atomic per wavefront (ballot + popcount for the
-// wave's total, mbcnt for the lane's rank).  After the tile, the workgroup's
-// lanes drain the queue -- entry j to lane j, so the refinement runs on dense
-// wavefronts -- and store those matrices' outputs.  Nothing is re-read from
-// HBM, and every output element is written exactly once.
+// matrix fails the check stores its provisional result and appends the matrix
+// to its wave's queue in LDS (ballot + popcount for the count, mbcnt for the
+// lane's rank; the count lives in a scalar register).  When the queue holds 64
+// entries the wave refines them together, entry j on lane j, so the float64
+// refinement always runs on full wavefronts, and overwrites those outputs.
+//
+// Offsets are 32-bit: one launch covers at most KSYM_CHUNK matrices (the host
+// splits larger batches), so every access is a scalar base plus one 32-bit
+// lane offset.
 #pragma once
 
 #include <stddef.h>
@@ -19,6 +23,7 @@
 #include "ksym_device.hpp"
 
 namespace ksym {
+
 
 enum { PATH_FP32_FIXUP = 0, PATH_FP64_PLAIN = 1, PATH_FP64_FIXUP = 2 };
 
@@ -33,11 +38,15 @@ template <typename T> struct Eig3Ptrs {
     uint8_t *flags;
 };
 
+// Matrices per launch: offsets inside a launch are 32-bit byte offsets.
+constexpr int64_t KSYM_CHUNK = int64_t(1) << 28;
+
 struct Eig3Params {
-    int64_t n;
+    int64_t n;            // at most KSYM_CHUNK
     double tau_gap, tau_res, tau_vec, tau_dbl;
     unsigned *counters;   // [0] refined, [1] non-finite; may be null
-    int32_t zero;         // always 0; see store_tile3
+    int32_t zero;         // always 0; see put3
+    int32_t drain_tiles;  // queue age limit in wave tiles (0 = full waves only)
 };
 
 template <typename T> struct Eig3Args {
@@ -95,7 +104,8 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             if (cu.g13 < cu.g32) { lm = 0.5 * (cu.mu1 + cu.mu3); ls = cu.mu2; }
             else { lm = 0.5 * (cu.mu3 + cu.mu2); ls = cu.mu1; }
             const T s = clamp01((T)((cu.d1 - ls) / (lm - ls)));
-            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, T(0), (T)(ls - lm), s, T(1));
+            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, T(0), (T)(lm - ls), (T)(ls - lm), s,
+                                              T(1) - s, T(1), T(0));
             T Di[9];
             build_D(R, Di);
             double L[3];
@@ -117,13 +127,24 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             o.v[O_GAP + 2] = (T)((L[2] - L[1]) * isc);
             o.flag = FLAG_DOUBLE;
         } else {
-            // general branch (5.1)-(5.15): v, w with the eigenvalue
-            // differences taken from the float64 stage
+            // general branch (5.1)-(5.15), with the eigenvalue differences
+            // taken from the float64 stage.  The plain path evaluates v, w as
+            // printed; the checked path forms v, 1 - v, w, 1 - w as separate
+            // quotients (u_quotients), which stay accurate near coincident
+            // eigenvalues.
             const T G12 = (T)cu.g12, G13 = (T)cu.g13, G32 = (T)cu.g32;
-            const T e1 = (T)(cu.d1 - cu.mu1), e3 = (T)(cu.d1 - cu.mu3);   // A11 - lam1, A11 - lam3
-            const T v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
-            const T w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
-            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G32, v, w);
+            T v, s2sq, w, cw;
+            if (PATH == PATH_FP64_PLAIN) {
+                const T e1 = (T)(cu.d1 - cu.mu1), e3 = (T)(cu.d1 - cu.mu3);   // A11 - lam1, A11 - lam3
+                v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
+                w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
+                s2sq = T(1) - v;
+                cw = T(1) - w;
+            } else {
+                const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a12, a13);
+                v = (T)u.v; s2sq = (T)u.s2sq; w = (T)u.w; cw = (T)u.cw;
+            }
+            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw);
             build_D(R, o.v + O_D);
             angles_of(R, o.v + O_PHI);
             o.v[O_LAM] = (T)((cu.m + cu.mu1) * isc);
@@ -158,30 +179,16 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     }
 }
 
-// Per-workgroup staging of a tile's outputs in LDS: the main pass and the
-// refinement both write here, then the tile leaves with one coalesced store per
-// plane, so every output element is written to HBM exactly once.
-template <typename T, int TILE> struct Stage3 {
-    T v[NOUT3][TILE];
-    uint8_t flag[TILE];
-};
-
-template <typename T, int TILE>
-__device__ __forceinline__ void stage_put(Stage3<T, TILE> *st, int slot, const Out3<T> &o) {
-#pragma unroll
-    for (int k = 0; k < NOUT3; ++k) st->v[k][slot] = o.v[k];
-    st->flag[slot] = (uint8_t)o.flag;
-}
-
-// The float32 path for one matrix, written for a small register footprint:
-// everything after the float64 cubic stage is float32, results go to the LDS
-// staging slot as soon as they exist (eigenvalues and gaps first, then the
-// angles, then D after the check), and the a-posteriori check runs in float32
-// on B = A - m I.  Sets `refine` (and the isolated eigenvalue lc for the
-// refinement, a float64 deviation in scaled units) and returns the flag.
-template <int TILE>
-__device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &prm,
-                                        Stage3<float, TILE> *st, int slot, bool &refine, double &lc) {
+// The float32 path for one matrix: the cubic stage in float64 (with float32
+// polynomial tails), the squared cosines of the angle solve as float64
+// quotients, the rest in float32, and the a-posteriori check in float32 on
+// B = A - m I.  Outputs leave through sink.put(k, value) as soon as they
+// exist (plane k of lam, D, phi, gap), which keeps few of them in registers.
+// Sets refine (and the isolated eigenvalue lc for the refinement, a float64
+// deviation in scaled units) and returns the flag.
+template <typename Sink>
+__device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &prm, const Sink &sink,
+                                        bool &refine, double &lc) {
     const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
                      finite(ain[4]) && finite(ain[5]);
     float amax = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[0]), __builtin_fabsf(ain[1])),
@@ -193,123 +200,63 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = fin ? (double)ain[c] * sc : 0.0;
+    for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;   // non-finite: handled below
     const Cubic cu = cubic_stage_fast(a[0], a[1], a[2], a[3], a[4], a[5]);
     refine = false;
     lc = 0.0;
-    int flag;
     if (cu.triple || !fin) {
         // §5, p = 0: A = lam I, D = I, angles 0 (non-finite input: all NaN)
         const float nan = __builtin_nanf("");
         const float lam = fin ? (float)(cu.m * isc) : nan;
-        st->v[O_LAM][slot] = lam; st->v[O_LAM + 1][slot] = lam; st->v[O_LAM + 2][slot] = lam;
+        const float one = fin ? 1.0f : nan, zero = fin ? 0.0f : nan;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st->v[O_D + i][slot] = fin ? ((i % 4 == 0) ? 1.0f : 0.0f) : nan;
+        for (int k = 0; k < 3; ++k) sink.put(O_LAM + k, lam);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sink.put(O_D + i, (i % 4 == 0) ? one : zero);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            st->v[O_PHI + k][slot] = fin ? 0.0f : nan;
-            st->v[O_GAP + k][slot] = fin ? 0.0f : nan;
+            sink.put(O_PHI + k, zero);
+            sink.put(O_GAP + k, zero);
         }
-        flag = fin ? FLAG_TRIPLE : FLAG_NONFINITE;
-        st->flag[slot] = (uint8_t)flag;
+        const int flag = fin ? FLAG_TRIPLE : FLAG_NONFINITE;
+        sink.flag(flag);
         return flag;
     }
-    st->v[O_LAM][slot] = (float)((cu.m + cu.mu1) * isc);
-    st->v[O_LAM + 1][slot] = (float)((cu.m + cu.mu2) * isc);
-    st->v[O_LAM + 2][slot] = (float)((cu.m + cu.mu3) * isc);
-    st->v[O_GAP][slot] = (float)(cu.g12 * isc);
-    st->v[O_GAP + 1][slot] = (float)(cu.g13 * isc);
-    st->v[O_GAP + 2][slot] = (float)(cu.g32 * isc);
-    const double split = fmin(cu.g13, cu.g32);
+    sink.put(O_LAM, (float)((cu.m + cu.mu1) * isc));
+    sink.put(O_LAM + 1, (float)((cu.m + cu.mu2) * isc));
+    sink.put(O_LAM + 2, (float)((cu.m + cu.mu3) * isc));
+    sink.put(O_GAP, (float)(cu.g12 * isc));
+    sink.put(O_GAP + 1, (float)(cu.g13 * isc));
+    sink.put(O_GAP + 2, (float)(cu.g32 * isc));
+    const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
     const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
-    const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
-    bool bad = dbl || (split < prm.tau_gap * lmax);
+    const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
+    bool bad = dbl || (split < prm.tau_gap * (l1 > l2 ? l1 : l2));
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
-    // float32 operands of the angle solve and the check (scaled units)
+    // general branch (5.1)-(5.15): the four squared cosines and sines as
+    // float64 quotients (u_quotients), the rest of the angle solve in float32
+    const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
     const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
-    const float A22 = (float)a[1], A33 = (float)a[2];
     const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
-    const float e1 = (float)(cu.d1 - cu.mu1), e3 = (float)(cu.d1 - cu.mu3);
-    const float d1 = (float)cu.d1, d2 = (float)cu.d2, d3 = (float)cu.d3;
-    const float m1 = (float)cu.mu1, m2 = (float)cu.mu2, m3 = (float)cu.mu3;
-    const float fro = __builtin_sqrtf((float)(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] +
-                                              2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5])));
-    // general branch (5.1)-(5.15)
-    const float v = clamp01(Mth<float>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
-    const float w = (v == 0.0f) ? 1.0f : clamp01(Mth<float>::div(e3 + G32 * v, G12 * v));
-    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G32, v, w);
+    const Rot<float> R = select_angles<float>(A12, A13, (float)a[1], (float)a[2], A23, G12, G13, G32,
+                                              (float)u.v, (float)u.s2sq, (float)u.w, (float)u.cw);
     float phi[3];
     angles_of(R, phi);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) st->v[O_PHI + k][slot] = phi[k];
+    for (int k = 0; k < 3; ++k) sink.put(O_PHI + k, phi[k]);
     float D[9];
     build_D(R, D);
-    bad = bad || check_fails<float>(d1, d2, d3, A12, A13, A23, D, m1, m2, m3, G12, G13, G32,
-                                    (float)prm.tau_res * fro, (float)prm.tau_vec);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st->v[O_D + i][slot] = D[i];
-    flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
-    st->flag[slot] = (uint8_t)flag;
+    for (int i = 0; i < 9; ++i) sink.put(O_D + i, D[i]);
+    const float fro = __builtin_sqrtf((float)(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] +
+                                              2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5])));
+    bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
+                                    (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
+                                    (float)prm.tau_res * fro, (float)prm.tau_vec);
+    const int flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
+    sink.flag(flag);
     refine = bad;
     return flag;
-}
-
-// Output plane pointers read from the kernel-argument segment with a
-// plane-dependent offset: the store loop fetches each pointer with one scalar
-// load when it needs it instead of holding all of them in registers.
-template <typename T> struct KernargPlanes {
-    uint32_t out_off, flags_off;   // byte offsets inside the argument segment
-    __device__ __forceinline__ T *out(int k) const {
-        typedef __attribute__((address_space(4))) const char *kptr;
-        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
-        return *(T *const __attribute__((address_space(4))) *)(ka + out_off + 8 * k);
-    }
-    __device__ __forceinline__ uint8_t *flags(int salt = 0) const {
-        typedef __attribute__((address_space(4))) const char *kptr;
-        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
-        return *(uint8_t *const __attribute__((address_space(4))) *)(ka + flags_off + 8 * salt);
-    }
-};
-
-// Output plane pointers of a group descriptor in device memory.
-template <typename T> struct TablePlanes {
-    const Eig3Ptrs<T> *p;
-    __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
-    __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
-};
-
-// Store a staged tile.  The plane pointers are fetched here, for this tile: the
-// plane index is offset by salt = tile * zero, which is 0 at run time but not
-// known to the compiler, so the fully unrolled loop issues all pointer loads
-// together without hoisting them out of the tile loop (where they would pin
-// 38 scalar registers for the whole kernel).
-template <typename T, int BS, int MPL, int TILE, typename Planes>
-__device__ __forceinline__ void store_tile3(const Planes &pl, const Stage3<T, TILE> *st, int64_t n,
-                                            int64_t base, int salt) {
-    const int tid = threadIdx.x;
-    T *dst[NOUT3];
-#pragma unroll
-    for (int k = 0; k < NOUT3; ++k) dst[k] = pl.out(k + salt);
-    uint8_t *fl = pl.flags(salt);
-#pragma unroll
-    for (int m = 0; m < MPL; ++m) {
-        const int64_t i = base + m * BS + tid;
-        T val[NOUT3];   // all LDS reads first, then the stores
-#pragma unroll
-        for (int k = 0; k < NOUT3; ++k) val[k] = st->v[k][m * BS + tid];
-        if (i < n) {
-#pragma unroll
-            for (int k = 0; k < NOUT3; ++k)
-                if (dst[k]) dst[k][i] = val[k];
-        }
-    }
-    if (fl) {
-#pragma unroll
-        for (int m = 0; m < MPL; ++m) {
-            const int64_t i = base + m * BS + tid;
-            if (i < n) fl[i] = st->flag[m * BS + tid];
-        }
-    }
 }
 
 // The refinement of one queued matrix (original entries ain, isolated
@@ -337,136 +284,205 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
     o.flag = flag | FLAG_FIXUP;
 }
 
-// On-chip refinement queue of one workgroup.  Entries accumulate over tiles;
-// the queue is drained when it holds at least one entry per lane, so the
-// float64 refinement always runs on full wavefronts.
-template <typename T, int CAP> struct Queue {
-    int n;
-    int64_t idx[CAP];   // matrix index within its group
-    int grp[CAP];       // group (mixed batches; 0 otherwise) | flag << 24
-    T a[6][CAP];
-    double lc[CAP];
-};
+// ------------------------------------------------------ per-wave tiles -----
+constexpr int WAVE = 64;
 
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+}
 __device__ __forceinline__ unsigned lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
+// Orders this wave's LDS accesses around a hand-over between its lanes (the
+// hardware executes one wave's LDS instructions in order; this keeps the
+// compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// Element `off` of plane p through a 32-bit byte offset (off < KSYM_CHUNK).
+template <typename T> __device__ __forceinline__ T *elem(T *p, uint32_t off) {
+    return (T *)((char *)p + off * (uint32_t)sizeof(T));
+}
 
-// Inputs of one tile held in registers.  SoA: each lane's MPL matrices.
-// AoS: the lane's share of the tile's contiguous records as 16-byte vectors,
-// transposed through LDS when the tile is processed.
-template <typename T, int BS, int MPL, bool AOS> struct TileIn {
+// Output plane pointers read from the kernel-argument segment with a
+// plane-dependent offset: the pointers are fetched (a few scalar loads) where a
+// matrix's outputs are stored instead of being held in scalar registers for
+// the whole kernel.
+template <typename T> struct KernargPlanes {
+    uint32_t out_off, flags_off;   // byte offsets inside the argument segment
+    __device__ __forceinline__ T *out(int k) const {
+        typedef __attribute__((address_space(4))) const char *kptr;
+        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+        return *(T *const __attribute__((address_space(4))) *)(ka + out_off + 8 * k);
+    }
+    __device__ __forceinline__ uint8_t *flags(int salt = 0) const {
+        typedef __attribute__((address_space(4))) const char *kptr;
+        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+        return *(uint8_t *const __attribute__((address_space(4))) *)(ka + flags_off + 8 * salt);
+    }
+};
+
+// Output plane pointers of a group descriptor in device memory.
+template <typename T> struct TablePlanes {
+    const Eig3Ptrs<T> *p;
+    __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
+    __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
+};
+
+// Store one matrix's outputs.  The plane index is offset by salt, which is 0
+// at run time but not known to the compiler, so the pointer loads stay here
+// instead of being hoisted out of the tile loop (where they would pin 38
+// scalar registers for the whole kernel).
+template <typename T, typename Planes>
+__device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, const Out3<T> &o) {
+    T *dst[NOUT3];
+#pragma unroll
+    for (int k = 0; k < NOUT3; ++k) dst[k] = pl.out(k + salt);
+    uint8_t *fl = pl.flags(salt);
+#pragma unroll
+    for (int k = 0; k < NOUT3; ++k)
+        if (dst[k]) *elem(dst[k], off) = o.v[k];
+    if (fl) fl[off] = (uint8_t)o.flag;
+}
+
+// Stores of one lane's matrix as its outputs are produced (float32 path).
+template <typename T, typename Planes> struct LaneSink {
+    const Planes &pl;
+    int salt;
+    uint32_t off;
+    bool valid;
+    __device__ __forceinline__ void put(int k, T v) const {
+        T *d = pl.out(k + salt);
+        if (valid && d) *elem(d, off) = v;
+    }
+    __device__ __forceinline__ void flag(int f) const {
+        uint8_t *fl = pl.flags(salt);
+        if (valid && fl) fl[off] = (uint8_t)f;
+    }
+};
+
+// A refined result: scattered stores (the rare path).
+template <typename T, typename Planes>
+__device__ __forceinline__ void write_out3(const Planes &pl, uint32_t off, const Out3<T> &o) {
+#pragma unroll
+    for (int k = 0; k < NOUT3; ++k) {
+        T *dst = pl.out(k);
+        if (dst) *elem(dst, off) = o.v[k];
+    }
+    uint8_t *fl = pl.flags();
+    if (fl) fl[off] = (uint8_t)o.flag;
+}
+
+// One wave's refinement queue: CAP = 64 * (MPL + 1) entries, enough for a
+// queue one entry short of a drain plus a whole tile.
+template <typename T, int CAP> struct WaveQueue {
+    uint32_t off[CAP];   // matrix offset within its launch chunk / group
+    int32_t grp[CAP];    // group (mixed batches; 0 otherwise) | flag << 24
+    double lc[CAP];
+    T a[6][CAP];
+};
+
+template <typename T, int MPL, bool QUEUE, bool AOS> struct WaveSmem {
+    WaveQueue<T, QUEUE ? WAVE * (MPL + 1) : 1> q;
+    __align__(16) T rec[AOS ? WAVE * MPL * 6 : 4];
+};
+
+// The inputs of one wave tile held in registers.  SoA: each lane's MPL
+// matrices.  AoS: the lane's share of the tile's contiguous records as 16-byte
+// vectors, transposed through LDS when the tile is processed.
+template <typename T, int MPL, bool AOS> struct WIn {
     static constexpr int VEC = 16 / sizeof(T);
-    static constexpr int NV = BS * MPL * 6 / VEC;          // 16-byte vectors per tile
-    static constexpr int NVL = (NV + BS - 1) / BS;         // per lane
+    static constexpr int NV = WAVE * MPL * 6 / VEC;   // 16-byte vectors per tile
+    static constexpr int NVL = (NV + WAVE - 1) / WAVE;
     T a[AOS ? 1 : MPL][6];
     T v[AOS ? NVL : 1][AOS ? VEC : 1];
 };
 
-template <typename T, int BS, int MPL, bool AOS>
-__device__ __forceinline__ void load_tile3(TileIn<T, BS, MPL, AOS> &in, const T *const *planes,
-                                           const T *aos, int64_t n, int64_t base) {
-    const int tid = threadIdx.x;
+template <typename T, int MPL, bool AOS>
+__device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const *planes,
+                                            const T *aos, uint32_t n, uint32_t base) {
+    const int lane = lane_id();
     if constexpr (AOS) {
-        using TI = TileIn<T, BS, MPL, AOS>;
-        constexpr int VEC = TI::VEC;
-        const int64_t lim = (n - base) * 6;   // valid elements in this tile
-        const T *src = aos + base * 6;
+        using W = WIn<T, MPL, AOS>;
+        constexpr int VEC = W::VEC;
+        const uint32_t lim = (n - base) * 6;   // valid elements from `base` on
+        const T *src = aos + (size_t)base * 6;
 #pragma unroll
-        for (int u = 0; u < TI::NVL; ++u) {
-            const int j = u * BS + tid;
-            const int64_t e0 = (int64_t)j * VEC;
-            if (j < TI::NV && e0 + VEC <= lim) {
+        for (int u = 0; u < W::NVL; ++u) {
+            const uint32_t j = u * WAVE + lane;
+            const uint32_t e0 = j * VEC;
+            if (j < (uint32_t)W::NV && e0 + VEC <= lim) {
                 if constexpr (sizeof(T) == 4) {
-                    const float4 x = *reinterpret_cast<const float4 *>(src + e0);
+                    const float4 x = *reinterpret_cast<const float4 *>(elem(src, e0));
                     in.v[u][0] = x.x; in.v[u][1] = x.y; in.v[u][2] = x.z; in.v[u][3] = x.w;
                 } else {
-                    const double2 x = *reinterpret_cast<const double2 *>(src + e0);
+                    const double2 x = *reinterpret_cast<const double2 *>(elem(src, e0));
                     in.v[u][0] = x.x; in.v[u][1] = x.y;
                 }
             } else {
 #pragma unroll
                 for (int t = 0; t < VEC; ++t)
-                    in.v[u][t] = (j < TI::NV && e0 + t < lim) ? src[e0 + t] : T(0);
+                    in.v[u][t] = (j < (uint32_t)W::NV && e0 + t < lim) ? *elem(src, e0 + t) : T(0);
             }
         }
     } else {
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
-            const int64_t i = base + k * BS + tid;
+            const uint32_t off = base + k * WAVE + lane;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) in.a[k][c] = (i < n) ? planes[c][i] : T(0);
+            for (int c = 0; c < 6; ++c) in.a[k][c] = (off < n) ? *elem(planes[c], off) : T(0);
         }
     }
 }
 
-// Write one matrix's outputs (a refined result) to the output planes.
-template <typename T, typename Planes>
-__device__ __forceinline__ void write_out3(const Planes &pl, int64_t i, const Out3<T> &o) {
-#pragma nounroll
-    for (int k = 0; k < NOUT3; ++k) {
-        T *dst = pl.out(k);
-        if (dst) dst[i] = o.v[k];
-    }
-    uint8_t *fl = pl.flags();
-    if (fl) fl[i] = (uint8_t)o.flag;
-}
-
-// Drain the first `cnt` queue entries: entry j goes to lane j (mod BS), each
-// result is written straight to its output planes.  The tile store that wrote
-// the provisional values happened before the workgroup barrier (with its
-// release fence) that precedes every call.
-template <typename T, int BS, int CAP, typename PlanesOf>
-__device__ __forceinline__ void drain_queue(Queue<T, CAP> *q, int cnt, const PlanesOf &planes_of) {
-    for (int j = threadIdx.x; j < cnt; j += BS) {
+// Refine the first `cnt` (<= 64) queue entries, entry j on lane j, and
+// overwrite their provisional outputs.  The wave's own provisional stores are
+// waited for first, so a refined value always lands last.
+template <typename T, int CAP, typename PlanesOf>
+__device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const PlanesOf &planes_of) {
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): earlier stores of this wave have completed
+    const int lane = lane_id();
+    if (lane < cnt) {
         T a[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a[c] = q->a[c][j];
-        const int g = q->grp[j];
+        for (int c = 0; c < 6; ++c) a[c] = q->a[c][lane];
+        const int g = q->grp[lane];
         Out3<T> o;
-        refine_one<T>(a, q->lc[j], g >> 24, o);
-        write_out3(planes_of(g & 0xffffff), q->idx[j], o);
+        refine_one<T>(a, q->lc[lane], g >> 24, o);
+        write_out3(planes_of(g & 0xffffff), q->off[lane], o);
     }
 }
 
-// Workgroup-shared memory of the 3x3 kernels.
-template <typename T, int BS, int TILE, bool QUEUE, bool AOS> struct Smem3 {
-    Queue<T, QUEUE ? BS + TILE : 1> q;
-    Stage3<T, TILE> st;
-    __align__(16) T rec[AOS ? TILE * 6 : 1];
-};
-
-// Process one tile of BS*MPL 3x3 matrices starting at `base` from inputs
-// already in registers, store it, and drain the refinement queue when it holds
-// at least BS entries.  Block-uniform control flow.  The staging slots are
-// written and read only by their own lane, so the tile store needs no barrier;
-// two barriers per tile make the queue length consistent, two more surround a
-// drain.  The AoS record buffer is last read before the first barrier (an
-// extra barrier closes the tile when there is no queue).
-template <typename T, int PATH, int BS, int MPL, bool AOS, typename Planes, typename PlanesOf>
-__device__ __forceinline__ void tile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
-                                          const Eig3Params &prm, TileIn<T, BS, MPL, AOS> &in,
-                                          int64_t n, int64_t base,
-                                          Smem3<T, BS, BS * MPL, PATH != PATH_FP64_PLAIN, AOS> *sm,
-                                          unsigned &refined, unsigned &nonfinite) {
-    constexpr int TILE = BS * MPL;
-    const int tid = threadIdx.x;
+// Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
+// already in registers: compute, store, queue the matrices that need the
+// refinement, and drain the queue in rounds of 64.  Wave-uniform control flow.
+template <typename T, int PATH, int MPL, bool AOS, typename Planes, typename PlanesOf>
+__device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
+                                           const Eig3Params &prm, const WIn<T, MPL, AOS> &in,
+                                           uint32_t n, uint32_t base,
+                                           WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS> *sm,
+                                           int &qn, int &qage, unsigned &refined, unsigned &nonfinite) {
+    constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
+    const int lane = lane_id();
     if constexpr (AOS) {
-        using TI = TileIn<T, BS, MPL, AOS>;
+        using W = WIn<T, MPL, AOS>;
 #pragma unroll
-        for (int u = 0; u < TI::NVL; ++u) {
-            const int j = u * BS + tid;
-            if (j < TI::NV) {
+        for (int u = 0; u < W::NVL; ++u) {
+            const int j = u * WAVE + lane;
+            if (j < W::NV) {
 #pragma unroll
-                for (int t = 0; t < TI::VEC; ++t) sm->rec[j * TI::VEC + t] = in.v[u][t];
+                for (int t = 0; t < W::VEC; ++t) sm->rec[j * W::VEC + t] = in.v[u][t];
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
-        const int slot = k * BS + tid;
-        const bool valid = base + slot < n;
+        const int slot = k * WAVE + lane;
+        const uint32_t off = base + slot;
+        const bool valid = off < n;
         T A[6];
         if constexpr (AOS) {
 #pragma unroll
@@ -475,117 +491,123 @@ __device__ __forceinline__ void tile_eig3(const Planes &pl, const PlanesOf &plan
 #pragma unroll
             for (int c = 0; c < 6; ++c) A[c] = in.a[k][c];
         }
+        const int salt = (int)((base + k) * (uint32_t)prm.zero);
+        int flag;
         bool refine;
         double lc;
-        int flag;
         if constexpr (PATH == PATH_FP32_FIXUP) {
-            flag = eig3_f32<TILE>(A, prm, &sm->st, slot, refine, lc);
+            flag = eig3_f32(A, prm, LaneSink<T, Planes>{pl, salt, off, valid}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T, PATH>(A, prm, o);
-            stage_put(&sm->st, slot, o);
+            if (valid) put3(pl, salt, off, o);
+            flag = o.flag;
             refine = o.refine;
             lc = o.lc;
-            flag = o.flag;
         }
-        if (flag == FLAG_NONFINITE) nonfinite += valid ? 1u : 0u;
-        if constexpr (PATH != PATH_FP64_PLAIN) {
+        nonfinite += (unsigned)__popcll(__ballot(valid && flag == FLAG_NONFINITE));
+        if constexpr (QUEUE) {
             const bool r = valid && refine;
             const uint64_t mask = __ballot(r);
             if (mask) {
-                int off = 0;
-                if ((tid & 63) == 0) off = atomicAdd(&sm->q.n, (int)__popcll(mask));
-                off = __builtin_amdgcn_readfirstlane(off);
                 if (r) {
-                    const int pos = off + (int)lane_rank(mask);
-                    sm->q.idx[pos] = base + slot;
+                    const int pos = qn + (int)lane_rank(mask);
+                    sm->q.off[pos] = off;
                     sm->q.grp[pos] = grp | (flag << 24);
+                    sm->q.lc[pos] = lc;
 #pragma unroll
                     for (int c = 0; c < 6; ++c) sm->q.a[c][pos] = A[c];
-                    sm->q.lc[pos] = lc;
                 }
+                qn += (int)__popcll(mask);
             }
         }
     }
-    store_tile3<T, BS, MPL, TILE>(pl, &sm->st, n, base, (int)(base * prm.zero));
-    if constexpr (PATH != PATH_FP64_PLAIN) {
-        __syncthreads();
-        const int cnt = sm->q.n;
-        __syncthreads();
-        if (cnt >= BS) {
-            // drain whole rounds only, then move the remainder to the front
-            const int nfull = cnt - cnt % BS;
-            drain_queue<T, BS>(&sm->q, nfull, planes_of);
-            refined += (tid == 0) ? (unsigned)nfull : 0u;
-            __syncthreads();
-            const int rest = cnt - nfull;   // < BS
-            if (tid < rest) {
-                const int j = nfull + tid;
-                const int64_t ix = sm->q.idx[j];
-                const int gf = sm->q.grp[j];
-                const double l = sm->q.lc[j];
-                T a[6];
+    if constexpr (AOS) wave_sync();
+    if constexpr (QUEUE) {
+        // drain rounds of up to 64: when a full round waits, or when the
+        // oldest entry has waited drain_tiles tiles (its tile's output lines
+        // are then still likely to be in cache when they are overwritten)
+        qage = qn > 0 ? qage + 1 : 0;
+        while (qn >= WAVE || (qn > 0 && prm.drain_tiles > 0 && qage >= prm.drain_tiles)) {
+            const int cnt = qn < WAVE ? qn : WAVE;
+            wave_sync();
+            drain_wave<T>(&sm->q, cnt, planes_of);
+            refined += (unsigned)cnt;
+            const int rest = qn - cnt;
+            // move entries [cnt, qn) to the front; a lane reads only entries
+            // no lane writes in the same round
+            for (int j = lane; j < rest; j += WAVE) {
+                const int s = j + cnt;
+                const uint32_t o_ = sm->q.off[s];
+                const int32_t g_ = sm->q.grp[s];
+                const double l_ = sm->q.lc[s];
+                T a_[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) a[c] = sm->q.a[c][j];
-                sm->q.idx[tid] = ix;
-                sm->q.grp[tid] = gf;
-                sm->q.lc[tid] = l;
+                for (int c = 0; c < 6; ++c) a_[c] = sm->q.a[c][s];
+                sm->q.off[j] = o_;
+                sm->q.grp[j] = g_;
+                sm->q.lc[j] = l_;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sm->q.a[c][tid] = a[c];
+                for (int c = 0; c < 6; ++c) sm->q.a[c][j] = a_[c];
             }
-            if (tid == 0) sm->q.n = rest;
-            __syncthreads();
-        }
-    } else if constexpr (AOS) {
-        __syncthreads();
-    }
-}
-
-// Drain what is left in the queue at the end of a workgroup's work.
-template <typename T, int PATH, int BS, int TILE, bool AOS, typename PlanesOf>
-__device__ __forceinline__ void final_drain(const PlanesOf &planes_of,
-                                            Smem3<T, BS, TILE, PATH != PATH_FP64_PLAIN, AOS> *sm,
-                                            unsigned &refined) {
-    if constexpr (PATH != PATH_FP64_PLAIN) {
-        __syncthreads();
-        const int cnt = sm->q.n;
-        if (cnt > 0) {
-            drain_queue<T, BS>(&sm->q, cnt, planes_of);
-            refined += (threadIdx.x == 0) ? (unsigned)cnt : 0u;
+            qn = rest;
+            qage = rest > 0 ? 1 : 0;
+            wave_sync();
         }
     }
 }
 
+// Refine what is left in a wave's queue at the end of its work.
+template <typename T, int MPL, bool AOS, typename PlanesOf>
+__device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
+                                            int qn, unsigned &refined) {
+    if (qn > 0) {
+        wave_sync();
+        drain_wave<T>(&sm->q, qn, planes_of);
+        refined += (unsigned)qn;
+    }
+}
+
+__device__ __forceinline__ void add_counters(unsigned *counters, unsigned refined, unsigned nonfinite) {
+    if (counters && lane_id() == 0) {
+        if (refined) atomicAdd(&counters[0], refined);
+        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+    }
+}
+
+// float32, one matrix per lane, SoA: the refinement path needs a few more
+// registers than the main path; asking for 5 waves per SIMD makes the
+// compiler fit both into 96 VGPRs (without spills) instead of dropping to 4.
 template <typename T, int PATH, int BS, int MPL, bool AOS>
-__global__ __launch_bounds__(BS) void k_eig3(Eig3Args<T> args) {
-    constexpr int TILE = BS * MPL;
-    __shared__ Smem3<T, BS, TILE, PATH != PATH_FP64_PLAIN, AOS> sm;
-    if (threadIdx.x == 0) sm.q.n = 0;
-    __syncthreads();
-    const int64_t n = args.prm.n;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
+__global__ __launch_bounds__(BS)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1 && !AOS) ? 5 : 1)))
+void k_eig3(Eig3Args<T> args) {
+    constexpr int NW = BS / WAVE;
+    constexpr int WT = WAVE * MPL;
+    constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
+    __shared__ WaveSmem<T, MPL, QUEUE, AOS> sm[NW];
+    WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wave_id()];
+    const uint32_t n = (uint32_t)args.prm.n;
+    const uint32_t ntiles = (n + WT - 1) / WT;
     KernargPlanes<T> pl;
     pl.out_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, out));
     pl.flags_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, flags));
     auto planes_of = [&](int) { return pl; };
     unsigned refined = 0, nonfinite = 0;
-    TileIn<T, BS, MPL, AOS> cur, nxt;
-    int64_t t = blockIdx.x;
-    if (t < ntiles) load_tile3<T, BS, MPL, AOS>(cur, args.p.in, args.aos, n, t * TILE);
-    for (; t < ntiles; t += gridDim.x) {
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) load_tile3<T, BS, MPL, AOS>(nxt, args.p.in, args.aos, n, tn * TILE);
-        tile_eig3<T, PATH, BS, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * TILE, &sm, refined,
-                                         nonfinite);
+    int qn = 0, qage = 0;
+    WIn<T, MPL, AOS> cur, nxt;
+    const uint32_t stride = gridDim.x * NW;
+    uint32_t t = blockIdx.x * NW + wave_id();
+    if (t < ntiles) load_wtile3<T, MPL, AOS>(cur, args.p.in, args.aos, n, t * WT);
+    for (; t < ntiles; t += stride) {
+        const uint32_t tn = t + stride;
+        if (tn < ntiles) load_wtile3<T, MPL, AOS>(nxt, args.p.in, args.aos, n, tn * WT);
+        wtile_eig3<T, PATH, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
+                                      nonfinite);
         cur = nxt;
     }
-    final_drain<T, PATH, BS, TILE, AOS>(planes_of, &sm, refined);
-    if (args.prm.counters) {
-        if (threadIdx.x == 0 && refined) atomicAdd(&args.prm.counters[0], refined);
-        unsigned s = nonfinite;
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-        if ((threadIdx.x & 63) == 0 && s) atomicAdd(&args.prm.counters[1], s);
-    }
+    if constexpr (QUEUE) final_drain<T, MPL, AOS>(planes_of, my, qn, refined);
+    add_counters(args.prm.counters, refined, nonfinite);
 }
 
 // ------------------------------------------------------------- 2x2 ---------
@@ -597,20 +619,21 @@ template <typename T> struct Eig2Ptrs {
     uint8_t *flags;
 };
 
-template <typename T, int BS, int MPL>
-__device__ __forceinline__ void tile_eig2(const Eig2Ptrs<T> &p, int64_t n, int64_t base) {
-    const int tid = threadIdx.x;
+// One wave tile of 64*MPL 2x2 matrices (§3), straight from and to HBM.
+template <typename T, int MPL>
+__device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uint32_t base) {
+    const int lane = lane_id();
     T A[MPL][3];
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
-        const int64_t i = base + k * BS + tid;
+        const uint32_t off = base + k * WAVE + lane;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) A[k][c] = (i < n) ? p.in[c][i] : T(0);
+        for (int c = 0; c < 3; ++c) A[k][c] = (off < n) ? *elem(p.in[c], off) : T(0);
     }
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
-        const int64_t i = base + k * BS + tid;
-        if (i >= n) continue;
+        const uint32_t off = base + k * WAVE + lane;
+        if (off >= n) continue;
         const bool fin = finite(A[k][0]) && finite(A[k][1]) && finite(A[k][2]);
         // exact power-of-two scaling keeps d^2 + 4 A12^2 in range
         double amax = fmax(fmax(__builtin_fabs((double)A[k][0]), __builtin_fabs((double)A[k][1])),
@@ -624,22 +647,24 @@ __device__ __forceinline__ void tile_eig2(const Eig2Ptrs<T> &p, int64_t n, int64
             const T nan = T(__builtin_nan(""));
             e.l1 = e.l2 = e.c = e.s = e.phi = nan;
         }
-        if (p.lam[0]) p.lam[0][i] = e.l1;
-        if (p.lam[1]) p.lam[1][i] = e.l2;
-        if (p.D[0]) p.D[0][i] = e.c;
-        if (p.D[1]) p.D[1][i] = -e.s;
-        if (p.D[2]) p.D[2][i] = e.s;
-        if (p.D[3]) p.D[3][i] = e.c;
-        if (p.phi) p.phi[i] = e.phi;
-        if (p.flags) p.flags[i] = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
+        if (p.lam[0]) *elem(p.lam[0], off) = e.l1;
+        if (p.lam[1]) *elem(p.lam[1], off) = e.l2;
+        if (p.D[0]) *elem(p.D[0], off) = e.c;
+        if (p.D[1]) *elem(p.D[1], off) = -e.s;
+        if (p.D[2]) *elem(p.D[2], off) = e.s;
+        if (p.D[3]) *elem(p.D[3], off) = e.c;
+        if (p.phi) *elem(p.phi, off) = e.phi;
+        if (p.flags) p.flags[off] = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
     }
 }
 
 template <typename T, int BS, int MPL>
-__global__ __launch_bounds__(BS) void k_eig2(Eig2Ptrs<T> p, int64_t n) {
-    constexpr int TILE = BS * MPL;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_eig2<T, BS, MPL>(p, n, t * TILE);
+__global__ __launch_bounds__(BS) void k_eig2(Eig2Ptrs<T> p, uint32_t n) {
+    constexpr int NW = BS / WAVE, WT = WAVE * MPL;
+    const uint32_t ntiles = (n + WT - 1) / WT;
+    const uint32_t stride = gridDim.x * NW;
+    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += stride)
+        wtile_eig2<T, MPL>(p, n, t * WT);
 }
 
 // -------------------------------------------------------- adjoint ----------
@@ -653,29 +678,29 @@ template <typename T> struct BwdPtrs {
 };
 
 template <typename T, int BS, int MPL>
-__global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, int64_t n, double eps_rel) {
+__global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, uint32_t n, double eps_rel) {
     constexpr int TILE = BS * MPL;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
     const bool has_gap = p.gap[0] && p.gap[1] && p.gap[2];
     const bool has_gl = p.glam[0] != nullptr;
     const bool has_gd = p.gD[0] != nullptr;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
-            const int64_t i = t * TILE + k * BS + threadIdx.x;
+            const uint32_t i = t * TILE + k * BS + threadIdx.x;
             if (i >= n) continue;
             T L[3], D[9], gl[3], gD[9], gA[6];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) L[c] = p.lam[c][i];
+            for (int c = 0; c < 3; ++c) L[c] = *elem(p.lam[c], i);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) D[c] = p.D[c][i];
+            for (int c = 0; c < 9; ++c) D[c] = *elem(p.D[c], i);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) gl[c] = has_gl ? p.glam[c][i] : T(0);
+            for (int c = 0; c < 3; ++c) gl[c] = has_gl ? *elem(p.glam[c], i) : T(0);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) gD[c] = has_gd ? p.gD[c][i] : T(0);
+            for (int c = 0; c < 9; ++c) gD[c] = has_gd ? *elem(p.gD[c], i) : T(0);
             T g12, g13, g32;
             if (has_gap) {
-                g12 = p.gap[0][i]; g13 = p.gap[1][i]; g32 = p.gap[2][i];
+                g12 = *elem(p.gap[0], i); g13 = *elem(p.gap[1], i); g32 = *elem(p.gap[2], i);
             } else {
                 // differences of the stored eigenvalues, exact in float64
                 g12 = (T)((double)L[0] - (double)L[1]);
@@ -685,14 +710,14 @@ __global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, int64_t n, double
             const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
             adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) p.gA[c][i] = gA[c];
+            for (int c = 0; c < 6; ++c) *elem(p.gA[c], i) = gA[c];
         }
     }
 }
 
 // ------------------------------------------------ mixed persistent batch ---
 template <typename T> struct GroupDesc {
-    int64_t n;
+    int64_t n;        // at most KSYM_CHUNK (the host splits larger groups)
     int32_t kind;
     int32_t pad;
     Eig3Ptrs<T> p3;   // kind 2 uses in[0..2] and out[O_LAM..+1], out[O_D..+3], out[O_PHI], flags
@@ -700,35 +725,41 @@ template <typename T> struct GroupDesc {
 
 template <typename T> struct MixedArgs {
     const GroupDesc<T> *groups;
-    const int64_t *tile_begin;   // ngroups + 1 prefix sums of tiles
+    const int64_t *tile_begin;   // ngroups + 1 prefix sums of wave tiles
     int32_t ngroups;
     int64_t ntiles;
     Eig3Params prm;              // thresholds and counters (prm.n unused)
 };
 
+// One persistent launch over all groups: wave tile t belongs to the last group
+// g with tile_begin[g] <= t (a tile never spans two groups, so a wave runs one
+// kind at a time); 3x3 groups share the wave's refinement queue.
 template <typename T, int BS, int MPL>
-__global__ __launch_bounds__(BS) void k_mixed(MixedArgs<T> a) {
-    constexpr int TILE = BS * MPL;
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1) ? 5 : 1)))
+void k_mixed(MixedArgs<T> a) {
+    constexpr int NW = BS / WAVE;
+    constexpr int WT = WAVE * MPL;
     constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
-    __shared__ Smem3<T, BS, TILE, true, false> sm;
-    if (threadIdx.x == 0) sm.q.n = 0;
-    __syncthreads();
+    __shared__ WaveSmem<T, MPL, true, false> sm[NW];
+    WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
     auto planes_of = [&](int g) { return TablePlanes<T>{&a.groups[g].p3}; };
     unsigned refined = 0, nonfinite = 0;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        // binary search: last g with tile_begin[g] <= t (block-uniform)
+    int qn = 0, qage = 0;
+    const int64_t stride = (int64_t)gridDim.x * NW;
+    for (int64_t t = (int64_t)blockIdx.x * NW + wave_id(); t < a.ntiles; t += stride) {
         int lo = 0, hi = a.ngroups - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (a.tile_begin[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const GroupDesc<T> &g = a.groups[lo];
-        const int64_t base = (t - a.tile_begin[lo]) * TILE;
+        const uint32_t n = (uint32_t)g.n;
+        const uint32_t base = (uint32_t)(t - a.tile_begin[lo]) * WT;
         if (g.kind == 3) {
-            TileIn<T, BS, MPL, false> in;
-            load_tile3<T, BS, MPL, false>(in, g.p3.in, nullptr, g.n, base);
-            tile_eig3<T, PATH, BS, MPL, false>(planes_of(lo), planes_of, lo, a.prm, in, g.n, base, &sm,
-                                               refined, nonfinite);
+            WIn<T, MPL, false> in;
+            load_wtile3<T, MPL, false>(in, g.p3.in, nullptr, n, base);
+            wtile_eig3<T, PATH, MPL, false>(planes_of(lo), planes_of, lo, a.prm, in, n, base, my, qn,
+                                            qage, refined, nonfinite);
         } else {
             Eig2Ptrs<T> p2;
             for (int c = 0; c < 3; ++c) p2.in[c] = g.p3.in[c];
@@ -736,16 +767,11 @@ __global__ __launch_bounds__(BS) void k_mixed(MixedArgs<T> a) {
             for (int c = 0; c < 4; ++c) p2.D[c] = g.p3.out[O_D + c];
             p2.phi = g.p3.out[O_PHI];
             p2.flags = g.p3.flags;
-            tile_eig2<T, BS, MPL>(p2, g.n, base);
+            wtile_eig2<T, MPL>(p2, n, base);
         }
     }
-    final_drain<T, PATH, BS, TILE, false>(planes_of, &sm, refined);
-    if (a.prm.counters) {
-        if (threadIdx.x == 0 && refined) atomicAdd(&a.prm.counters[0], refined);
-        unsigned s = nonfinite;
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-        if ((threadIdx.x & 63) == 0 && s) atomicAdd(&a.prm.counters[1], s);
-    }
+    final_drain<T, MPL, false>(planes_of, my, qn, refined);
+    add_counters(a.prm.counters, refined, nonfinite);
 }
 
 __global__ void k_zero_u32(unsigned *p, int n) {

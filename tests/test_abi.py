@@ -52,7 +52,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("mats_per_lane", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
                 ("tau_gap", ctypes.c_double), ("tau_res", ctypes.c_double),
-                ("tau_vec", ctypes.c_double), ("tau_dbl", ctypes.c_double)]
+                ("tau_vec", ctypes.c_double), ("tau_dbl", ctypes.c_double),
+                ("drain_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _err(lib):
@@ -65,6 +66,7 @@ def test_defaults(lib):
     lib.ksym_opts_default(0, ctypes.byref(o))
     assert o.path == 0 and o.block == 256 and o.mats_per_lane in (1, 2, 4)
     assert 0 < o.tau_res < 1e-5
+    assert o.drain_tiles >= 0 and o.reserved == 0
     lib.ksym_opts_default(1, ctypes.byref(o))
     assert o.path == 2 and 0 < o.tau_res < 1e-9
 
@@ -105,7 +107,8 @@ def test_eig3_argument_errors(lib):
     o.path = 0
     assert f(1, 10, ok, None, None, None, None, None, None, 0, ctypes.byref(o), None) == 2
     # launch-shape options
-    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 65)):
+    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 65),
+                       ("drain_tiles", (1 << 20) + 1)):
         lib.ksym_opts_default(0, ctypes.byref(o))
         setattr(o, field, bad)
         assert f(0, 10, ok, None, None, None, None, None, None, 0, ctypes.byref(o), None) == 1, field

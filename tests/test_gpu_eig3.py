@@ -149,7 +149,7 @@ def test_f32_launch_shapes_bitwise(ksym):
     again = _run(ksym, P32, torch.float32)
     for k in ("lam", "D", "phi", "gap", "flags"):
         assert np.array_equal(base[k], again[k], equal_nan=True), k
-    for block, mpl in ((64, 1), (64, 4), (128, 2), (256, 1), (256, 2), (256, 4), (512, 1), (512, 2)):
+    for block, mpl in ((64, 1), (64, 2), (128, 1), (128, 2), (256, 1), (256, 2), (512, 1), (512, 2)):
         for gm in (1, 16):
             g = _run(ksym, P32, torch.float32, block=block, mats_per_lane=mpl, grid_mult=gm)
             for k in ("lam", "D", "phi", "gap", "flags"):
@@ -192,7 +192,7 @@ def test_all_matrices_refined_f32(ksym):
     P32 = synth._sandwich(Q, np.stack([a, a, c], 1)).astype(np.float32)
     P64 = P32.astype(np.float64)
     lam_ref, V_ref = certified_reference(P64)
-    for block, mpl in ((64, 1), (256, 4), (512, 2)):
+    for block, mpl in ((64, 1), (256, 2), (512, 2)):
         g = _run(ksym, P32, torch.float32, block=block, mats_per_lane=mpl, tau_gap=1.0)
         assert np.all(g["flags"] & 4)
         check_f32_result(P64, g, lam_ref, V_ref, f"all-refined {block}x{mpl}")
@@ -211,7 +211,7 @@ def test_aos_matches_soa(ksym):
     P32 = synth.make_precision(70001, seed=99)
     soa = _run(ksym, P32, torch.float32)
     rec = to_dev(np.ascontiguousarray(P32.T), torch.float32)
-    for block, mpl in ((64, 1), (128, 2), (256, 1), (256, 2), (512, 1)):
+    for block, mpl in ((64, 1), (128, 1), (256, 1), (256, 2), (512, 1)):
         o = ksym.Opts.defaults(ksym.F32, block=block, mats_per_lane=mpl)
         out = ksym.eig3_aos(rec, opts=o, outputs=("lam", "D", "phi", "gap", "flags"))
         torch.cuda.synchronize()
