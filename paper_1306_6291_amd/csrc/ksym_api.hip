@@ -271,7 +271,7 @@ struct ksym_plan {
     int64_t ntiles;
     int grid;
     void *d_groups;
-    int64_t *d_tiles;
+    TileInfo *d_tiles;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -543,13 +543,26 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
     p->grid = (int)grid;
-    const size_t tb_bytes = tb.size() * sizeof(int64_t);
+    // one (descriptor, first-matrix offset) entry per wave tile
+    std::vector<TileInfo> ti;
+    try {
+        ti.resize((size_t)p->ntiles);
+    } catch (...) {
+        delete p;
+        return fail(KSYM_E_ARG, "out of host memory for the tile table");
+    }
+    for (int64_t d = 0; d < ndesc; ++d)
+        for (int64_t t = tb[d]; t < tb[d + 1]; ++t) {
+            ti[t].group = (int32_t)d;
+            ti[t].base = (uint32_t)((t - tb[d]) * tile);
+        }
+    const size_t tb_bytes = ti.size() * sizeof(TileInfo);
     const size_t total = desc.size() + 256 + tb_bytes;
     hipError_t e = hipMalloc(&p->d_groups, total);
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc plan descriptors"); }
-    p->d_tiles = (int64_t *)((char *)p->d_groups + ((desc.size() + 255) / 256) * 256);
+    p->d_tiles = (TileInfo *)((char *)p->d_groups + ((desc.size() + 255) / 256) * 256);
     e = hipMemcpy(p->d_groups, desc.data(), desc.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tb.data(), tb_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && tb_bytes) e = hipMemcpy(p->d_tiles, ti.data(), tb_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->d_groups);
         delete p;
@@ -574,7 +587,7 @@ ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
         MixedArgs<T> a;
         memset(&a, 0, sizeof a);
         a.groups = (const GroupDesc<T> *)p->d_groups;
-        a.tile_begin = p->d_tiles;
+        a.tiles = p->d_tiles;
         a.ngroups = p->ngroups;
         a.ntiles = p->ntiles;
         a.prm.n = 0;

@@ -301,10 +301,19 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-// Element `off` of plane p through a 32-bit byte offset (off < KSYM_CHUNK).
-template <typename T> __device__ __forceinline__ T *elem(T *p, uint32_t off) {
-    return (T *)((char *)p + off * (uint32_t)sizeof(T));
+// Element `off` of plane p through a 32-bit byte offset (off < KSYM_CHUNK),
+// as a global-memory pointer: every plane is device memory, and saying so
+// gives global_load / global_store with a scalar base instead of flat
+// accesses when the plane pointer itself was read from memory.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> elem(T *p, uint32_t off) {
+    return (gptr<T>)((char *)p + off * (uint32_t)sizeof(T));
 }
+// Read-only tables (mixed-batch descriptors and tile entries) in the constant
+// address space: they do not change while a kernel runs, so uniform reads
+// become scalar loads even though the kernel stores to global memory.
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
 
 // Output plane pointers read from the kernel-argument segment with a
 // plane-dependent offset: the pointers are fetched (a few scalar loads) where a
@@ -326,7 +335,7 @@ template <typename T> struct KernargPlanes {
 
 // Output plane pointers of a group descriptor in device memory.
 template <typename T> struct TablePlanes {
-    const Eig3Ptrs<T> *p;
+    cptr<Eig3Ptrs<T>> p;
     __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
     __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
 };
@@ -344,7 +353,7 @@ __device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, c
 #pragma unroll
     for (int k = 0; k < NOUT3; ++k)
         if (dst[k]) *elem(dst[k], off) = o.v[k];
-    if (fl) fl[off] = (uint8_t)o.flag;
+    if (fl) *elem(fl, off) = (uint8_t)o.flag;
 }
 
 // Stores of one lane's matrix as its outputs are produced (float32 path).
@@ -359,7 +368,7 @@ template <typename T, typename Planes> struct LaneSink {
     }
     __device__ __forceinline__ void flag(int f) const {
         uint8_t *fl = pl.flags(salt);
-        if (valid && fl) fl[off] = (uint8_t)f;
+        if (valid && fl) *elem(fl, off) = (uint8_t)f;
     }
 };
 
@@ -372,7 +381,7 @@ __device__ __forceinline__ void write_out3(const Planes &pl, uint32_t off, const
         if (dst) *elem(dst, off) = o.v[k];
     }
     uint8_t *fl = pl.flags();
-    if (fl) fl[off] = (uint8_t)o.flag;
+    if (fl) *elem(fl, off) = (uint8_t)o.flag;
 }
 
 // One wave's refinement queue: CAP = 64 * (MPL + 1) entries, enough for a
@@ -414,13 +423,10 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const
             const uint32_t j = u * WAVE + lane;
             const uint32_t e0 = j * VEC;
             if (j < (uint32_t)W::NV && e0 + VEC <= lim) {
-                if constexpr (sizeof(T) == 4) {
-                    const float4 x = *reinterpret_cast<const float4 *>(elem(src, e0));
-                    in.v[u][0] = x.x; in.v[u][1] = x.y; in.v[u][2] = x.z; in.v[u][3] = x.w;
-                } else {
-                    const double2 x = *reinterpret_cast<const double2 *>(elem(src, e0));
-                    in.v[u][0] = x.x; in.v[u][1] = x.y;
-                }
+                typedef T vec_t __attribute__((ext_vector_type(VEC)));
+                const vec_t x = *reinterpret_cast<gptr<const vec_t>>(elem(src, e0));
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) in.v[u][t] = x[t];
             } else {
 #pragma unroll
                 for (int t = 0; t < VEC; ++t)
@@ -619,7 +625,32 @@ template <typename T> struct Eig2Ptrs {
     uint8_t *flags;
 };
 
-// One wave tile of 64*MPL 2x2 matrices (§3), straight from and to HBM.
+// One 2x2 matrix (§3) and its stores; out = lam1, lam2, D11, D12, D21, D22,
+// phi (any may be null).
+template <typename T>
+__device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], uint8_t *flags,
+                                          uint32_t off) {
+    const bool fin = finite(a11) && finite(a22) && finite(a12);
+    // exact power-of-two scaling keeps d^2 + 4 A12^2 in range
+    const double amax = fmax(fmax(__builtin_fabs((double)a11), __builtin_fabs((double)a22)),
+                             __builtin_fabs((double)a12));
+    const int ex = fin ? scale_exponent(amax) : 0;
+    const T sc = (T)pow2(-ex), isc = (T)pow2(ex);
+    Eig2<T> e = eig2_one<T>(a11 * sc, a22 * sc, a12 * sc);
+    e.l1 *= isc;
+    e.l2 *= isc;
+    if (!fin) {
+        const T nan = T(__builtin_nan(""));
+        e.l1 = e.l2 = e.c = e.s = e.phi = nan;
+    }
+    const T v[7] = {e.l1, e.l2, e.c, -e.s, e.s, e.c, e.phi};
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        if (out[k]) *elem(out[k], off) = v[k];
+    if (flags) *elem(flags, off) = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
+}
+
+// One wave tile of 64*MPL 2x2 matrices, straight from and to HBM.
 template <typename T, int MPL>
 __device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uint32_t base) {
     const int lane = lane_id();
@@ -630,31 +661,11 @@ __device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uin
 #pragma unroll
         for (int c = 0; c < 3; ++c) A[k][c] = (off < n) ? *elem(p.in[c], off) : T(0);
     }
+    T *const out[7] = {p.lam[0], p.lam[1], p.D[0], p.D[1], p.D[2], p.D[3], p.phi};
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
-        if (off >= n) continue;
-        const bool fin = finite(A[k][0]) && finite(A[k][1]) && finite(A[k][2]);
-        // exact power-of-two scaling keeps d^2 + 4 A12^2 in range
-        double amax = fmax(fmax(__builtin_fabs((double)A[k][0]), __builtin_fabs((double)A[k][1])),
-                           __builtin_fabs((double)A[k][2]));
-        const int ex = fin ? scale_exponent(amax) : 0;
-        const T sc = (T)pow2(-ex), isc = (T)pow2(ex);
-        Eig2<T> e = eig2_one<T>(A[k][0] * sc, A[k][1] * sc, A[k][2] * sc);
-        e.l1 *= isc;
-        e.l2 *= isc;
-        if (!fin) {
-            const T nan = T(__builtin_nan(""));
-            e.l1 = e.l2 = e.c = e.s = e.phi = nan;
-        }
-        if (p.lam[0]) *elem(p.lam[0], off) = e.l1;
-        if (p.lam[1]) *elem(p.lam[1], off) = e.l2;
-        if (p.D[0]) *elem(p.D[0], off) = e.c;
-        if (p.D[1]) *elem(p.D[1], off) = -e.s;
-        if (p.D[2]) *elem(p.D[2], off) = e.s;
-        if (p.D[3]) *elem(p.D[3], off) = e.c;
-        if (p.phi) *elem(p.phi, off) = e.phi;
-        if (p.flags) p.flags[off] = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
+        if (off < n) eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, off);
     }
 }
 
@@ -723,52 +734,104 @@ template <typename T> struct GroupDesc {
     Eig3Ptrs<T> p3;   // kind 2 uses in[0..2] and out[O_LAM..+1], out[O_D..+3], out[O_PHI], flags
 };
 
+// Where a wave tile of a mixed batch lives: its group descriptor and the
+// offset of its first matrix inside the group.
+struct TileInfo {
+    int32_t group;
+    uint32_t base;
+};
+
+__device__ __forceinline__ TileInfo tile_at(cptr<TileInfo> tiles, int64_t t) {
+    TileInfo r;
+    r.group = tiles[t].group;
+    r.base = tiles[t].base;
+    return r;
+}
+
 template <typename T> struct MixedArgs {
     const GroupDesc<T> *groups;
-    const int64_t *tile_begin;   // ngroups + 1 prefix sums of wave tiles
+    const TileInfo *tiles;       // one entry per wave tile, in group order
     int32_t ngroups;
     int64_t ntiles;
     Eig3Params prm;              // thresholds and counters (prm.n unused)
 };
 
-// One persistent launch over all groups: wave tile t belongs to the last group
-// g with tile_begin[g] <= t (a tile never spans two groups, so a wave runs one
-// kind at a time); 3x3 groups share the wave's refinement queue.
+// Inputs of one mixed-batch wave tile (the 2x2 kind uses planes 0..2; the
+// other slots are zero).  One loop for both kinds keeps the tile in registers.
+template <typename T, int MPL>
+__device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, const __attribute__((address_space(4))) GroupDesc<T> &g,
+                                           uint32_t base) {
+    const uint32_t n = (uint32_t)g.n;
+    const int np = g.kind == 3 ? 6 : 3;
+    const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const T *pc = g.p3.in[c];
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) {
+            const uint32_t off = base + k * WAVE + lane;
+            in.a[k][c] = (c < np && off < n) ? *elem(pc, off) : T(0);
+        }
+    }
+}
+
+// One 2x2 wave tile of a mixed batch from inputs already in registers.
+template <typename T, int MPL>
+__device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space(4))) GroupDesc<T> &g,
+                                              const WIn<T, MPL, false> &in,
+                                              uint32_t base) {
+    const uint32_t n = (uint32_t)g.n;
+    const int lane = lane_id();
+    T *const out[7] = {g.p3.out[O_LAM], g.p3.out[O_LAM + 1], g.p3.out[O_D], g.p3.out[O_D + 1],
+                       g.p3.out[O_D + 2], g.p3.out[O_D + 3], g.p3.out[O_PHI]};
+#pragma unroll
+    for (int k = 0; k < MPL; ++k) {
+        const uint32_t off = base + k * WAVE + lane;
+        if (off < n) eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, off);
+    }
+}
+
+// One persistent launch over all groups.  Wave tile t is described by
+// tiles[t] (a tile never spans two groups, so a wave runs one kind at a
+// time); the wave reads the descriptor of tile t + 2*stride and the inputs of
+// tile t + stride while it computes tile t.  3x3 groups share the wave's
+// refinement queue.
 template <typename T, int BS, int MPL>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1) ? 5 : 1)))
 void k_mixed(MixedArgs<T> a) {
     constexpr int NW = BS / WAVE;
-    constexpr int WT = WAVE * MPL;
     constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
     WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
-    auto planes_of = [&](int g) { return TablePlanes<T>{&a.groups[g].p3}; };
+    const cptr<GroupDesc<T>> groups = as_const(a.groups);
+    const cptr<TileInfo> tiles = as_const(a.tiles);
+    auto planes_of = [&](int g) { return TablePlanes<T>{&groups[g].p3}; };
     unsigned refined = 0, nonfinite = 0;
     int qn = 0, qage = 0;
     const int64_t stride = (int64_t)gridDim.x * NW;
-    for (int64_t t = (int64_t)blockIdx.x * NW + wave_id(); t < a.ntiles; t += stride) {
-        int lo = 0, hi = a.ngroups - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.tile_begin[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-        const GroupDesc<T> &g = a.groups[lo];
-        const uint32_t n = (uint32_t)g.n;
-        const uint32_t base = (uint32_t)(t - a.tile_begin[lo]) * WT;
+    int64_t t = (int64_t)blockIdx.x * NW + wave_id();
+    TileInfo cur = {0, 0}, nxt = {0, 0};
+    WIn<T, MPL, false> in_cur, in_nxt;
+    if (t < a.ntiles) {
+        cur = tile_at(tiles, t);
+        load_mixed<T, MPL>(in_cur, groups[cur.group], cur.base);
+    }
+    if (t + stride < a.ntiles) nxt = tile_at(tiles, t + stride);
+    for (; t < a.ntiles; t += stride) {
+        const bool has_next = t + stride < a.ntiles;
+        TileInfo nxt2 = {0, 0};
+        if (t + 2 * stride < a.ntiles) nxt2 = tile_at(tiles, t + 2 * stride);
+        if (has_next) load_mixed<T, MPL>(in_nxt, groups[nxt.group], nxt.base);
+        const auto &g = groups[cur.group];
         if (g.kind == 3) {
-            WIn<T, MPL, false> in;
-            load_wtile3<T, MPL, false>(in, g.p3.in, nullptr, n, base);
-            wtile_eig3<T, PATH, MPL, false>(planes_of(lo), planes_of, lo, a.prm, in, n, base, my, qn,
-                                            qage, refined, nonfinite);
+            wtile_eig3<T, PATH, MPL, false>(planes_of(cur.group), planes_of, cur.group, a.prm, in_cur,
+                                            (uint32_t)g.n, cur.base, my, qn, qage, refined, nonfinite);
         } else {
-            Eig2Ptrs<T> p2;
-            for (int c = 0; c < 3; ++c) p2.in[c] = g.p3.in[c];
-            p2.lam[0] = g.p3.out[O_LAM]; p2.lam[1] = g.p3.out[O_LAM + 1];
-            for (int c = 0; c < 4; ++c) p2.D[c] = g.p3.out[O_D + c];
-            p2.phi = g.p3.out[O_PHI];
-            p2.flags = g.p3.flags;
-            wtile_eig2<T, MPL>(p2, n, base);
+            wtile_eig2_in<T, MPL>(g, in_cur, cur.base);
         }
+        cur = nxt;
+        nxt = nxt2;
+        in_cur = in_nxt;
     }
     final_drain<T, MPL, false>(planes_of, my, qn, refined);
     add_counters(a.prm.counters, refined, nonfinite);
