@@ -287,7 +287,13 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
 // ------------------------------------------------------ per-wave tiles -----
 constexpr int WAVE = 64;
 
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+// The lane index, recomputed where it is used (two mbcnt) rather than kept in
+// a register across the tile loop: under the 96-register budget the compiler
+// would otherwise spill it and reload it (with a full memory wait) per tile.
+__device__ __forceinline__ uint32_t fresh(uint32_t x);
+__device__ __forceinline__ int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, fresh(0u)));
+}
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
 }
@@ -307,11 +313,19 @@ __device__ __forceinline__ void wave_sync() {
 // accesses when the plane pointer itself was read from memory.
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr<T> elem(T *p, uint32_t off) {
-    return (gptr<T>)((char *)p + off * (uint32_t)sizeof(T));
+    return (gptr<T>)((gptr<char>)p + off * (uint32_t)sizeof(T));
 }
 // Read-only tables (mixed-batch descriptors and tile entries) in the constant
 // address space: they do not change while a kernel runs, so uniform reads
 // become scalar loads even though the kernel stores to global memory.
+// The value x, opaque to the optimizer (no instruction is emitted).  Used on
+// the 32-bit offset of an access inside a conditional block, so the offset is
+// extended to 64 bits in that block and the access can take the scalar-base
+// plus 32-bit-offset form instead of a 64-bit per-lane address.
+__device__ __forceinline__ uint32_t fresh(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
 
@@ -352,23 +366,24 @@ __device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, c
     uint8_t *fl = pl.flags(salt);
 #pragma unroll
     for (int k = 0; k < NOUT3; ++k)
-        if (dst[k]) *elem(dst[k], off) = o.v[k];
-    if (fl) *elem(fl, off) = (uint8_t)o.flag;
+        if (dst[k]) *elem(dst[k], fresh(off)) = o.v[k];
+    if (fl) *elem(fl, fresh(off)) = (uint8_t)o.flag;
 }
 
 // Stores of one lane's matrix as its outputs are produced (float32 path).
-template <typename T, typename Planes> struct LaneSink {
+// FULL: every lane of the tile holds a matrix (no per-lane bounds test).
+template <typename T, typename Planes, bool FULL> struct LaneSink {
     const Planes &pl;
     int salt;
     uint32_t off;
     bool valid;
     __device__ __forceinline__ void put(int k, T v) const {
         T *d = pl.out(k + salt);
-        if (valid && d) *elem(d, off) = v;
+        if ((FULL || valid) && d) *elem(d, fresh(off)) = v;
     }
     __device__ __forceinline__ void flag(int f) const {
         uint8_t *fl = pl.flags(salt);
-        if (valid && fl) *elem(fl, off) = (uint8_t)f;
+        if ((FULL || valid) && fl) *elem(fl, fresh(off)) = (uint8_t)f;
     }
 };
 
@@ -378,10 +393,10 @@ __device__ __forceinline__ void write_out3(const Planes &pl, uint32_t off, const
 #pragma unroll
     for (int k = 0; k < NOUT3; ++k) {
         T *dst = pl.out(k);
-        if (dst) *elem(dst, off) = o.v[k];
+        if (dst) *elem(dst, fresh(off)) = o.v[k];
     }
     uint8_t *fl = pl.flags();
-    if (fl) *elem(fl, off) = (uint8_t)o.flag;
+    if (fl) *elem(fl, fresh(off)) = (uint8_t)o.flag;
 }
 
 // One wave's refinement queue: CAP = 64 * (MPL + 1) entries, enough for a
@@ -409,7 +424,9 @@ template <typename T, int MPL, bool AOS> struct WIn {
     T v[AOS ? NVL : 1][AOS ? VEC : 1];
 };
 
-template <typename T, int MPL, bool AOS>
+// FULL: the whole tile lies below n (unconditional loads).  Otherwise lanes
+// past n load the last matrix (a clamped, in-bounds offset) and take zeros.
+template <typename T, int MPL, bool AOS, bool FULL>
 __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const *planes,
                                             const T *aos, uint32_t n, uint32_t base) {
     const int lane = lane_id();
@@ -437,8 +454,13 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const uint32_t off = base + k * WAVE + lane;
+            const bool ok = FULL || off < n;
+            const uint32_t offc = ok ? off : n - 1;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) in.a[k][c] = (off < n) ? *elem(planes[c], off) : T(0);
+            for (int c = 0; c < 6; ++c) {
+                const T v = *elem(planes[c], offc);
+                in.a[k][c] = ok ? v : T(0);
+            }
         }
     }
 }
@@ -464,7 +486,7 @@ __device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const 
 // Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
 // already in registers: compute, store, queue the matrices that need the
 // refinement, and drain the queue in rounds of 64.  Wave-uniform control flow.
-template <typename T, int PATH, int MPL, bool AOS, typename Planes, typename PlanesOf>
+template <typename T, int PATH, int MPL, bool AOS, bool FULL, typename Planes, typename PlanesOf>
 __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
                                            const Eig3Params &prm, const WIn<T, MPL, AOS> &in,
                                            uint32_t n, uint32_t base,
@@ -488,7 +510,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
     for (int k = 0; k < MPL; ++k) {
         const int slot = k * WAVE + lane;
         const uint32_t off = base + slot;
-        const bool valid = off < n;
+        const bool valid = FULL || off < n;
         T A[6];
         if constexpr (AOS) {
 #pragma unroll
@@ -502,7 +524,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         bool refine;
         double lc;
         if constexpr (PATH == PATH_FP32_FIXUP) {
-            flag = eig3_f32(A, prm, LaneSink<T, Planes>{pl, salt, off, valid}, refine, lc);
+            flag = eig3_f32(A, prm, LaneSink<T, Planes, FULL>{pl, salt, off, valid}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T, PATH>(A, prm, o);
@@ -604,12 +626,21 @@ void k_eig3(Eig3Args<T> args) {
     WIn<T, MPL, AOS> cur, nxt;
     const uint32_t stride = gridDim.x * NW;
     uint32_t t = blockIdx.x * NW + wave_id();
-    if (t < ntiles) load_wtile3<T, MPL, AOS>(cur, args.p.in, args.aos, n, t * WT);
+    const uint32_t nfull = n / WT;   // tiles with no lane past n
+    auto load = [&](WIn<T, MPL, AOS> &w, uint32_t tt) {
+        if (tt < nfull) load_wtile3<T, MPL, AOS, true>(w, args.p.in, args.aos, n, tt * WT);
+        else load_wtile3<T, MPL, AOS, false>(w, args.p.in, args.aos, n, tt * WT);
+    };
+    if (t < ntiles) load(cur, t);
     for (; t < ntiles; t += stride) {
         const uint32_t tn = t + stride;
-        if (tn < ntiles) load_wtile3<T, MPL, AOS>(nxt, args.p.in, args.aos, n, tn * WT);
-        wtile_eig3<T, PATH, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
-                                      nonfinite);
+        if (tn < ntiles) load(nxt, tn);
+        if (t < nfull)
+            wtile_eig3<T, PATH, MPL, AOS, true>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage,
+                                                refined, nonfinite);
+        else
+            wtile_eig3<T, PATH, MPL, AOS, false>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage,
+                                                 refined, nonfinite);
         cur = nxt;
     }
     if constexpr (QUEUE) final_drain<T, MPL, AOS>(planes_of, my, qn, refined);
@@ -646,26 +677,31 @@ __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], 
     const T v[7] = {e.l1, e.l2, e.c, -e.s, e.s, e.c, e.phi};
 #pragma unroll
     for (int k = 0; k < 7; ++k)
-        if (out[k]) *elem(out[k], off) = v[k];
-    if (flags) *elem(flags, off) = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
+        if (out[k]) *elem(out[k], fresh(off)) = v[k];
+    if (flags) *elem(flags, fresh(off)) = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
 }
 
 // One wave tile of 64*MPL 2x2 matrices, straight from and to HBM.
-template <typename T, int MPL>
+template <typename T, int MPL, bool FULL>
 __device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uint32_t base) {
     const int lane = lane_id();
     T A[MPL][3];
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
+        const bool ok = FULL || off < n;
+        const uint32_t offc = ok ? off : n - 1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) A[k][c] = (off < n) ? *elem(p.in[c], off) : T(0);
+        for (int c = 0; c < 3; ++c) {
+            const T v = *elem(p.in[c], offc);
+            A[k][c] = ok ? v : T(0);
+        }
     }
     T *const out[7] = {p.lam[0], p.lam[1], p.D[0], p.D[1], p.D[2], p.D[3], p.phi};
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
-        if (off < n) eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, off);
+        if (FULL || off < n) eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, off);
     }
 }
 
@@ -674,8 +710,11 @@ __global__ __launch_bounds__(BS) void k_eig2(Eig2Ptrs<T> p, uint32_t n) {
     constexpr int NW = BS / WAVE, WT = WAVE * MPL;
     const uint32_t ntiles = (n + WT - 1) / WT;
     const uint32_t stride = gridDim.x * NW;
-    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += stride)
-        wtile_eig2<T, MPL>(p, n, t * WT);
+    const uint32_t nfull = n / WT;
+    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += stride) {
+        if (t < nfull) wtile_eig2<T, MPL, true>(p, n, t * WT);
+        else wtile_eig2<T, MPL, false>(p, n, t * WT);
+    }
 }
 
 // -------------------------------------------------------- adjoint ----------
@@ -688,10 +727,46 @@ template <typename T> struct BwdPtrs {
     T *gA[6];
 };
 
+// One lane's adjoint.  FULL: i < n is known; otherwise lanes past n read the
+// last matrix (in bounds) and store nothing.
+template <typename T, bool FULL>
+__device__ __forceinline__ void bwd_lane(const BwdPtrs<T> &p, bool has_gap, bool has_gl, bool has_gd,
+                                         uint32_t i, uint32_t n, double eps_rel) {
+    const bool ok = FULL || i < n;
+    const uint32_t ic = ok ? i : n - 1;
+    T L[3], D[9], gl[3], gD[9], gA[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L[c] = *elem(p.lam[c], ic);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) D[c] = *elem(p.D[c], ic);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gl[c] = has_gl ? *elem(p.glam[c], fresh(ic)) : T(0);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gD[c] = has_gd ? *elem(p.gD[c], fresh(ic)) : T(0);
+    T g12, g13, g32;
+    if (has_gap) {
+        const uint32_t o = fresh(ic);
+        g12 = *elem(p.gap[0], o); g13 = *elem(p.gap[1], o); g32 = *elem(p.gap[2], o);
+    } else {
+        // differences of the stored eigenvalues, exact in float64
+        g12 = (T)((double)L[0] - (double)L[1]);
+        g13 = (T)((double)L[0] - (double)L[2]);
+        g32 = (T)((double)L[2] - (double)L[1]);
+    }
+    const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+    adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
+    if (ok) {
+        const uint32_t o = fresh(i);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) *elem(p.gA[c], o) = gA[c];
+    }
+}
+
 template <typename T, int BS, int MPL>
 __global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, uint32_t n, double eps_rel) {
     constexpr int TILE = BS * MPL;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
+    const uint32_t nfull = n / TILE;
     const bool has_gap = p.gap[0] && p.gap[1] && p.gap[2];
     const bool has_gl = p.glam[0] != nullptr;
     const bool has_gd = p.gD[0] != nullptr;
@@ -699,29 +774,8 @@ __global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, uint32_t n, doubl
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const uint32_t i = t * TILE + k * BS + threadIdx.x;
-            if (i >= n) continue;
-            T L[3], D[9], gl[3], gD[9], gA[6];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) L[c] = *elem(p.lam[c], i);
-#pragma unroll
-            for (int c = 0; c < 9; ++c) D[c] = *elem(p.D[c], i);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gl[c] = has_gl ? *elem(p.glam[c], i) : T(0);
-#pragma unroll
-            for (int c = 0; c < 9; ++c) gD[c] = has_gd ? *elem(p.gD[c], i) : T(0);
-            T g12, g13, g32;
-            if (has_gap) {
-                g12 = *elem(p.gap[0], i); g13 = *elem(p.gap[1], i); g32 = *elem(p.gap[2], i);
-            } else {
-                // differences of the stored eigenvalues, exact in float64
-                g12 = (T)((double)L[0] - (double)L[1]);
-                g13 = (T)((double)L[0] - (double)L[2]);
-                g32 = (T)((double)L[2] - (double)L[1]);
-            }
-            const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
-            adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
-#pragma unroll
-            for (int c = 0; c < 6; ++c) *elem(p.gA[c], i) = gA[c];
+            if (t < nfull) bwd_lane<T, true>(p, has_gap, has_gl, has_gd, i, n, eps_rel);
+            else bwd_lane<T, false>(p, has_gap, has_gl, has_gd, i, n, eps_rel);
         }
     }
 }
@@ -757,7 +811,8 @@ template <typename T> struct MixedArgs {
 };
 
 // Inputs of one mixed-batch wave tile (the 2x2 kind uses planes 0..2; the
-// other slots are zero).  One loop for both kinds keeps the tile in registers.
+// other slots are zero).  One loop for both kinds keeps the tile in registers;
+// lanes past n read the group's last matrix (in bounds) and take zeros.
 template <typename T, int MPL>
 __device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, const __attribute__((address_space(4))) GroupDesc<T> &g,
                                            uint32_t base) {
@@ -770,13 +825,17 @@ __device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, const __attri
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const uint32_t off = base + k * WAVE + lane;
-            in.a[k][c] = (c < np && off < n) ? *elem(pc, off) : T(0);
+            const bool ok = off < n;
+            const uint32_t offc = ok ? off : n - 1;
+            T v = T(0);
+            if (c < np) v = *elem(pc, fresh(offc));
+            in.a[k][c] = ok ? v : T(0);
         }
     }
 }
 
 // One 2x2 wave tile of a mixed batch from inputs already in registers.
-template <typename T, int MPL>
+template <typename T, int MPL, bool FULL>
 __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space(4))) GroupDesc<T> &g,
                                               const WIn<T, MPL, false> &in,
                                               uint32_t base) {
@@ -787,7 +846,7 @@ __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
-        if (off < n) eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, off);
+        if (FULL || off < n) eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, off);
     }
 }
 
@@ -823,11 +882,18 @@ void k_mixed(MixedArgs<T> a) {
         if (t + 2 * stride < a.ntiles) nxt2 = tile_at(tiles, t + 2 * stride);
         if (has_next) load_mixed<T, MPL>(in_nxt, groups[nxt.group], nxt.base);
         const auto &g = groups[cur.group];
+        const uint32_t n = (uint32_t)g.n;
+        const bool full = cur.base + WAVE * MPL <= n;
         if (g.kind == 3) {
-            wtile_eig3<T, PATH, MPL, false>(planes_of(cur.group), planes_of, cur.group, a.prm, in_cur,
-                                            (uint32_t)g.n, cur.base, my, qn, qage, refined, nonfinite);
+            if (full)
+                wtile_eig3<T, PATH, MPL, false, true>(planes_of(cur.group), planes_of, cur.group, a.prm,
+                                                      in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
+            else
+                wtile_eig3<T, PATH, MPL, false, false>(planes_of(cur.group), planes_of, cur.group, a.prm,
+                                                       in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
         } else {
-            wtile_eig2_in<T, MPL>(g, in_cur, cur.base);
+            if (full) wtile_eig2_in<T, MPL, true>(g, in_cur, cur.base);
+            else wtile_eig2_in<T, MPL, false>(g, in_cur, cur.base);
         }
         cur = nxt;
         nxt = nxt2;
