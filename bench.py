@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TLANE = 256 * 64 * 2.4e9 / 1e12   # 39.3 T lane-instructions/s
 BYTES_3X3_F32 = 84      # 24 in + 60 out (lam 12, D 36, phi 12)
 BYTES_3X3_F64 = 168
 BYTES_2X2_F32 = 40      # 12 in + 28 out (lam 8, D 16, phi 4)
@@ -41,21 +42,24 @@ BYTES_BWD_F32 = 120     # lam 12 + D 36 + glam 12 + gD 36 in, gA 24 out
 
 
 def _source_digest():
-    """sha256 of the HIP sources, to tie stored counter readings to a kernel."""
+    """sha256 of the HIP sources (csrc/*.hip, *.hpp), to tie stored counter
+    readings to the kernels they were taken on."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1306_6291_amd", "csrc")
     for f in sorted(os.listdir(d)):
+        if not f.endswith((".hip", ".hpp")):
+            continue
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _stored_traffic(name):
-    """HBM bytes per launch recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE
-    runs (profiles/<name>_traffic.txt), or None when the kernel sources have
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
+def _stored_profile(name):
+    """Key/value lines of profiles/<name>.txt (written from rocprofv3 runs), or
+    None when the file is missing or the kernel sources have changed since
+    the counters were taken (its source_digest no longer matches)."""
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -65,8 +69,24 @@ def _stored_traffic(name):
             rec[k.strip()] = v.strip()
     if rec.get("source_digest") != _source_digest():
         return None
+    return rec
+
+
+def _stored_traffic(name):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs, or None."""
+    rec = _stored_profile(f"{name}_traffic")
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec["hbm_bytes_per_launch"]) if rec else None
+    except (KeyError, ValueError):
+        return None
+
+
+def _stored_valu(name):
+    """VALU instructions per dispatch (SQ_INSTS_VALU, wave instructions) from
+    the counter run, or None."""
+    rec = _stored_profile(f"{name}_valu")
+    try:
+        return float(rec["SQ_INSTS_VALU_per_dispatch"]) if rec else None
     except (KeyError, ValueError):
         return None
 
@@ -101,26 +121,28 @@ def _time_steps(fn, steps, warmup, torch):
 def _accuracy(P32, out, n_sample, torch, seed=0):
     """Accuracy of a result, without the oracle: residual max_k ||A d_k -
     lam_k d_k|| / ||A||_F and max |D^T D - I| over every matrix (float64 on the
-    GPU, in chunks), and |delta lam| / ||A||_F against LAPACK (numpy eigvalsh)
-    on a random sample."""
+    GPU, plane by plane, in chunks), and |delta lam| / ||A||_F against LAPACK
+    (numpy eigvalsh) on a random sample."""
     n = P32.shape[1]
     res_max = 0.0
     orth_max = 0.0
     chunk = 1 << 22
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        P = torch.from_numpy(P32[:, s:e]).to("cuda", torch.float64)
-        a11, a22, a33, a12, a13, a23 = P
-        A = torch.stack([torch.stack([a11, a12, a13], 1), torch.stack([a12, a22, a23], 1),
-                         torch.stack([a13, a23, a33], 1)], 1)
-        D = out["D"][:, s:e].to(torch.float64).T.reshape(-1, 3, 3)
-        L = out["lam"][:, s:e].to(torch.float64).T
-        fro = torch.sqrt((A * A).sum((1, 2)))
-        r = torch.linalg.vector_norm(torch.bmm(A, D) - D * L[:, None, :], dim=1).amax(1)
-        r = torch.where(fro > 0, r / torch.where(fro > 0, fro, torch.ones_like(fro)), r)
-        res_max = max(res_max, float(r.max()))
-        o = (torch.bmm(D.transpose(1, 2).contiguous(), D) - torch.eye(3, dtype=torch.float64, device="cuda")).abs()
-        orth_max = max(orth_max, float(o.amax()))
+        a11, a22, a33, a12, a13, a23 = torch.from_numpy(P32[:, s:e]).to("cuda", torch.float64)
+        A = ((a11, a12, a13), (a12, a22, a23), (a13, a23, a33))
+        D = out["D"][:, s:e].to(torch.float64)
+        L = out["lam"][:, s:e].to(torch.float64)
+        fro = torch.sqrt(a11 * a11 + a22 * a22 + a33 * a33 + 2 * (a12 * a12 + a13 * a13 + a23 * a23))
+        fro = torch.where(fro > 0, fro, torch.ones_like(fro))
+        for k in range(3):
+            col = (D[k], D[3 + k], D[6 + k])
+            r2 = sum((A[i][0] * col[0] + A[i][1] * col[1] + A[i][2] * col[2] - L[k] * col[i]) ** 2
+                     for i in range(3))
+            res_max = max(res_max, float((torch.sqrt(r2) / fro).max()))
+            for j in range(k, 3):
+                dot = D[j] * D[k] + D[3 + j] * D[3 + k] + D[6 + j] * D[6 + k]
+                orth_max = max(orth_max, float((dot - (1.0 if j == k else 0.0)).abs().max()))
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(n, size=min(n_sample, n), replace=False))
     P64 = P32[:, idx].astype(np.float64)
@@ -173,7 +195,8 @@ def bench_precision(args, torch, ksym, synth):
         for name, path in (("fp64_fixup", ksym.PATH_FP64_FIXUP), ("fp64_plain", ksym.PATH_FP64_PLAIN)):
             o64 = ksym.tuned_opts("eig3", ksym.F64)
             o64.path = path
-            ms64, _ = _time_steps(lambda: ksym.eig3(A64, opts=o64, out=out64), max(3, args.steps // 4), 2, torch)
+            ms64, _ = _time_steps(lambda: ksym.eig3(A64, opts=o64, out=out64), max(3, args.steps // 4),
+                                  max(2, args.warmup // 4), torch)
             rec = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64,
                    "achieved_GBs": BYTES_3X3_F64 * n / (ms64 * 1e-3) / 1e9}
             if args.accuracy:
@@ -281,8 +304,9 @@ def bench_field(args, torch, ksym, synth):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed launches first (the GPU reaches its steady clock after ~0.1 s of work)")
     ap.add_argument("--workload", default="precision",
                     choices=["precision", "mixed", "grad", "field", "copy"])
     ap.add_argument("--n", type=int, default=0, help="override the batch size")
@@ -320,6 +344,7 @@ def main():
     if args.workload == "precision":
         r = bench_precision(args, torch, ksym, synth)
         traffic = _stored_traffic("eig3_f32_precision")
+        valu = _stored_valu("eig3_f32_precision")
         line = dict(base)
         line.update({
             "value": r["value"], "unit": "matrices/s", "ms_per_step": r["ms"], "dtype": "f32",
@@ -336,6 +361,12 @@ def main():
                          "algorithmic_bytes": BYTES_3X3_F32 * r["n"],
                          "kernel": "k_eig3<float, FP32_FIXUP>", "bytes_per_matrix": BYTES_3X3_F32},
         })
+        if valu is not None:
+            # VALU side of the same kernel: wave instructions per launch (rocprofv3
+            # SQ_INSTS_VALU) x 64 lanes / launch time, against 256 CUs x 64 lanes x 2.4 GHz
+            rate = valu * 64 / (r["ms"] * 1e-3) / 1e12
+            line["valu"] = {"achieved": rate, "peak": VALU_PEAK_TLANE, "unit": "T lane-instr/s",
+                            "frac": rate / VALU_PEAK_TLANE, "instr_per_matrix": valu * 64 / r["n"]}
         if "cpu" in r:
             line["cpu_baseline"] = r["cpu"]
         if "fp64" in r:
