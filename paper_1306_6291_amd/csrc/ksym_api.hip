@@ -164,7 +164,7 @@ template <typename T> Eig2K<T> pick_eig2(int bs, int mpl) {
     return nullptr;
 }
 
-template <typename T> using BwdK = void (*)(BwdPtrs<T>, uint32_t, double);
+template <typename T> using BwdK = void (*)(BwdArgs<T>);
 template <typename T> BwdK<T> pick_bwd(int bs, int mpl) {
 #define KSYM_B(B, M) \
     if (bs == B && mpl == M) return &k_eig3_bwd<T, B, M>;
@@ -214,9 +214,10 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     if (!k)
         return fail(KSYM_E_UNSUPPORTED, "no compiled 3x3 kernel for block %d, mats_per_lane %d%s",
                     o.block, o.mats_per_lane, AOS ? " (AoS)" : "");
-    // one launch per KSYM_CHUNK matrices, every pointer advanced by the chunk start
-    for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
-        const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+    // one launch per chunk of matrices, every pointer advanced by the chunk start
+    const int64_t chunk = !AOS ? KSYM_CHUNK : (sizeof(T) == 4 ? KSYM_CHUNK_AOS_F32 : KSYM_CHUNK_AOS_F64);
+    for (int64_t start = 0; start < n; start += chunk) {
+        const int64_t len = n - start < chunk ? n - start : chunk;
         Eig3Args<T> c = a;
         c.prm.n = len;
         for (int k = 0; k < 6; ++k) c.p.in[k] = a.p.in[k] ? a.p.in[k] + start : nullptr;
@@ -456,8 +457,13 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
             int grid = 0;
             ksym_status st = grid_for(len, o.block * o.mats_per_lane, o.grid_mult, &grid);
             if (st != KSYM_OK) return st;
-            hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, p, (uint32_t)len,
-                                  eps_rel);
+            BwdArgs<T> ba;
+            memset(&ba, 0, sizeof ba);
+            ba.p = p;
+            ba.n = (uint32_t)len;
+            ba.zero = 0;
+            ba.eps_rel = eps_rel;
+            hipError_t e = launch(k, dim3(grid), dim3(o.block), (hipStream_t)stream, ba);
             if (e != hipSuccess) return hip_fail(e, "launch k_eig3_bwd");
         }
         return KSYM_OK;

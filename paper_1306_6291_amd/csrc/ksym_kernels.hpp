@@ -13,9 +13,13 @@
 // entries the wave refines them together, entry j on lane j, so the float64
 // refinement always runs on full wavefronts, and overwrites those outputs.
 //
-// Offsets are 32-bit: one launch covers at most KSYM_CHUNK matrices (the host
-// splits larger batches), so every access is a scalar base plus one 32-bit
-// lane offset.
+// Memory access: every plane is read and written through a raw buffer
+// descriptor (base address and size in bytes) with a 32-bit lane offset.  A
+// load outside the plane returns 0 and a store outside it is dropped by the
+// hardware, so the last, partial tile of a launch needs no bounds tests and an
+// absent output plane is simply a plane of size 0.  One launch covers at most
+// KSYM_CHUNK matrices (less for array-of-structures input); the host splits
+// larger batches.
 #pragma once
 
 #include <stddef.h>
@@ -38,8 +42,12 @@ template <typename T> struct Eig3Ptrs {
     uint8_t *flags;
 };
 
-// Matrices per launch: offsets inside a launch are 32-bit byte offsets.
+// Matrices per launch: plane sizes and offsets inside a launch are 32-bit byte
+// counts (structure-of-arrays planes of float64 reach 2^31 bytes; records of
+// six float32 / float64 values take 24 / 48 bytes each).
 constexpr int64_t KSYM_CHUNK = int64_t(1) << 28;
+constexpr int64_t KSYM_CHUNK_AOS_F32 = int64_t(1) << 27;
+constexpr int64_t KSYM_CHUNK_AOS_F64 = int64_t(1) << 26;
 
 struct Eig3Params {
     int64_t n;            // at most KSYM_CHUNK
@@ -287,10 +295,15 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
 // ------------------------------------------------------ per-wave tiles -----
 constexpr int WAVE = 64;
 
+// The value x, opaque to the optimizer (no instruction is emitted).
+__device__ __forceinline__ uint32_t fresh(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // The lane index, recomputed where it is used (two mbcnt) rather than kept in
 // a register across the tile loop: under the 96-register budget the compiler
 // would otherwise spill it and reload it (with a full memory wait) per tile.
-__device__ __forceinline__ uint32_t fresh(uint32_t x);
 __device__ __forceinline__ int lane_id() {
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, fresh(0u)));
 }
@@ -307,10 +320,45 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-// Element `off` of plane p through a 32-bit byte offset (off < KSYM_CHUNK),
-// as a global-memory pointer: every plane is device memory, and saying so
-// gives global_load / global_store with a scalar base instead of flat
-// accesses when the plane pointer itself was read from memory.
+
+// ---- raw buffer access -----------------------------------------------------
+// A descriptor covers one plane: base address, size in bytes (0 for an absent
+// plane), and the fourth word of gfx9-family raw buffers (32-bit data format,
+// no swizzle, no stride).  Offsets are byte offsets.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufWord3 = 0x00020000;
+typedef int v2i32 __attribute__((ext_vector_type(2)));
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t plane_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(p ? bytes : 0u),
+                                             kBufWord3);
+}
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double bload(rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i32, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, uint8_t v) {
+    __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)off, 0, 0);
+}
+// Element `i` of plane p (T values) through a plane descriptor of n elements.
+template <typename T> __device__ __forceinline__ T ld_plane(const T *p, uint32_t n, uint32_t i) {
+    return bload(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), T());
+}
+template <typename T> __device__ __forceinline__ void st_plane(T *p, uint32_t n, uint32_t i, T v) {
+    bstore(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), v);
+}
+
+// Per-lane global stores for the refinement's scattered results, whose plane
+// pointers may differ from lane to lane (mixed batches).
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr<T> elem(T *p, uint32_t off) {
     return (gptr<T>)((gptr<char>)p + off * (uint32_t)sizeof(T));
@@ -318,84 +366,68 @@ template <typename T> __device__ __forceinline__ gptr<T> elem(T *p, uint32_t off
 // Read-only tables (mixed-batch descriptors and tile entries) in the constant
 // address space: they do not change while a kernel runs, so uniform reads
 // become scalar loads even though the kernel stores to global memory.
-// The value x, opaque to the optimizer (no instruction is emitted).  Used on
-// the 32-bit offset of an access inside a conditional block, so the offset is
-// extended to 64 bits in that block and the access can take the scalar-base
-// plus 32-bit-offset form instead of a 64-bit per-lane address.
-__device__ __forceinline__ uint32_t fresh(uint32_t x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
 
-// Output plane pointers read from the kernel-argument segment with a
-// plane-dependent offset: the pointers are fetched (a few scalar loads) where a
-// matrix's outputs are stored instead of being held in scalar registers for
-// the whole kernel.
+// A plane pointer stored in the kernel-argument segment at byte offset off.
+// Read this way, with a plane index offset by a salt (0 at run time, unknown
+// to the compiler) where the plane is used, the pointers and the descriptors
+// built from them are fetched per tile instead of being hoisted out of the
+// tile loop, where dozens of them would exhaust the scalar registers.
+template <typename T> __device__ __forceinline__ T *karg_ptr(uint32_t off) {
+    typedef __attribute__((address_space(4))) const char *kptr;
+    kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+    return *(T *const __attribute__((address_space(4))) *)(ka + off);
+}
+
+// Output plane pointers of a launch in the kernel-argument segment.
+// n: matrices in this launch.
 template <typename T> struct KernargPlanes {
-    uint32_t out_off, flags_off;   // byte offsets inside the argument segment
-    __device__ __forceinline__ T *out(int k) const {
-        typedef __attribute__((address_space(4))) const char *kptr;
-        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
-        return *(T *const __attribute__((address_space(4))) *)(ka + out_off + 8 * k);
-    }
-    __device__ __forceinline__ uint8_t *flags(int salt = 0) const {
-        typedef __attribute__((address_space(4))) const char *kptr;
-        kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
-        return *(uint8_t *const __attribute__((address_space(4))) *)(ka + flags_off + 8 * salt);
-    }
+    uint32_t out_off, flags_off, n;   // byte offsets inside the argument segment
+    __device__ __forceinline__ T *out(int k) const { return karg_ptr<T>(out_off + 8 * k); }
+    __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return karg_ptr<uint8_t>(flags_off + 8 * salt); }
 };
 
 // Output plane pointers of a group descriptor in device memory.
 template <typename T> struct TablePlanes {
     cptr<Eig3Ptrs<T>> p;
+    uint32_t n;
     __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
     __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
 };
 
-// Store one matrix's outputs.  The plane index is offset by salt, which is 0
-// at run time but not known to the compiler, so the pointer loads stay here
-// instead of being hoisted out of the tile loop (where they would pin 38
-// scalar registers for the whole kernel).
+// Store one matrix's outputs (float64 paths).  The plane index is offset by
+// salt, which is 0 at run time but not known to the compiler, so the pointer
+// loads stay here instead of being hoisted out of the tile loop (where they
+// would pin 38 scalar registers for the whole kernel).
 template <typename T, typename Planes>
 __device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, const Out3<T> &o) {
-    T *dst[NOUT3];
 #pragma unroll
-    for (int k = 0; k < NOUT3; ++k) dst[k] = pl.out(k + salt);
-    uint8_t *fl = pl.flags(salt);
-#pragma unroll
-    for (int k = 0; k < NOUT3; ++k)
-        if (dst[k]) *elem(dst[k], fresh(off)) = o.v[k];
-    if (fl) *elem(fl, fresh(off)) = (uint8_t)o.flag;
+    for (int k = 0; k < NOUT3; ++k) st_plane<T>(pl.out(k + salt), pl.n, off, o.v[k]);
+    st_plane<uint8_t>(pl.flags(salt), pl.n, off, (uint8_t)o.flag);
 }
 
 // Stores of one lane's matrix as its outputs are produced (float32 path).
-// FULL: every lane of the tile holds a matrix (no per-lane bounds test).
-template <typename T, typename Planes, bool FULL> struct LaneSink {
+// Lanes past n and absent planes are dropped by the descriptors.
+template <typename T, typename Planes> struct LaneSink {
     const Planes &pl;
     int salt;
     uint32_t off;
-    bool valid;
-    __device__ __forceinline__ void put(int k, T v) const {
-        T *d = pl.out(k + salt);
-        if ((FULL || valid) && d) *elem(d, fresh(off)) = v;
-    }
+    __device__ __forceinline__ void put(int k, T v) const { st_plane<T>(pl.out(k + salt), pl.n, off, v); }
     __device__ __forceinline__ void flag(int f) const {
-        uint8_t *fl = pl.flags(salt);
-        if ((FULL || valid) && fl) *elem(fl, fresh(off)) = (uint8_t)f;
+        st_plane<uint8_t>(pl.flags(salt), pl.n, off, (uint8_t)f);
     }
 };
 
-// A refined result: scattered stores (the rare path).
+// A refined result: scattered per-lane stores (the rare path).
 template <typename T, typename Planes>
-__device__ __forceinline__ void write_out3(const Planes &pl, uint32_t off, const Out3<T> &o) {
+__device__ __forceinline__ void write_out3(const Planes &pl, int salt, uint32_t off, const Out3<T> &o) {
 #pragma unroll
     for (int k = 0; k < NOUT3; ++k) {
-        T *dst = pl.out(k);
+        T *dst = pl.out(k + salt);
         if (dst) *elem(dst, fresh(off)) = o.v[k];
     }
-    uint8_t *fl = pl.flags();
+    uint8_t *fl = pl.flags(salt);
     if (fl) *elem(fl, fresh(off)) = (uint8_t)o.flag;
 }
 
@@ -424,43 +456,50 @@ template <typename T, int MPL, bool AOS> struct WIn {
     T v[AOS ? NVL : 1][AOS ? VEC : 1];
 };
 
-// FULL: the whole tile lies below n (unconditional loads).  Otherwise lanes
-// past n load the last matrix (a clamped, in-bounds offset) and take zeros.
-template <typename T, int MPL, bool AOS, bool FULL>
-__device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const *planes,
-                                            const T *aos, uint32_t n, uint32_t base) {
+// Lanes past n read zeros (the descriptor's bound).  AoS: a 16-byte vector
+// that straddles the end of the records is read element by element.
+// Input planes (SoA: six pointers; AoS: the record pointer), read where a
+// tile is loaded.  Kernel arguments: through the argument segment with a salt;
+// mixed batches: from the group descriptor.
+template <typename T> struct KernargInputs {
+    uint32_t in_off, aos_off;
+    int salt;
+    __device__ __forceinline__ const T *in(int c) const { return karg_ptr<const T>(in_off + 8 * (c + salt)); }
+    __device__ __forceinline__ const T *aos() const { return karg_ptr<const T>(aos_off + 8 * salt); }
+};
+
+template <typename T, int MPL, bool AOS, typename Inputs>
+__device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &src, uint32_t n,
+                                            uint32_t base) {
     const int lane = lane_id();
     if constexpr (AOS) {
         using W = WIn<T, MPL, AOS>;
         constexpr int VEC = W::VEC;
-        const uint32_t lim = (n - base) * 6;   // valid elements from `base` on
-        const T *src = aos + (size_t)base * 6;
+        const uint32_t lim = n * 6;   // elements in the launch
+        const rsrc_t r = plane_rsrc(src.aos(), lim * (uint32_t)sizeof(T));
 #pragma unroll
         for (int u = 0; u < W::NVL; ++u) {
             const uint32_t j = u * WAVE + lane;
-            const uint32_t e0 = j * VEC;
-            if (j < (uint32_t)W::NV && e0 + VEC <= lim) {
-                typedef T vec_t __attribute__((ext_vector_type(VEC)));
-                const vec_t x = *reinterpret_cast<gptr<const vec_t>>(elem(src, e0));
+            const uint32_t e0 = base * 6 + j * VEC;
+            if (j < (uint32_t)W::NV) {
+                if (e0 + VEC <= lim) {
+                    const v4i32 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(e0 * sizeof(T)), 0, 0);
+                    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+                    const vec_t y = __builtin_bit_cast(vec_t, x);
 #pragma unroll
-                for (int t = 0; t < VEC; ++t) in.v[u][t] = x[t];
-            } else {
+                    for (int t = 0; t < VEC; ++t) in.v[u][t] = y[t];
+                } else {
 #pragma unroll
-                for (int t = 0; t < VEC; ++t)
-                    in.v[u][t] = (j < (uint32_t)W::NV && e0 + t < lim) ? *elem(src, e0 + t) : T(0);
+                    for (int t = 0; t < VEC; ++t) in.v[u][t] = bload(r, (e0 + t) * (uint32_t)sizeof(T), T());
+                }
             }
         }
     } else {
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const uint32_t off = base + k * WAVE + lane;
-            const bool ok = FULL || off < n;
-            const uint32_t offc = ok ? off : n - 1;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const T v = *elem(planes[c], offc);
-                in.a[k][c] = ok ? v : T(0);
-            }
+            for (int c = 0; c < 6; ++c) in.a[k][c] = ld_plane<T>(src.in(c), n, off);
         }
     }
 }
@@ -469,7 +508,8 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const T *const
 // overwrite their provisional outputs.  The wave's own provisional stores are
 // waited for first, so a refined value always lands last.
 template <typename T, int CAP, typename PlanesOf>
-__device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const PlanesOf &planes_of) {
+__device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const PlanesOf &planes_of,
+                                           int salt) {
     __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): earlier stores of this wave have completed
     const int lane = lane_id();
     if (lane < cnt) {
@@ -479,14 +519,14 @@ __device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const 
         const int g = q->grp[lane];
         Out3<T> o;
         refine_one<T>(a, q->lc[lane], g >> 24, o);
-        write_out3(planes_of(g & 0xffffff), q->off[lane], o);
+        write_out3(planes_of(g & 0xffffff), salt, q->off[lane], o);
     }
 }
 
 // Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
 // already in registers: compute, store, queue the matrices that need the
-// refinement, and drain the queue in rounds of 64.  Wave-uniform control flow.
-template <typename T, int PATH, int MPL, bool AOS, bool FULL, typename Planes, typename PlanesOf>
+// refinement, and drain the queue.  Wave-uniform control flow.
+template <typename T, int PATH, int MPL, bool AOS, typename Planes, typename PlanesOf>
 __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
                                            const Eig3Params &prm, const WIn<T, MPL, AOS> &in,
                                            uint32_t n, uint32_t base,
@@ -510,7 +550,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
     for (int k = 0; k < MPL; ++k) {
         const int slot = k * WAVE + lane;
         const uint32_t off = base + slot;
-        const bool valid = FULL || off < n;
+        const bool valid = off < n;
         T A[6];
         if constexpr (AOS) {
 #pragma unroll
@@ -524,11 +564,11 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         bool refine;
         double lc;
         if constexpr (PATH == PATH_FP32_FIXUP) {
-            flag = eig3_f32(A, prm, LaneSink<T, Planes, FULL>{pl, salt, off, valid}, refine, lc);
+            flag = eig3_f32(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T, PATH>(A, prm, o);
-            if (valid) put3(pl, salt, off, o);
+            put3(pl, salt, off, o);
             flag = o.flag;
             refine = o.refine;
             lc = o.lc;
@@ -559,7 +599,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         while (qn >= WAVE || (qn > 0 && prm.drain_tiles > 0 && qage >= prm.drain_tiles)) {
             const int cnt = qn < WAVE ? qn : WAVE;
             wave_sync();
-            drain_wave<T>(&sm->q, cnt, planes_of);
+            drain_wave<T>(&sm->q, cnt, planes_of, (int)(base * (uint32_t)prm.zero));
             refined += (unsigned)cnt;
             const int rest = qn - cnt;
             // move entries [cnt, qn) to the front; a lane reads only entries
@@ -591,7 +631,7 @@ __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<
                                             int qn, unsigned &refined) {
     if (qn > 0) {
         wave_sync();
-        drain_wave<T>(&sm->q, qn, planes_of);
+        drain_wave<T>(&sm->q, qn, planes_of, 0);
         refined += (unsigned)qn;
     }
 }
@@ -620,27 +660,23 @@ void k_eig3(Eig3Args<T> args) {
     KernargPlanes<T> pl;
     pl.out_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, out));
     pl.flags_off = (uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, flags));
+    pl.n = n;
     auto planes_of = [&](int) { return pl; };
     unsigned refined = 0, nonfinite = 0;
     int qn = 0, qage = 0;
     WIn<T, MPL, AOS> cur, nxt;
     const uint32_t stride = gridDim.x * NW;
     uint32_t t = blockIdx.x * NW + wave_id();
-    const uint32_t nfull = n / WT;   // tiles with no lane past n
-    auto load = [&](WIn<T, MPL, AOS> &w, uint32_t tt) {
-        if (tt < nfull) load_wtile3<T, MPL, AOS, true>(w, args.p.in, args.aos, n, tt * WT);
-        else load_wtile3<T, MPL, AOS, false>(w, args.p.in, args.aos, n, tt * WT);
+    auto inputs = [&](uint32_t tt) {
+        return KernargInputs<T>{(uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, in)),
+                                (uint32_t)offsetof(Eig3Args<T>, aos), (int)(tt * (uint32_t)args.prm.zero)};
     };
-    if (t < ntiles) load(cur, t);
+    if (t < ntiles) load_wtile3<T, MPL, AOS>(cur, inputs(t), n, t * WT);
     for (; t < ntiles; t += stride) {
         const uint32_t tn = t + stride;
-        if (tn < ntiles) load(nxt, tn);
-        if (t < nfull)
-            wtile_eig3<T, PATH, MPL, AOS, true>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage,
-                                                refined, nonfinite);
-        else
-            wtile_eig3<T, PATH, MPL, AOS, false>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage,
-                                                 refined, nonfinite);
+        if (tn < ntiles) load_wtile3<T, MPL, AOS>(nxt, inputs(tn), n, tn * WT);
+        wtile_eig3<T, PATH, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
+                                      nonfinite);
         cur = nxt;
     }
     if constexpr (QUEUE) final_drain<T, MPL, AOS>(planes_of, my, qn, refined);
@@ -657,10 +693,10 @@ template <typename T> struct Eig2Ptrs {
 };
 
 // One 2x2 matrix (§3) and its stores; out = lam1, lam2, D11, D12, D21, D22,
-// phi (any may be null).
+// phi (absent planes and lanes past n are dropped by the descriptors).
 template <typename T>
 __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], uint8_t *flags,
-                                          uint32_t off) {
+                                          uint32_t n, uint32_t off) {
     const bool fin = finite(a11) && finite(a22) && finite(a12);
     // exact power-of-two scaling keeps d^2 + 4 A12^2 in range
     const double amax = fmax(fmax(__builtin_fabs((double)a11), __builtin_fabs((double)a22)),
@@ -676,33 +712,25 @@ __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], 
     }
     const T v[7] = {e.l1, e.l2, e.c, -e.s, e.s, e.c, e.phi};
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
-        if (out[k]) *elem(out[k], fresh(off)) = v[k];
-    if (flags) *elem(flags, fresh(off)) = fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE;
+    for (int k = 0; k < 7; ++k) st_plane<T>(out[k], n, off, v[k]);
+    st_plane<uint8_t>(flags, n, off, fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE);
 }
 
 // One wave tile of 64*MPL 2x2 matrices, straight from and to HBM.
-template <typename T, int MPL, bool FULL>
+template <typename T, int MPL>
 __device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uint32_t base) {
     const int lane = lane_id();
     T A[MPL][3];
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
-        const bool ok = FULL || off < n;
-        const uint32_t offc = ok ? off : n - 1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T v = *elem(p.in[c], offc);
-            A[k][c] = ok ? v : T(0);
-        }
+        for (int c = 0; c < 3; ++c) A[k][c] = ld_plane<T>(p.in[c], n, off);
     }
     T *const out[7] = {p.lam[0], p.lam[1], p.D[0], p.D[1], p.D[2], p.D[3], p.phi};
 #pragma unroll
-    for (int k = 0; k < MPL; ++k) {
-        const uint32_t off = base + k * WAVE + lane;
-        if (FULL || off < n) eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, off);
-    }
+    for (int k = 0; k < MPL; ++k)
+        eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, n, base + k * WAVE + lane);
 }
 
 template <typename T, int BS, int MPL>
@@ -710,11 +738,7 @@ __global__ __launch_bounds__(BS) void k_eig2(Eig2Ptrs<T> p, uint32_t n) {
     constexpr int NW = BS / WAVE, WT = WAVE * MPL;
     const uint32_t ntiles = (n + WT - 1) / WT;
     const uint32_t stride = gridDim.x * NW;
-    const uint32_t nfull = n / WT;
-    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += stride) {
-        if (t < nfull) wtile_eig2<T, MPL, true>(p, n, t * WT);
-        else wtile_eig2<T, MPL, false>(p, n, t * WT);
-    }
+    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += stride) wtile_eig2<T, MPL>(p, n, t * WT);
 }
 
 // -------------------------------------------------------- adjoint ----------
@@ -727,26 +751,34 @@ template <typename T> struct BwdPtrs {
     T *gA[6];
 };
 
-// One lane's adjoint.  FULL: i < n is known; otherwise lanes past n read the
-// last matrix (in bounds) and store nothing.
-template <typename T, bool FULL>
-__device__ __forceinline__ void bwd_lane(const BwdPtrs<T> &p, bool has_gap, bool has_gl, bool has_gd,
-                                         uint32_t i, uint32_t n, double eps_rel) {
-    const bool ok = FULL || i < n;
-    const uint32_t ic = ok ? i : n - 1;
+template <typename T> struct BwdArgs {
+    BwdPtrs<T> p;
+    uint32_t n;
+    int32_t zero;     // always 0; see karg_ptr
+    double eps_rel;
+};
+
+// One lane's adjoint.  Absent cotangents read as zeros; lanes past n read
+// zeros and store nothing (the descriptors' bounds).  Plane pointers come
+// from the argument segment (salt: see karg_ptr).
+template <typename T>
+__device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, double eps_rel, int salt) {
+    constexpr uint32_t P = (uint32_t)offsetof(BwdArgs<T>, p);
+    auto ptr = [&](uint32_t field, int c) { return karg_ptr<T>(P + field + 8 * (c + salt)); };
     T L[3], D[9], gl[3], gD[9], gA[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c] = *elem(p.lam[c], ic);
+    for (int c = 0; c < 3; ++c) L[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, lam), c), n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) D[c] = *elem(p.D[c], ic);
+    for (int c = 0; c < 9; ++c) D[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, D), c), n, i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gl[c] = has_gl ? *elem(p.glam[c], fresh(ic)) : T(0);
+    for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, glam), c), n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) gD[c] = has_gd ? *elem(p.gD[c], fresh(ic)) : T(0);
+    for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gD), c), n, i);
     T g12, g13, g32;
     if (has_gap) {
-        const uint32_t o = fresh(ic);
-        g12 = *elem(p.gap[0], o); g13 = *elem(p.gap[1], o); g32 = *elem(p.gap[2], o);
+        g12 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 0), n, i);
+        g13 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 1), n, i);
+        g32 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 2), n, i);
     } else {
         // differences of the stored eigenvalues, exact in float64
         g12 = (T)((double)L[0] - (double)L[1]);
@@ -755,28 +787,20 @@ __device__ __forceinline__ void bwd_lane(const BwdPtrs<T> &p, bool has_gap, bool
     }
     const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
-    if (ok) {
-        const uint32_t o = fresh(i);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) *elem(p.gA[c], o) = gA[c];
-    }
+    for (int c = 0; c < 6; ++c) st_plane<T>(ptr(offsetof(BwdPtrs<T>, gA), c), n, i, gA[c]);
 }
 
 template <typename T, int BS, int MPL>
-__global__ __launch_bounds__(BS) void k_eig3_bwd(BwdPtrs<T> p, uint32_t n, double eps_rel) {
+__global__ __launch_bounds__(BS) void k_eig3_bwd(BwdArgs<T> a) {
     constexpr int TILE = BS * MPL;
+    const uint32_t n = a.n;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
-    const uint32_t nfull = n / TILE;
-    const bool has_gap = p.gap[0] && p.gap[1] && p.gap[2];
-    const bool has_gl = p.glam[0] != nullptr;
-    const bool has_gd = p.gD[0] != nullptr;
+    const bool has_gap = a.p.gap[0] && a.p.gap[1] && a.p.gap[2];
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int salt = (int)(t * (uint32_t)a.zero);
 #pragma unroll
-        for (int k = 0; k < MPL; ++k) {
-            const uint32_t i = t * TILE + k * BS + threadIdx.x;
-            if (t < nfull) bwd_lane<T, true>(p, has_gap, has_gl, has_gd, i, n, eps_rel);
-            else bwd_lane<T, false>(p, has_gap, has_gl, has_gd, i, n, eps_rel);
-        }
+        for (int k = 0; k < MPL; ++k) bwd_lane<T>(has_gap, t * TILE + k * BS + threadIdx.x, n, a.eps_rel, salt);
     }
 }
 
@@ -810,44 +834,30 @@ template <typename T> struct MixedArgs {
     Eig3Params prm;              // thresholds and counters (prm.n unused)
 };
 
-// Inputs of one mixed-batch wave tile (the 2x2 kind uses planes 0..2; the
-// other slots are zero).  One loop for both kinds keeps the tile in registers;
-// lanes past n read the group's last matrix (in bounds) and take zeros.
+// Inputs of one mixed-batch wave tile (the 2x2 kind uses planes 0..2; its
+// planes 3..5 are absent and read as zeros).
+template <typename T> struct TableInputs {
+    cptr<GroupDesc<T>> g;
+    __device__ __forceinline__ const T *in(int c) const { return g->p3.in[c]; }
+    __device__ __forceinline__ const T *aos() const { return nullptr; }
+};
+
 template <typename T, int MPL>
-__device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, const __attribute__((address_space(4))) GroupDesc<T> &g,
-                                           uint32_t base) {
-    const uint32_t n = (uint32_t)g.n;
-    const int np = g.kind == 3 ? 6 : 3;
-    const int lane = lane_id();
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const T *pc = g.p3.in[c];
-#pragma unroll
-        for (int k = 0; k < MPL; ++k) {
-            const uint32_t off = base + k * WAVE + lane;
-            const bool ok = off < n;
-            const uint32_t offc = ok ? off : n - 1;
-            T v = T(0);
-            if (c < np) v = *elem(pc, fresh(offc));
-            in.a[k][c] = ok ? v : T(0);
-        }
-    }
+__device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, cptr<GroupDesc<T>> g, uint32_t base) {
+    load_wtile3<T, MPL, false>(in, TableInputs<T>{g}, (uint32_t)g->n, base);
 }
 
 // One 2x2 wave tile of a mixed batch from inputs already in registers.
-template <typename T, int MPL, bool FULL>
+template <typename T, int MPL>
 __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space(4))) GroupDesc<T> &g,
-                                              const WIn<T, MPL, false> &in,
-                                              uint32_t base) {
+                                              const WIn<T, MPL, false> &in, uint32_t base) {
     const uint32_t n = (uint32_t)g.n;
     const int lane = lane_id();
     T *const out[7] = {g.p3.out[O_LAM], g.p3.out[O_LAM + 1], g.p3.out[O_D], g.p3.out[O_D + 1],
                        g.p3.out[O_D + 2], g.p3.out[O_D + 3], g.p3.out[O_PHI]};
 #pragma unroll
-    for (int k = 0; k < MPL; ++k) {
-        const uint32_t off = base + k * WAVE + lane;
-        if (FULL || off < n) eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, off);
-    }
+    for (int k = 0; k < MPL; ++k)
+        eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, n, base + k * WAVE + lane);
 }
 
 // One persistent launch over all groups.  Wave tile t is described by
@@ -864,7 +874,7 @@ void k_mixed(MixedArgs<T> a) {
     WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
     const cptr<GroupDesc<T>> groups = as_const(a.groups);
     const cptr<TileInfo> tiles = as_const(a.tiles);
-    auto planes_of = [&](int g) { return TablePlanes<T>{&groups[g].p3}; };
+    auto planes_of = [&](int g) { return TablePlanes<T>{&groups[g].p3, (uint32_t)groups[g].n}; };
     unsigned refined = 0, nonfinite = 0;
     int qn = 0, qage = 0;
     const int64_t stride = (int64_t)gridDim.x * NW;
@@ -873,28 +883,21 @@ void k_mixed(MixedArgs<T> a) {
     WIn<T, MPL, false> in_cur, in_nxt;
     if (t < a.ntiles) {
         cur = tile_at(tiles, t);
-        load_mixed<T, MPL>(in_cur, groups[cur.group], cur.base);
+        load_mixed<T, MPL>(in_cur, groups + cur.group, cur.base);
     }
     if (t + stride < a.ntiles) nxt = tile_at(tiles, t + stride);
     for (; t < a.ntiles; t += stride) {
         const bool has_next = t + stride < a.ntiles;
         TileInfo nxt2 = {0, 0};
         if (t + 2 * stride < a.ntiles) nxt2 = tile_at(tiles, t + 2 * stride);
-        if (has_next) load_mixed<T, MPL>(in_nxt, groups[nxt.group], nxt.base);
+        if (has_next) load_mixed<T, MPL>(in_nxt, groups + nxt.group, nxt.base);
         const auto &g = groups[cur.group];
         const uint32_t n = (uint32_t)g.n;
-        const bool full = cur.base + WAVE * MPL <= n;
-        if (g.kind == 3) {
-            if (full)
-                wtile_eig3<T, PATH, MPL, false, true>(planes_of(cur.group), planes_of, cur.group, a.prm,
-                                                      in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
-            else
-                wtile_eig3<T, PATH, MPL, false, false>(planes_of(cur.group), planes_of, cur.group, a.prm,
-                                                       in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
-        } else {
-            if (full) wtile_eig2_in<T, MPL, true>(g, in_cur, cur.base);
-            else wtile_eig2_in<T, MPL, false>(g, in_cur, cur.base);
-        }
+        if (g.kind == 3)
+            wtile_eig3<T, PATH, MPL, false>(planes_of(cur.group), planes_of, cur.group, a.prm, in_cur, n,
+                                            cur.base, my, qn, qage, refined, nonfinite);
+        else
+            wtile_eig2_in<T, MPL>(g, in_cur, cur.base);
         cur = nxt;
         nxt = nxt2;
         in_cur = in_nxt;
