@@ -625,14 +625,43 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
     }
 }
 
-// Refine what is left in a wave's queue at the end of its work.
-template <typename T, int MPL, bool AOS, typename PlanesOf>
+// Refine what is left in the queues of all NW waves of the workgroup once
+// they have finished their tiles: the leftovers are pooled (entry e of the
+// concatenated queues goes to lane e % 64 of wave (e / 64) % NW), so a
+// workgroup pays for one partly filled refinement round instead of one per
+// wave.  Each wave first waits for its own stores, because a refined result
+// may now overwrite a provisional one that another wave wrote.
+template <typename T, int MPL, bool AOS, int NW, typename PlanesOf>
 __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
-                                            int qn, unsigned &refined) {
-    if (qn > 0) {
-        wave_sync();
-        drain_wave<T>(&sm->q, qn, planes_of, 0);
-        refined += (unsigned)qn;
+                                            int *qcount, int qn, unsigned &refined) {
+    const int w = wave_id();
+    const int lane = lane_id();
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
+    if (lane == 0) qcount[w] = qn;
+    __syncthreads();
+    int pre[NW + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) pre[v + 1] = pre[v] + qcount[v];
+    const int total = pre[NW];
+    for (int r = w; r * WAVE < total; r += NW) {
+        const int e = r * WAVE + lane;
+        const int cnt = total - r * WAVE < WAVE ? total - r * WAVE : WAVE;
+        refined += (unsigned)cnt;
+        if (e < total) {
+            int src = 0;
+#pragma unroll
+            for (int v = 1; v < NW; ++v) src += (e >= pre[v]) ? 1 : 0;
+            const int i = e - pre[src];
+            const WaveQueue<T, WAVE *(MPL + 1)> *q = &sm[src].q;
+            T a[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] = q->a[c][i];
+            const int g = q->grp[i];
+            Out3<T> o;
+            refine_one<T>(a, q->lc[i], g >> 24, o);
+            write_out3(planes_of(g & 0xffffff), 0, q->off[i], o);
+        }
     }
 }
 
@@ -654,6 +683,7 @@ void k_eig3(Eig3Args<T> args) {
     constexpr int WT = WAVE * MPL;
     constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
     __shared__ WaveSmem<T, MPL, QUEUE, AOS> sm[NW];
+    __shared__ int qcount[NW];
     WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wave_id()];
     const uint32_t n = (uint32_t)args.prm.n;
     const uint32_t ntiles = (n + WT - 1) / WT;
@@ -679,7 +709,7 @@ void k_eig3(Eig3Args<T> args) {
                                       nonfinite);
         cur = nxt;
     }
-    if constexpr (QUEUE) final_drain<T, MPL, AOS>(planes_of, my, qn, refined);
+    if constexpr (QUEUE) final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, refined);
     add_counters(args.prm.counters, refined, nonfinite);
 }
 
@@ -871,6 +901,7 @@ void k_mixed(MixedArgs<T> a) {
     constexpr int NW = BS / WAVE;
     constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
+    __shared__ int qcount[NW];
     WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
     const cptr<GroupDesc<T>> groups = as_const(a.groups);
     const cptr<TileInfo> tiles = as_const(a.tiles);
@@ -902,7 +933,7 @@ void k_mixed(MixedArgs<T> a) {
         nxt = nxt2;
         in_cur = in_nxt;
     }
-    final_drain<T, MPL, false>(planes_of, my, qn, refined);
+    final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, refined);
     add_counters(a.prm.counters, refined, nonfinite);
 }
 
