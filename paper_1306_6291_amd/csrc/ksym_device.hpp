@@ -61,21 +61,28 @@ __device__ __forceinline__ int scale_exponent(double amax) {
 // ------------------------------------------------ polynomial kernels -----
 // Coefficients and their derivation: ksym_poly.hpp / gen_poly.py.
 
-// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rsqrt64(double x) {
+// 1/sqrt(x) for normal x > 0: hardware estimate (about 23 bits) refined by
+// NEWTON Newton steps; two give full float64 accuracy, one about 2^-44, which
+// is what the float32 path needs.
+template <int NEWTON = 2> __device__ __forceinline__ double rsqrt64(double x) {
     double y = __builtin_amdgcn_rsq(x);
-    double e = __builtin_fma(-x * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-x * y, y, 1.0);
-    return __builtin_fma(0.5 * y, e, y);
+#pragma unroll
+    for (int k = 0; k < NEWTON; ++k) {
+        const double e = __builtin_fma(-x * y, y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
 }
 
-// sqrt(z) for z in [0, 1/4]: sqrt = z / sqrt(z) with one correction step.
-__device__ __forceinline__ double sqrt_small64(double z) {
-    const double y = rsqrt64(z);
+// sqrt(z) for z in [0, 1/4]: sqrt = z / sqrt(z), with one correction step when
+// full float64 accuracy is wanted (NEWTON = 2).
+template <int NEWTON = 2> __device__ __forceinline__ double sqrt_small64(double z) {
+    const double y = rsqrt64<NEWTON>(z);
     double s = z * y;
-    const double d = __builtin_fma(-s, s, z);
-    s = __builtin_fma(0.5 * y, d, s);
+    if constexpr (NEWTON >= 2) {
+        const double d = __builtin_fma(-s, s, z);
+        s = __builtin_fma(0.5 * y, d, s);
+    }
     return z > 0.0 ? s : 0.0;
 }
 
@@ -126,7 +133,7 @@ __device__ __forceinline__ void acos_pair_fast(double r, double &D, double &Dc) 
     const double ar = __builtin_fabs(r);
     const bool small = ar <= 0.5;
     const double z = small ? ar * ar : 0.5 * (1.0 - ar);
-    const double x = small ? ar : sqrt_small64(z);
+    const double x = small ? ar : sqrt_small64<1>(z);
     const float P = tail_poly(poly::AT, 6, (float)z);
     const double a = __builtin_fma(x * z, (double)P, x);   // asin(x)
     if (small) {
@@ -166,6 +173,20 @@ __device__ __forceinline__ float atan2_fast(float y, float x) {
     float a = __builtin_fmaf(t * t2, Q, t);
     a = (ay > ax) ? 1.57079632679489662f - a : a;
     a = (x < 0.0f) ? 3.14159265358979324f - a : a;
+    return (y < 0.0f) ? -a : a;
+}
+
+// atan2(y, x) for x >= 0 (the right half plane), same polynomial as atan2_fast.
+__device__ __forceinline__ float atan2_right(float y, float x) {
+    const float ay = __builtin_fabsf(y);
+    const float mn = __builtin_fminf(x, ay), mx = __builtin_fmaxf(x, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t2 = t * t;
+    float Q = poly::ATAN[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) Q = __builtin_fmaf(Q, t2, poly::ATAN[k]);
+    float a = __builtin_fmaf(t * t2, Q, t);
+    a = (ay > x) ? 1.57079632679489662f - a : a;
     return (y < 0.0f) ? -a : a;
 }
 
@@ -260,7 +281,7 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
     const double det = d1 * (d2 * d3 - a23 * a23) - a12 * (a12 * d3 - a13 * a23) +
                        a13 * (a12 * a23 - a13 * d2);
     c.triple = !(p >= 1e-280);
-    const double ip = rsqrt64(c.triple ? 1.0 : p);
+    const double ip = rsqrt64<1>(c.triple ? 1.0 : p);
     const double sp = c.triple ? 0.0 : p * ip;
     double r = 13.5 * det * (ip * ip * ip);        // 27 det / (2 sqrt(p)^3)
     r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
@@ -280,12 +301,16 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
 
 // ------------------------------------------------ 3x3 angle solve (§5) -----
 // 1/x for positive normal x: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rcp64(double x) {
+// 1/x for positive normal x: hardware estimate refined by NEWTON Newton steps
+// (two: full float64 accuracy; one: about 2^-44).
+template <int NEWTON = 2> __device__ __forceinline__ double rcp64(double x) {
     double y = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-x, y, 1.0);
-    return __builtin_fma(y, e, y);
+#pragma unroll
+    for (int k = 0; k < NEWTON; ++k) {
+        const double e = __builtin_fma(-x, y, 1.0);
+        y = __builtin_fma(y, e, y);
+    }
+    return y;
 }
 
 // The squared direction cosines of the first row of D, each as its own
@@ -306,28 +331,26 @@ struct URow {
     double v, s2sq, w, cw;   // cos^2 phi2, sin^2 phi2, cos^2 phi3, sin^2 phi3
 };
 
-__device__ __forceinline__ void split_unit(double p, double q, double &x, double &y) {
+template <int NEWTON> __device__ __forceinline__ void split_unit(double p, double q, double &x, double &y) {
     p = p > 0.0 ? p : 0.0;
     q = q > 0.0 ? q : 0.0;
     const double t = p + q;
-    if (t > 0.0) {
-        const double r = rcp64(t);
-        x = p * r;
-        y = q * r;
-    } else {
-        x = 1.0;
-        y = 0.0;
-    }
+    const bool pos = t > 0.0;
+    const double r = rcp64<NEWTON>(pos ? t : 1.0);
+    x = pos ? p * r : 1.0;
+    y = pos ? q * r : 0.0;
 }
 
+// NEWTON = 1 is enough when the quotients are rounded to float32.
+template <int NEWTON = 2>
 __device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, double mu3, double g13,
                                             double g32, double a12, double a13) {
     const double F = a12 * a12 + a13 * a13;
     const double e1 = d1 - mu1, e2 = d1 - mu2, e3 = d1 - mu3;
     URow u;
-    split_unit(F + e3 * (e1 + g32), -(F + e1 * e2), u.v, u.s2sq);
+    split_unit<NEWTON>(F + e3 * (e1 + g32), -(F + e1 * e2), u.v, u.s2sq);
     // v = 0 gives w = 1, the paper's convention
-    split_unit((F + e2 * e3) * g32, (F + e1 * e3) * g13, u.w, u.cw);
+    split_unit<NEWTON>((F + e2 * e3) * g32, (F + e1 * e3) * g13, u.w, u.cw);
     return u;
 }
 
@@ -439,11 +462,18 @@ template <typename T> __device__ __forceinline__ void build_D(const Rot<T>& R, T
     D[8] = R.c1 * R.c2;
 }
 
+// phi2 and phi3 have non-negative cosines (c2 = sqrt(v), c3 = sqrt(w)), which
+// saves the quadrant fold of a general atan2 in float32.
 template <typename T> __device__ __forceinline__ void angles_of(const Rot<T>& R, T phi[3]) {
     using M = Mth<T>;
     phi[0] = M::atan2(R.s1, R.c1);
-    phi[1] = M::atan2(R.s2, R.c2);
-    phi[2] = M::atan2(R.s3, R.c3);
+    if constexpr (sizeof(T) == 4) {
+        phi[1] = atan2_right(R.s2, R.c2);
+        phi[2] = atan2_right(R.s3, R.c3);
+    } else {
+        phi[1] = M::atan2(R.s2, R.c2);
+        phi[2] = M::atan2(R.s3, R.c3);
+    }
 }
 
 // Angles of a rotation D (det +1) with D = R1 R2 R3: phi1 from the third

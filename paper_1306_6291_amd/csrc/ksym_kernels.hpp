@@ -243,10 +243,11 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
     // general branch (5.1)-(5.15): the four squared cosines and sines as
     // float64 quotients (u_quotients), the rest of the angle solve in float32
-    const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
+    const URow u = u_quotients<1>(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
+    const float A11 = (float)a[0], A22 = (float)a[1], A33 = (float)a[2];
     const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
     const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
-    const Rot<float> R = select_angles<float>(A12, A13, (float)a[1], (float)a[2], A23, G12, G13, G32,
+    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32,
                                               (float)u.v, (float)u.s2sq, (float)u.w, (float)u.cw);
     float phi[3];
     angles_of(R, phi);
@@ -256,8 +257,8 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     build_D(R, D);
 #pragma unroll
     for (int i = 0; i < 9; ++i) sink.put(O_D + i, D[i]);
-    const float fro = __builtin_sqrtf((float)(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] +
-                                              2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5])));
+    const float fro = __builtin_sqrtf(A11 * A11 + A22 * A22 + A33 * A33 +
+                                      2.0f * (A12 * A12 + A13 * A13 + A23 * A23));
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                     (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
                                     (float)prm.tau_res * fro, (float)prm.tau_vec);
