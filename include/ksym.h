@@ -111,8 +111,8 @@ typedef enum {
  *                  (the grid is min(tiles, grid_mult * CUs)); 1..64.
  *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
  *                  below which a matrix always takes the refinement (0 = off).
- *   tau_res        refinement if some |d_j^T A d_k| (j != k) exceeds
- *                  tau_res * ||A||_F (a residual bound).
+ *   tau_res        refinement if some residual ||A d_k - lam_k d_k|| exceeds
+ *                  tau_res * ||A||_F.
  *   tau_vec        refinement if some |d_j^T A d_k| / |lam_k - lam_j| exceeds
  *                  tau_vec (first-order angle error of the eigenvectors;
  *                  0 = off).

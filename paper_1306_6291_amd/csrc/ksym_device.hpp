@@ -376,16 +376,15 @@ __device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, d
 template <typename T>
 __device__ __forceinline__ void csqrt_principal(T x, T y, T& rx, T& ry) {
     using M = Mth<T>;
+    // t = sqrt((|z| + |x|) / 2) is the larger component of the root, u = y / (2t)
+    // the other: (t, u) in the right half plane, (|u|, +-t) in the left, where
+    // y = +-0 on the negative axis gives +i (arg = +pi).  Branch-free.
     const T m = M::sqrt(x * x + y * y);
-    if (m == T(0)) { rx = T(0); ry = T(0); return; }
-    if (x >= T(0)) {
-        rx = M::sqrt(T(0.5) * (m + x));
-        ry = M::div(T(0.5) * y, rx);
-    } else {
-        const T t = M::sqrt(T(0.5) * (m - x));
-        ry = (y >= T(0)) ? t : -t;   // y = +-0 on the negative axis -> +i: arg = +pi
-        rx = M::div(T(0.5) * y, ry);
-    }
+    const T t = M::sqrt(T(0.5) * (m + M::fabs(x)));
+    const T u = T(0.5) * y * M::rcp(t);
+    const bool right = x >= T(0), nz = m > T(0);
+    rx = nz ? (right ? t : M::fabs(u)) : T(0);
+    ry = nz ? (right ? u : ((y >= T(0)) ? t : -t)) : T(0);
 }
 
 template <typename T> struct Rot {
@@ -511,35 +510,37 @@ template <typename T> __device__ __forceinline__ void extract_angles(T D[9], T p
 }
 
 // ------------------------------------------------- a-posteriori check -----
-// With B = A - m I (its diagonal d1, d2, d3 and the off-diagonal entries), the
-// deviations mu_k = lam_k - m and the computed D, D^T B D should be diag(mu).
-// Fails when an off-diagonal |(D^T B D)_jk| exceeds lim = tau_res ||A||_F (a
-// residual bound: ||A d_k - lam_k d_k||^2 is the sum of the squares of column
-// k of D^T B D - diag(mu)), when a diagonal entry misses its mu_k by more than
-// lim, or (tau_vec > 0) when |(D^T B D)_jk| / |lam_j - lam_k|, the first-order
-// angle by which d_k leans towards d_j, exceeds tau_vec.  C is the arithmetic
-// type of the check; in float32 its rounding noise is about 1e-7 ||A||_F.
+// With B = A - m I (its diagonal d1, d2, d3 and the off-diagonal entries) and
+// the deviations mu_k = lam_k - m, the residual of column k is
+// r_k = B d_k - mu_k d_k = A d_k - lam_k d_k.  Fails when some ||r_k||^2
+// exceeds lim2 = (tau_res ||A||_F)^2; for orthonormal D, ||r_k|| is the norm
+// of column k of D^T B D - diag(mu), so this covers both a wrong eigenvector
+// (off-diagonal entries) and a wrong pairing with mu_k (diagonal entry).  With
+// tau_vec > 0 it also fails when |d_j^T A d_k| / |lam_j - lam_k|, the
+// first-order angle by which d_k leans towards d_j, exceeds tau_vec.  C is the
+// arithmetic type; in float32 its rounding noise is about 1e-7 ||A||_F.
 template <typename C>
 __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a23, const C d[9],
-                                            C mu1, C mu2, C mu3, C g12, C g13, C g32, C lim,
+                                            C mu1, C mu2, C mu3, C g12, C g13, C g32, C lim2,
                                             C tau_vec) {
-    C Bd[9];
+    const C mu[3] = {mu1, mu2, mu3};
+    C r[9];
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const C x = d[k], y = d[3 + k], z = d[6 + k];
-        Bd[k] = d1 * x + a12 * y + a13 * z;
-        Bd[3 + k] = a12 * x + d2 * y + a23 * z;
-        Bd[6 + k] = a13 * x + a23 * y + d3 * z;
+        r[k] = (d1 - mu[k]) * x + a12 * y + a13 * z;
+        r[3 + k] = a12 * x + (d2 - mu[k]) * y + a23 * z;
+        r[6 + k] = a13 * x + a23 * y + (d3 - mu[k]) * z;
+        const C n2 = r[k] * r[k] + r[3 + k] * r[3 + k] + r[6 + k] * r[6 + k];
+        bad |= !(n2 <= lim2);
     }
-    auto dot = [&](int j, int k) { return d[j] * Bd[k] + d[3 + j] * Bd[3 + k] + d[6 + j] * Bd[6 + k]; };
-    const C B01 = dot(0, 1), B02 = dot(0, 2), B12 = dot(1, 2);
-    const C B00 = dot(0, 0), B11 = dot(1, 1), B22 = dot(2, 2);
-    using M = Mth<C>;
-    bool bad = !(M::fabs(B01) <= lim && M::fabs(B02) <= lim && M::fabs(B12) <= lim);
-    bad |= !(M::fabs(B00 - mu1) <= lim && M::fabs(B11 - mu2) <= lim && M::fabs(B22 - mu3) <= lim);
     if (tau_vec > C(0)) {
-        bad |= !(M::fabs(B01) <= tau_vec * g12 && M::fabs(B02) <= tau_vec * g13 &&
-                 M::fabs(B12) <= tau_vec * g32);
+        using M = Mth<C>;
+        // d_j^T B d_k = d_j^T r_k for j != k (the columns are orthogonal)
+        auto dot = [&](int j, int k) { return d[j] * r[k] + d[3 + j] * r[3 + k] + d[6 + j] * r[6 + k]; };
+        bad |= !(M::fabs(dot(0, 1)) <= tau_vec * g12 && M::fabs(dot(0, 2)) <= tau_vec * g13 &&
+                 M::fabs(dot(1, 2)) <= tau_vec * g32);
     }
     return bad;
 }

@@ -163,16 +163,16 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             o.v[O_GAP + 2] = (T)(cu.g32 * isc);
             o.flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
             if (PATH != PATH_FP64_PLAIN) {
-                const double fro = ::sqrt(a11 * a11 + a22 * a22 + a33 * a33 +
-                                          2.0 * (a12 * a12 + a13 * a13 + a23 * a23));
+                const double fro2 = a11 * a11 + a22 * a22 + a33 * a33 +
+                                    2.0 * (a12 * a12 + a13 * a13 + a23 * a23);
                 const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
                 bool bad = dbl || (split < prm.tau_gap * lmax);
                 double dd[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) dd[i] = (double)o.v[O_D + i];
                 bad = bad || check_fails<double>(cu.d1, cu.d2, cu.d3, a12, a13, a23, dd, cu.mu1, cu.mu2,
-                                                 cu.mu3, cu.g12, cu.g13, cu.g32, prm.tau_res * fro,
-                                                 prm.tau_vec);
+                                                 cu.mu3, cu.g12, cu.g13, cu.g32,
+                                                 prm.tau_res * prm.tau_res * fro2, prm.tau_vec);
                 o.refine = bad;
                 o.lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
             }
@@ -257,11 +257,11 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     build_D(R, D);
 #pragma unroll
     for (int i = 0; i < 9; ++i) sink.put(O_D + i, D[i]);
-    const float fro = __builtin_sqrtf(A11 * A11 + A22 * A22 + A33 * A33 +
-                                      2.0f * (A12 * A12 + A13 * A13 + A23 * A23));
+    const float fro2 = A11 * A11 + A22 * A22 + A33 * A33 + 2.0f * (A12 * A12 + A13 * A13 + A23 * A23);
+    const float tr = (float)prm.tau_res;
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                     (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
-                                    (float)prm.tau_res * fro, (float)prm.tau_vec);
+                                    tr * tr * fro2, (float)prm.tau_vec);
     const int flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
     sink.flag(flag);
     refine = bad;
