@@ -153,12 +153,6 @@ __device__ __forceinline__ double sin_fast(double t) {
     return __builtin_fma(t * t2, (double)S, t);
 }
 
-__device__ __forceinline__ double cos_fast(double t) {
-    const double t2 = t * t;
-    const float C = tail_poly(poly::CT, 4, (float)t2);
-    return __builtin_fma(t2 * t2, (double)C, __builtin_fma(t2, -0.5, 1.0));
-}
-
 // atan2(y, x) in float32: reduce to t = min(|x|,|y|)/max(|x|,|y|) in [0, 1],
 // atan t = t + t^3 Q(t^2), then fold the octant; y = -0 counts as +0, so the
 // result lies in (-pi, pi].
@@ -269,7 +263,8 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
 // t = Delta/3 and of pi/3 - t = (pi - Delta)/3, so each is accurate to ~1e-8
 // relative even when two eigenvalues nearly coincide:
 //   lam3 - lam2 = (2/sqrt3) sqrt(p) sin t,  lam1 - lam3 = (2/sqrt3) sqrt(p) sin(pi/3 - t),
-//   lam1 - lam2 = their sum;  mu1 = (2/3) sqrt(p) cos t, mu2 = mu1 - g12, mu3 = mu1 - g13.
+//   lam1 - lam2 = their sum;  mu1 = (2 g13 + g32) / 3 (the deviations sum to zero),
+//   mu2 = mu1 - g12, mu3 = mu1 - g13.
 __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double a33, double a12,
                                                   double a13, double a23) {
     Cubic c;
@@ -292,7 +287,9 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
     c.g32 = k * sin_fast(t);
     c.g13 = k * sin_fast(tc);
     c.g12 = c.g13 + c.g32;
-    c.mu1 = (2.0 / 3.0) * sp * cos_fast(t);
+    // mu1 + mu2 + mu3 = 0 with mu1 - mu2 = g12, mu1 - mu3 = g13 (a sum of
+    // non-negative terms, so no cancellation)
+    c.mu1 = (2.0 * c.g13 + c.g32) * (1.0 / 3.0);
     c.mu2 = c.mu1 - c.g12;
     c.mu3 = c.mu1 - c.g13;
     c.sp = sp;
@@ -363,28 +360,38 @@ __device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, d
 // sign combination only flips signs inside g1 = (s3*alpha, s2*beta) and
 // g2 = (gamma, s2*s3*delta) of (5.7)-(5.8).  phi1(1) = arg(conj(f1) g1) and
 // 2 phi1(2) = arg(conj(f2) g2) (the angle from f to g, (5.11)-(5.14)), so
-// e^{i phi1(2)} is the principal square root of conj(f2) g2 / |.|.  The
-// combination with the smallest circular distance |phi1(1) - phi1(2)| is the
-// one with the largest Re(z1 conj(sqrt z2)), where the norms |z1| = |f1||g1|,
-// |z2| = |f2||g2| do not depend on the signs.  Ties keep the first of
-// (+,+), (+,-), (-,+), (-,-).  phi1 is phi1(1) when |f1| >= |f2| and phi1(2)
-// otherwise (5.15); its cosine and sine come from normalising z1 or sqrt z2.
+// e^{i phi1(2)} is the principal square root of z2 / |z2|, z2 = conj(f2) g2.
+// The combination with the smallest circular distance Delta = |phi1(1) -
+// phi1(2)| has the largest cos(Delta).  Flipping both signs negates z1 and
+// keeps z2, so the two combinations of one product s2*s3 have cos(Delta) of
+// opposite signs, and the choice splits in two:
+//  - the product is the one with the larger cos^2(Delta), i.e. the larger
+//    cos(2 Delta) = Re(z1^2 conj z2) / (|z1|^2 |z2|), where the norms
+//    |z1| = |f1||g1|, |z2| = |f2||g2| do not depend on the signs.  Expanding
+//    z1 = conj(f1) (alpha +- i beta'), z2 = conj(f2) (gamma +- i delta') and
+//    using cos^2 + sin^2 = 1 for both angles, the difference between the two
+//    products is exactly
+//      Re(z+^2 conj z+) - Re(z-^2 conj z-) = 8 K G12 G13 G32 c2^2 c3 |s2 s3|,
+//      K = A12 A13 (A22 - A33) - A23 (A12^2 - A13^2),
+//    so the product is +1 when K >= 0 and -1 otherwise (a tie keeps the
+//    first, +1).  K depends on the entries of A alone: the caller evaluates
+//    it in float64, where its sign stays reliable down to gaps near the
+//    float64 rounding level, while the two scores themselves differ only
+//    by an amount proportional to the gaps;
+//  - the overall sign makes Re(z1 conj h) >= 0, where h is a non-negative
+//    multiple of the principal root: h = (|z2| + x, y) for x >= 0 and
+//    (|y|, +-(|z2| - x)) for x < 0 (y = +-0 on the negative axis gives +i).
+//    The two overall signs give D and D diag(1, -1, -1), so this choice
+//    fixes the convention, not the accuracy.
+// phi1 is phi1(1) when |f1| >= |f2| and phi1(2) otherwise (5.15); its cosine
+// and sine come from normalising +-z1 or h.
 // The brackets of (5.7)-(5.8) are rearranged with w + (1 - w) = 1 and
 // v + (1 - v) = 1 so that no difference of nearly equal terms is formed:
 //   (lam1 - lam2) w + lam2 - lam3 = G13 w - G32 (1 - w),
 //   1 + (v - 2) w = (1 - w) - w (1 - v).
-template <typename T>
-__device__ __forceinline__ void csqrt_principal(T x, T y, T& rx, T& ry) {
-    using M = Mth<T>;
-    // t = sqrt((|z| + |x|) / 2) is the larger component of the root, u = y / (2t)
-    // the other: (t, u) in the right half plane, (|u|, +-t) in the left, where
-    // y = +-0 on the negative axis gives +i (arg = +pi).  Branch-free.
-    const T m = M::sqrt(x * x + y * y);
-    const T t = M::sqrt(T(0.5) * (m + M::fabs(x)));
-    const T u = T(0.5) * y * M::rcp(t);
-    const bool right = x >= T(0), nz = m > T(0);
-    rx = nz ? (right ? t : M::fabs(u)) : T(0);
-    ry = nz ? (right ? u : ((y >= T(0)) ? t : -t)) : T(0);
+__device__ __forceinline__ double product_key(double a12, double a13, double a22, double a33,
+                                              double a23) {
+    return __builtin_fma(a12 * a13, a22 - a33, -a23 * __builtin_fma(a12, a12, -a13 * a13));
 }
 
 template <typename T> struct Rot {
@@ -393,46 +400,31 @@ template <typename T> struct Rot {
 
 template <typename T>
 __device__ __forceinline__ Rot<T> select_angles(T a12, T a13, T a22, T a33, T a23, T G12, T G13, T G32,
-                                                T v, T s2sq, T w, T cw) {
+                                                T v, T s2sq, T w, T cw, bool plus) {
     using M = Mth<T>;
     Rot<T> R;
     const T c2 = M::sqrt(v), s2 = M::sqrt(s2sq);
     const T c3 = M::sqrt(w), s3 = M::sqrt(cw);
     // g1 = (s3 al, s2 be), g2 = (ga, s2 s3 de), from (5.7)-(5.8) with
-    // sin(2 phi) = 2 sin(phi) cos(phi)
-    const T al = G12 * c2 * s3 * c3;
+    // sin(2 phi) = 2 sin(phi) cos(phi); the product's sign t is folded into
+    // al and de, so z1 = conj(f1) (t al + i be), z2 = conj(f2) (ga + i t de)
+    const T t = plus ? T(1) : T(-1);
+    const T al = t * G12 * c2 * s3 * c3;
     const T be = (G13 * w - G32 * cw) * s2 * c2;
     const T ga = G12 * (cw - w * s2sq) - G32 * v;
-    const T de = T(2) * G12 * s2 * s3 * c3;
+    const T de = t * T(2) * G12 * s2 * s3 * c3;
     // conj(f1) = (a12, a13), conj(f2) = (a22 - a33, 2 a23), from (5.5)-(5.6)
     const T e = a22 - a33, f = T(2) * a23;
-    const T P1x = al * a12, P1y = al * a13;     // conj(f1) * al
-    const T Q1x = -be * a13, Q1y = be * a12;    // conj(f1) * i be
-    const T P2x = ga * e, P2y = ga * f;         // conj(f2) * ga
-    const T Q2x = -de * f, Q2y = de * e;        // conj(f2) * i de
-    T Rpx, Rpy, Rmx, Rmy;
-    csqrt_principal<T>(P2x + Q2x, P2y + Q2y, Rpx, Rpy);   // s2 s3 = +1
-    csqrt_principal<T>(P2x - Q2x, P2y - Q2y, Rmx, Rmy);   // s2 s3 = -1
-    const T sa = P1x * Rpx + P1y * Rpy, sb = Q1x * Rpx + Q1y * Rpy;
-    const T sc = P1x * Rmx + P1y * Rmy, sd = Q1x * Rmx + Q1y * Rmy;
-    const T Spp = sa + sb, Spm = sd - sc;   // S(-,+) = -Spm, S(-,-) = -Spp
-    int sel = 0;
-    T best = Spp;
-    if (Spm > best) { best = Spm; sel = 1; }
-    if (-Spm > best) { best = -Spm; sel = 2; }
-    if (-Spp > best) { sel = 3; }
-    const T sg2 = (sel >= 2) ? T(-1) : T(1);
-    const T sg3 = (sel & 1) ? T(-1) : T(1);
-    const bool plus = (sel == 0) || (sel == 3);
+    const T zx = al * a12 - be * a13, zy = al * a13 + be * a12;
+    const T wx = ga * e - de * f, wy = ga * f + de * e;
+    const T m2 = M::sqrt(wx * wx + wy * wy);
+    const bool right = wx >= T(0);
+    const T hx = right ? m2 + wx : M::fabs(wy);
+    const T hy = right ? wy : ((wy >= T(0)) ? m2 - wx : wx - m2);
+    const T sg = (zx * hx + zy * hy >= T(0)) ? T(1) : T(-1);
     const T f1sq = a12 * a12 + a13 * a13, f2sq = e * e + f * f;
-    T ux, uy;
-    if (f1sq >= f2sq) {
-        ux = sg3 * P1x + sg2 * Q1x;
-        uy = sg3 * P1y + sg2 * Q1y;
-    } else {
-        ux = plus ? Rpx : Rmx;
-        uy = plus ? Rpy : Rmy;
-    }
+    const bool use1 = f1sq >= f2sq;
+    const T ux = use1 ? sg * zx : hx, uy = use1 ? sg * zy : hy;
     const T nn = ux * ux + uy * uy;
     if (nn > T(0)) {
         const T inv = M::rsqrt(nn);
@@ -442,8 +434,8 @@ __device__ __forceinline__ Rot<T> select_angles(T a12, T a13, T a22, T a33, T a2
         R.c1 = T(1);
         R.s1 = T(0);
     }
-    R.c2 = c2; R.s2 = sg2 * s2;
-    R.c3 = c3; R.s3 = sg3 * s3;
+    R.c2 = c2; R.s2 = sg * s2;
+    R.c3 = c3; R.s3 = t * sg * s3;
     return R;
 }
 

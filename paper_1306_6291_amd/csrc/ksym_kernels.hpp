@@ -112,8 +112,9 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             if (cu.g13 < cu.g32) { lm = 0.5 * (cu.mu1 + cu.mu3); ls = cu.mu2; }
             else { lm = 0.5 * (cu.mu3 + cu.mu2); ls = cu.mu1; }
             const T s = clamp01((T)((cu.d1 - ls) / (lm - ls)));
+            // (G12 = 0, phi3 = 0: both products score alike; the first is kept)
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, T(0), (T)(lm - ls), (T)(ls - lm), s,
-                                              T(1) - s, T(1), T(0));
+                                              T(1) - s, T(1), T(0), true);
             T Di[9];
             build_D(R, Di);
             double L[3];
@@ -152,7 +153,8 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
                 const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a12, a13);
                 v = (T)u.v; s2sq = (T)u.s2sq; w = (T)u.w; cw = (T)u.cw;
             }
-            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw);
+            const bool plus = !(product_key(a12, a13, a22, a33, a23) < 0.0);
+            const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
             build_D(R, o.v + O_D);
             angles_of(R, o.v + O_PHI);
             o.v[O_LAM] = (T)((cu.m + cu.mu1) * isc);
@@ -247,8 +249,9 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const float A11 = (float)a[0], A22 = (float)a[1], A33 = (float)a[2];
     const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
     const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
+    const bool plus = !(product_key(a[3], a[4], a[1], a[2], a[5]) < 0.0);
     const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32,
-                                              (float)u.v, (float)u.s2sq, (float)u.w, (float)u.cw);
+                                              (float)u.v, (float)u.s2sq, (float)u.w, (float)u.cw, plus);
     float phi[3];
     angles_of(R, phi);
 #pragma unroll
