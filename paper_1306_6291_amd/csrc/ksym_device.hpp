@@ -62,8 +62,7 @@ __device__ __forceinline__ int scale_exponent(double amax) {
 // Coefficients and their derivation: ksym_poly.hpp / gen_poly.py.
 
 // 1/sqrt(x) for normal x > 0: hardware estimate (about 23 bits) refined by
-// NEWTON Newton steps; two give full float64 accuracy, one about 2^-44, which
-// is what the float32 path needs.
+// NEWTON Newton steps; two give full float64 accuracy, one about 2^-44.
 template <int NEWTON = 2> __device__ __forceinline__ double rsqrt64(double x) {
     double y = __builtin_amdgcn_rsq(x);
 #pragma unroll
@@ -116,11 +115,10 @@ __device__ __forceinline__ void sincos_third(double t, double &s, double &c) {
     c = pc;
 }
 
-// Float32-tail versions for the float32 path: the leading terms are formed in
-// float64 and only the small correction (at most 5-18 % of the result) in
-// float32, with coefficients that are literal operands.  Relative accuracy
-// about 1e-8, which is what float32 results need, while the float64 argument
-// keeps the sqrt(eps) amplification of arccos near |r| = 1 at float64 level.
+// Float32-tail versions for the cubic stage of the float32 path: the first
+// two terms of each series are formed in float64 and only the remainder (at
+// most 1.2 % of the value) in float32, with coefficients that are literal
+// operands; relative accuracy a few 1e-10.
 __device__ __forceinline__ float tail_poly(const float *c, int deg, float t) {
     float p = c[deg];
 #pragma unroll
@@ -129,28 +127,29 @@ __device__ __forceinline__ float tail_poly(const float *c, int deg, float t) {
 }
 
 // arccos(r) and pi - arccos(r), each formed without cancellation.
-__device__ __forceinline__ void acos_pair_fast(double r, double &D, double &Dc) {
+__device__ __forceinline__ void acos_pair(double r, double &D, double &Dc) {
     const double ar = __builtin_fabs(r);
     const bool small = ar <= 0.5;
     const double z = small ? ar * ar : 0.5 * (1.0 - ar);
     const double x = small ? ar : sqrt_small64<1>(z);
-    const float P = tail_poly(poly::AT, 6, (float)z);
-    const double a = __builtin_fma(x * z, (double)P, x);   // asin(x)
+    const double T = (double)tail_poly(poly::AT, 6, (float)z);
+    const double a = __builtin_fma(x * z, __builtin_fma(z, T, 1.0 / 6.0), x);   // asin(x)
     if (small) {
-        const double sa = r < 0.0 ? -a : a;                  // asin(r)
+        const double sa = r < 0.0 ? -a : a;        // asin(r)
         D = 0.5 * kPi - sa;
         Dc = 0.5 * kPi + sa;
     } else {
-        const double b = 2.0 * a;                            // acos(|r|)
+        const double b = 2.0 * a;                  // acos(|r|)
         D = r < 0.0 ? kPi - b : b;
         Dc = r < 0.0 ? b : kPi - b;
     }
 }
 
-__device__ __forceinline__ double sin_fast(double t) {
+// sin t for t in [0, pi/3].
+__device__ __forceinline__ double sin_third(double t) {
     const double t2 = t * t;
-    const float S = tail_poly(poly::ST, 4, (float)t2);
-    return __builtin_fma(t * t2, (double)S, t);
+    const double T = (double)tail_poly(poly::ST, 3, (float)t2);
+    return __builtin_fma(t * t2, __builtin_fma(t2, T, -1.0 / 6.0), t);
 }
 
 // atan2(y, x) in float32: reduce to t = min(|x|,|y|)/max(|x|,|y|) in [0, 1],
@@ -259,13 +258,18 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
 }
 
 // The cubic stage of the float32 path: the same quantities as cubic_stage,
-// with the float32-tail arccos / sin / cos.  The three gaps come from sines of
-// t = Delta/3 and of pi/3 - t = (pi - Delta)/3, so each is accurate to ~1e-8
-// relative even when two eigenvalues nearly coincide:
+// with the three gaps from sines of t = Delta/3 and of pi/3 - t = (pi -
+// Delta)/3, so each gap keeps its relative accuracy even when two eigenvalues
+// nearly coincide:
 //   lam3 - lam2 = (2/sqrt3) sqrt(p) sin t,  lam1 - lam3 = (2/sqrt3) sqrt(p) sin(pi/3 - t),
 //   lam1 - lam2 = their sum;  mu1 = (2 g13 + g32) / 3 (the deviations sum to zero),
 //   mu2 = mu1 - g12, mu3 = mu1 - g13.
-__device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double a33, double a12,
+// The arithmetic is float64 with float32 polynomial tails (relative accuracy
+// a few 1e-10): the squared direction cosines formed from these deviations
+// (u_quotients) can be differences of nearly equal terms, and their square
+// roots turn an absolute error e into one of sqrt(e), so eigenvalues good to
+// only 1e-8 would leave errors near 1e-4 in D.
+__device__ __forceinline__ Cubic cubic_stage_gaps(double a11, double a22, double a33, double a12,
                                                   double a13, double a23) {
     Cubic c;
     center3(a11, a22, a33, c.m, c.d1, c.d2, c.d3);
@@ -281,11 +285,11 @@ __device__ __forceinline__ Cubic cubic_stage_fast(double a11, double a22, double
     double r = 13.5 * det * (ip * ip * ip);        // 27 det / (2 sqrt(p)^3)
     r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
     double D, Dc;
-    acos_pair_fast(r, D, Dc);
+    acos_pair(r, D, Dc);
     const double t = D * (1.0 / 3.0), tc = Dc * (1.0 / 3.0);
     const double k = (2.0 * kInvSqrt3) * sp;
-    c.g32 = k * sin_fast(t);
-    c.g13 = k * sin_fast(tc);
+    c.g32 = k * sin_third(t);
+    c.g13 = k * sin_third(tc);
     c.g12 = c.g13 + c.g32;
     // mu1 + mu2 + mu3 = 0 with mu1 - mu2 = g12, mu1 - mu3 = g13 (a sum of
     // non-negative terms, so no cancellation)

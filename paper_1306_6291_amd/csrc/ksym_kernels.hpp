@@ -211,7 +211,7 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     double a[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;   // non-finite: handled below
-    const Cubic cu = cubic_stage_fast(a[0], a[1], a[2], a[3], a[4], a[5]);
+    const Cubic cu = cubic_stage_gaps(a[0], a[1], a[2], a[3], a[4], a[5]);
     refine = false;
     lc = 0.0;
     if (cu.triple || !fin) {
