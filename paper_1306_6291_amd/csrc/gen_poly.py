@@ -13,6 +13,9 @@ rounded to the target precision):
   rho^-k).
 * atan(x) = x + x t Q(t), t = x^2, x in [0, 1] (float32): Q interpolates
   (atan(sqrt t)/sqrt t - 1)/t at the Chebyshev points of [0, 1].
+* asin(x) = x + x z R(z), z = x^2, x in [0, 1/sqrt 2] (float32): R interpolates
+  (asin(sqrt z)/sqrt z - 1)/z at the Chebyshev points of [0, 1/2] (the angles
+  phi2, phi3 of the float32 path from their squared sines and cosines).
 * float32 tails for the cubic stage of the float32 path, where the first two
   terms of the series are formed in float64 and only the remainder (at most
   1.2 % of sin, 0.5 % of asin on their intervals) in float32:
@@ -118,6 +121,18 @@ def tail(kind, deg):
     return c, err
 
 
+def asin_f32_poly(deg):
+    def f(z):
+        if z == 0:
+            return mp.mpf(1) / 6
+        s = mp.sqrt(z)
+        return (mp.asin(s) / s - 1) / z
+    c = [f32(v) for v in cheb_interp(f, mp.mpf(0), mp.mpf(1) / 2, deg)]
+    err = max_rel_err(lambda x: x + x * x * x * horner([mp.mpf(v) for v in c], x * x),
+                      mp.asin, mp.mpf(0), mp.sqrt(mp.mpf(1) / 2), npts=801)
+    return c, err
+
+
 def f32(v):
     import struct
     return struct.unpack("f", struct.pack("f", float(v)))[0]
@@ -136,6 +151,7 @@ def main():
     sin_c, cos_c, tb = taylor_sin_cos()
     asin_c, asin_err = asin_poly(11)
     atan_c, atan_err = atan_poly(8)
+    asf_c, asf_err = asin_f32_poly(7)
     st_c, st_err = tail("sin", 3)
     at_c, at_err = tail("asin", 6)
     out = []
@@ -153,6 +169,9 @@ def main():
     out.append(f"// atan x = x + x t Q(t), t = x^2, x in [0, 1]; Chebyshev interpolant rounded to float, "
                f"max relative error {float(atan_err):.2e}")
     out.append("constexpr float ATAN[%d] = {%s};" % (len(atan_c), ", ".join(repr(v) + "f" for v in atan_c)))
+    out.append(f"// asin x = x + x z R(z), z = x^2, x in [0, 1/sqrt 2]; Chebyshev interpolant rounded to float, "
+               f"max relative error {float(asf_err):.2e}")
+    out.append("constexpr float ASINF[%d] = {%s};" % (len(asf_c), ", ".join(repr(v) + "f" for v in asf_c)))
     out.append(f"// float32 tails: sin x = x - x^3/6 + x^5 ST(x^2), max rel err {float(st_err):.1e}; "
                f"asin x = x + x^3/6 + x^5 AT(x^2), {float(at_err):.1e}")
     out.append("constexpr float ST[%d] = {%s};" % (len(st_c), ", ".join(repr(v) + "f" for v in st_c)))

@@ -203,6 +203,7 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     a.prm.tau_dbl = o.tau_dbl;
     a.prm.drain_tiles = o.drain_tiles;
     a.prm.counters = (unsigned *)ws;
+    finish_params(a.prm);
     (void)ws_bytes;
     void (*k)(Eig3Args<T>) = nullptr;
     if constexpr (sizeof(T) == 4) {
@@ -603,6 +604,7 @@ ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
         a.prm.tau_dbl = p->opts.tau_dbl;
         a.prm.drain_tiles = p->opts.drain_tiles;
         a.prm.counters = (unsigned *)ws;
+        finish_params(a.prm);
         MixK<T> k = pick_mixed<T>(p->opts.block, p->opts.mats_per_lane);
         hipError_t e = launch(k, dim3(p->grid), dim3(p->opts.block), st, a);
         if (e != hipSuccess) return hip_fail(e, "launch k_mixed");

@@ -169,18 +169,18 @@ __device__ __forceinline__ float atan2_fast(float y, float x) {
     return (y < 0.0f) ? -a : a;
 }
 
-// atan2(y, x) for x >= 0 (the right half plane), same polynomial as atan2_fast.
-__device__ __forceinline__ float atan2_right(float y, float x) {
-    const float ay = __builtin_fabsf(y);
-    const float mn = __builtin_fminf(x, ay), mx = __builtin_fmaxf(x, ay);
-    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
-    const float t2 = t * t;
-    float Q = poly::ATAN[8];
+// The angle in [0, pi/2] whose sine and cosine are s, c >= 0, given also
+// their squares s2q and c2q (s2q + c2q = 1): the arcsine of the smaller of
+// the two, so the series argument stays in [0, 1/2] and no reciprocal is
+// needed; asin x = x + x^3 R(x^2).
+__device__ __forceinline__ float angle_from_squares(float s, float s2q, float c, float c2q) {
+    const bool lo = s2q <= c2q;
+    const float x = lo ? s : c, z = lo ? s2q : c2q;
+    float R = poly::ASINF[7];
 #pragma unroll
-    for (int k = 7; k >= 0; --k) Q = __builtin_fmaf(Q, t2, poly::ATAN[k]);
-    float a = __builtin_fmaf(t * t2, Q, t);
-    a = (ay > x) ? 1.57079632679489662f - a : a;
-    return (y < 0.0f) ? -a : a;
+    for (int k = 6; k >= 0; --k) R = __builtin_fmaf(R, z, poly::ASINF[k]);
+    const float a = __builtin_fmaf(x * z, R, x);
+    return lo ? a : 1.57079632679489662f - a;
 }
 
 // ----------------------------------------------------- 3x3 cubic stage -----
@@ -332,15 +332,6 @@ struct URow {
     double v, s2sq, w, cw;   // cos^2 phi2, sin^2 phi2, cos^2 phi3, sin^2 phi3
 };
 
-template <int NEWTON> __device__ __forceinline__ void split_unit(double p, double q, double &x, double &y) {
-    p = p > 0.0 ? p : 0.0;
-    q = q > 0.0 ? q : 0.0;
-    const double t = p + q;
-    const bool pos = t > 0.0;
-    const double r = rcp64<NEWTON>(pos ? t : 1.0);
-    x = pos ? p * r : 1.0;
-    y = pos ? q * r : 0.0;
-}
 
 // NEWTON = 1 is enough when the quotients are rounded to float32.
 template <int NEWTON = 2>
@@ -349,9 +340,18 @@ __device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, d
     const double F = a12 * a12 + a13 * a13;
     const double e1 = d1 - mu1, e2 = d1 - mu2, e3 = d1 - mu3;
     URow u;
-    split_unit<NEWTON>(F + e3 * (e1 + g32), -(F + e1 * e2), u.v, u.s2sq);
-    // v = 0 gives w = 1, the paper's convention
-    split_unit<NEWTON>((F + e2 * e3) * g32, (F + e1 * e3) * g13, u.w, u.cw);
+    const double pv = fmax(F + e3 * (e1 + g32), 0.0), qv = fmax(-(F + e1 * e2), 0.0);
+    const double pw = fmax((F + e2 * e3) * g32, 0.0), qw = fmax((F + e1 * e3) * g13, 0.0);
+    // an empty pair gives (1, 0); v = 0 gives w = 1, the paper's convention
+    const double tv = pv + qv, tw = pw + qw;
+    const bool okv = tv > 0.0, okw = tw > 0.0;
+    const double Tv = okv ? tv : 1.0, Tw = okw ? tw : 1.0;
+    const double r = rcp64<NEWTON>(Tv * Tw);   // one reciprocal for both pairs
+    const double rv = Tw * r, rw = Tv * r;
+    u.v = okv ? pv * rv : 1.0;
+    u.s2sq = okv ? qv * rv : 0.0;
+    u.w = okw ? pw * rw : 1.0;
+    u.cw = okw ? qw * rw : 0.0;
     return u;
 }
 
@@ -457,18 +457,24 @@ template <typename T> __device__ __forceinline__ void build_D(const Rot<T>& R, T
     D[8] = R.c1 * R.c2;
 }
 
-// phi2 and phi3 have non-negative cosines (c2 = sqrt(v), c3 = sqrt(w)), which
-// saves the quadrant fold of a general atan2 in float32.
 template <typename T> __device__ __forceinline__ void angles_of(const Rot<T>& R, T phi[3]) {
     using M = Mth<T>;
     phi[0] = M::atan2(R.s1, R.c1);
-    if constexpr (sizeof(T) == 4) {
-        phi[1] = atan2_right(R.s2, R.c2);
-        phi[2] = atan2_right(R.s3, R.c3);
-    } else {
-        phi[1] = M::atan2(R.s2, R.c2);
-        phi[2] = M::atan2(R.s3, R.c3);
-    }
+    phi[1] = M::atan2(R.s2, R.c2);
+    phi[2] = M::atan2(R.s3, R.c3);
+}
+
+// float32: phi2 and phi3 lie in [-pi/2, pi/2] (non-negative cosines c2 =
+// sqrt(v), c3 = sqrt(w)), so each is +-asin of the smaller of its sine and
+// cosine, from the squared values the angle solve already has; a sine of -0
+// gives +0 like the general atan2.
+__device__ __forceinline__ void angles_of(const Rot<float>& R, float v, float s2sq, float w, float cw,
+                                          float phi[3]) {
+    phi[0] = atan2_fast(R.s1, R.c1);
+    const float t2 = angle_from_squares(__builtin_fabsf(R.s2), s2sq, R.c2, v);
+    const float t3 = angle_from_squares(__builtin_fabsf(R.s3), cw, R.c3, w);
+    phi[1] = R.s2 < 0.0f ? -t2 : t2;
+    phi[2] = R.s3 < 0.0f ? -t3 : t3;
 }
 
 // Angles of a rotation D (det +1) with D = R1 R2 R3: phi1 from the third

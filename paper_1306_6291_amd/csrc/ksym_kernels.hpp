@@ -55,7 +55,17 @@ struct Eig3Params {
     unsigned *counters;   // [0] refined, [1] non-finite; may be null
     int32_t zero;         // always 0; see put3
     int32_t drain_tiles;  // queue age limit in wave tiles (0 = full waves only)
+    // the float32 check's thresholds, rounded once on the host so that they
+    // stay scalar operands: (float)tau_res squared in float, (float)tau_vec
+    float tau_res2_f, tau_vec_f;
 };
+
+// Fills the float32 thresholds of a parameter block whose double fields are set.
+__host__ inline void finish_params(Eig3Params &prm) {
+    const float tr = (float)prm.tau_res;
+    prm.tau_res2_f = tr * tr;
+    prm.tau_vec_f = (float)prm.tau_vec;
+}
 
 template <typename T> struct Eig3Args {
     Eig3Ptrs<T> p;
@@ -212,36 +222,26 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
 #pragma unroll
     for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;   // non-finite: handled below
     const Cubic cu = cubic_stage_gaps(a[0], a[1], a[2], a[3], a[4], a[5]);
-    refine = false;
     lc = 0.0;
-    if (cu.triple || !fin) {
-        // §5, p = 0: A = lam I, D = I, angles 0 (non-finite input: all NaN)
-        const float nan = __builtin_nanf("");
-        const float lam = fin ? (float)(cu.m * isc) : nan;
-        const float one = fin ? 1.0f : nan, zero = fin ? 0.0f : nan;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) sink.put(O_LAM + k, lam);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) sink.put(O_D + i, (i % 4 == 0) ? one : zero);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            sink.put(O_PHI + k, zero);
-            sink.put(O_GAP + k, zero);
-        }
-        const int flag = fin ? FLAG_TRIPLE : FLAG_NONFINITE;
-        sink.flag(flag);
-        return flag;
-    }
+    const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
+    const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
+    // p = 0 (A = lam I, §5) and non-finite input: the general path below
+    // still runs (it cannot fault, and its stores are provisional) and the
+    // matrix is queued; the drain writes the special outputs.  Keeping every
+    // store on the one straight path lets the compiler count the memory
+    // operations in flight exactly, instead of assuming a path without
+    // stores and waiting for the prefetched inputs at every tile.
+    const bool special = cu.triple || !fin;
+    const int flag = special ? (fin ? FLAG_TRIPLE : FLAG_NONFINITE) : (dbl ? FLAG_DOUBLE : FLAG_GENERAL);
+    sink.flag(flag);
     sink.put(O_LAM, (float)((cu.m + cu.mu1) * isc));
     sink.put(O_LAM + 1, (float)((cu.m + cu.mu2) * isc));
     sink.put(O_LAM + 2, (float)((cu.m + cu.mu3) * isc));
     sink.put(O_GAP, (float)(cu.g12 * isc));
     sink.put(O_GAP + 1, (float)(cu.g13 * isc));
     sink.put(O_GAP + 2, (float)(cu.g32 * isc));
-    const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
-    const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
     const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
-    bool bad = dbl || (split < prm.tau_gap * (l1 > l2 ? l1 : l2));
+    bool bad = special || dbl || (split < prm.tau_gap * (l1 > l2 ? l1 : l2));
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
     // general branch (5.1)-(5.15): the four squared cosines and sines as
     // float64 quotients (u_quotients), the rest of the angle solve in float32
@@ -250,10 +250,10 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
     const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
     const bool plus = !(product_key(a[3], a[4], a[1], a[2], a[5]) < 0.0);
-    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32,
-                                              (float)u.v, (float)u.s2sq, (float)u.w, (float)u.cw, plus);
+    const float v = (float)u.v, s2sq = (float)u.s2sq, w = (float)u.w, cw = (float)u.cw;
+    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
     float phi[3];
-    angles_of(R, phi);
+    angles_of(R, v, s2sq, w, cw, phi);
 #pragma unroll
     for (int k = 0; k < 3; ++k) sink.put(O_PHI + k, phi[k]);
     float D[9];
@@ -261,19 +261,20 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
 #pragma unroll
     for (int i = 0; i < 9; ++i) sink.put(O_D + i, D[i]);
     const float fro2 = A11 * A11 + A22 * A22 + A33 * A33 + 2.0f * (A12 * A12 + A13 * A13 + A23 * A23);
-    const float tr = (float)prm.tau_res;
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                     (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
-                                    tr * tr * fro2, (float)prm.tau_vec);
-    const int flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
-    sink.flag(flag);
+                                    prm.tau_res2_f * fro2, prm.tau_vec_f);
     refine = bad;
     return flag;
 }
 
 // The refinement of one queued matrix (original entries ain, isolated
 // eigenvalue lc as a deviation from the centre, in the scaled units eig3_one
-// used; the centre is recomputed here with the same arithmetic).
+// used; the centre is recomputed here with the same arithmetic).  A matrix
+// queued with the p = 0 or the non-finite flag (float32 path) gets the
+// special outputs instead: lam = the centre m, D = I, angles and gaps 0, or
+// all NaN; the refinement's arithmetic is harmless for those inputs.
+__device__ __forceinline__ bool is_special(int flag) { return flag == FLAG_TRIPLE || flag == FLAG_NONFINITE; }
 template <typename T>
 __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, Out3<T> &o) {
     double amax = 0.0;
@@ -294,6 +295,20 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
     o.v[O_GAP + 1] = (T)(fmax(rf.lam[0] - rf.lam[2], 0.0) * isc);
     o.v[O_GAP + 2] = (T)(fmax(rf.lam[2] - rf.lam[1], 0.0) * isc);
     o.flag = flag | FLAG_FIXUP;
+    if (is_special(flag)) {
+        const bool fin = flag != FLAG_NONFINITE;
+        const T nan = (T)__builtin_nan("");
+        const T lam = fin ? (T)(m * isc) : nan, one = fin ? T(1) : nan, zero = fin ? T(0) : nan;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o.v[O_LAM + k] = lam;
+            o.v[O_PHI + k] = zero;
+            o.v[O_GAP + k] = zero;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o.v[O_D + i] = (i % 4 == 0) ? one : zero;
+        o.flag = flag;
+    }
 }
 
 // ------------------------------------------------------ per-wave tiles -----
@@ -508,23 +523,26 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &
     }
 }
 
-// Refine the first `cnt` (<= 64) queue entries, entry j on lane j, and
+// Finish the first `cnt` (<= 64) queue entries, entry j on lane j, and
 // overwrite their provisional outputs.  The wave's own provisional stores are
-// waited for first, so a refined value always lands last.
+// waited for first, so a final value always lands last.  Returns the number
+// of refined (not special) entries.
 template <typename T, int CAP, typename PlanesOf>
-__device__ __forceinline__ void drain_wave(WaveQueue<T, CAP> *q, int cnt, const PlanesOf &planes_of,
-                                           int salt) {
+__device__ __forceinline__ unsigned drain_wave(WaveQueue<T, CAP> *q, int cnt, const PlanesOf &planes_of,
+                                               int salt) {
     __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): earlier stores of this wave have completed
     const int lane = lane_id();
+    const int g = lane < cnt ? q->grp[lane] : 0;
+    const bool ref = lane < cnt && !is_special(g >> 24);
     if (lane < cnt) {
         T a[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] = q->a[c][lane];
-        const int g = q->grp[lane];
         Out3<T> o;
         refine_one<T>(a, q->lc[lane], g >> 24, o);
         write_out3(planes_of(g & 0xffffff), salt, q->off[lane], o);
     }
+    return (unsigned)__popcll(__ballot(ref));
 }
 
 // Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
@@ -603,8 +621,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         while (qn >= WAVE || (qn > 0 && prm.drain_tiles > 0 && qage >= prm.drain_tiles)) {
             const int cnt = qn < WAVE ? qn : WAVE;
             wave_sync();
-            drain_wave<T>(&sm->q, cnt, planes_of, (int)(base * (uint32_t)prm.zero));
-            refined += (unsigned)cnt;
+            refined += drain_wave<T>(&sm->q, cnt, planes_of, (int)(base * (uint32_t)prm.zero));
             const int rest = qn - cnt;
             // move entries [cnt, qn) to the front; a lane reads only entries
             // no lane writes in the same round
@@ -650,8 +667,7 @@ __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<
     const int total = pre[NW];
     for (int r = w; r * WAVE < total; r += NW) {
         const int e = r * WAVE + lane;
-        const int cnt = total - r * WAVE < WAVE ? total - r * WAVE : WAVE;
-        refined += (unsigned)cnt;
+        bool ref = false;
         if (e < total) {
             int src = 0;
 #pragma unroll
@@ -662,10 +678,12 @@ __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<
 #pragma unroll
             for (int c = 0; c < 6; ++c) a[c] = q->a[c][i];
             const int g = q->grp[i];
+            ref = !is_special(g >> 24);
             Out3<T> o;
             refine_one<T>(a, q->lc[i], g >> 24, o);
             write_out3(planes_of(g & 0xffffff), 0, q->off[i], o);
         }
+        refined += (unsigned)__popcll(__ballot(ref));
     }
 }
 
@@ -705,13 +723,23 @@ void k_eig3(Eig3Args<T> args) {
         return KernargInputs<T>{(uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, in)),
                                 (uint32_t)offsetof(Eig3Args<T>, aos), (int)(tt * (uint32_t)args.prm.zero)};
     };
-    if (t < ntiles) load_wtile3<T, MPL, AOS>(cur, inputs(t), n, t * WT);
-    for (; t < ntiles; t += stride) {
+    // Software pipeline: the next tile's inputs are loaded while this one is
+    // computed.  The first tile is peeled off: inside the loop every input
+    // register is then a copy made at the end of the previous tile, so the
+    // memory waits the compiler places do not depend on the path into the
+    // loop (merged with the entry path they would wait for the prefetch and
+    // for the previous tile's stores at every tile).
+    auto step = [&]() {
         const uint32_t tn = t + stride;
         if (tn < ntiles) load_wtile3<T, MPL, AOS>(nxt, inputs(tn), n, tn * WT);
         wtile_eig3<T, PATH, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
                                       nonfinite);
         cur = nxt;
+    };
+    if (t < ntiles) {
+        load_wtile3<T, MPL, AOS>(cur, inputs(t), n, t * WT);
+        step();
+        for (t += stride; t < ntiles; t += stride) step();
     }
     if constexpr (QUEUE) final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, refined);
     add_counters(args.prm.counters, refined, nonfinite);
@@ -916,12 +944,7 @@ void k_mixed(MixedArgs<T> a) {
     int64_t t = (int64_t)blockIdx.x * NW + wave_id();
     TileInfo cur = {0, 0}, nxt = {0, 0};
     WIn<T, MPL, false> in_cur, in_nxt;
-    if (t < a.ntiles) {
-        cur = tile_at(tiles, t);
-        load_mixed<T, MPL>(in_cur, groups + cur.group, cur.base);
-    }
-    if (t + stride < a.ntiles) nxt = tile_at(tiles, t + stride);
-    for (; t < a.ntiles; t += stride) {
+    auto step = [&]() {
         const bool has_next = t + stride < a.ntiles;
         TileInfo nxt2 = {0, 0};
         if (t + 2 * stride < a.ntiles) nxt2 = tile_at(tiles, t + 2 * stride);
@@ -936,6 +959,15 @@ void k_mixed(MixedArgs<T> a) {
         cur = nxt;
         nxt = nxt2;
         in_cur = in_nxt;
+    };
+    if (t < a.ntiles) {
+        // the first tile peeled off, as in k_eig3: inside the loop the inputs
+        // are register copies and need no memory wait
+        cur = tile_at(tiles, t);
+        load_mixed<T, MPL>(in_cur, groups + cur.group, cur.base);
+        if (t + stride < a.ntiles) nxt = tile_at(tiles, t + stride);
+        step();
+        for (t += stride; t < a.ntiles; t += stride) step();
     }
     final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, refined);
     add_counters(a.prm.counters, refined, nonfinite);
