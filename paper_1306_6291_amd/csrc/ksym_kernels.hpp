@@ -234,12 +234,13 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const bool special = cu.triple || !fin;
     const int flag = special ? (fin ? FLAG_TRIPLE : FLAG_NONFINITE) : (dbl ? FLAG_DOUBLE : FLAG_GENERAL);
     sink.flag(flag);
-    sink.put(O_LAM, (float)((cu.m + cu.mu1) * isc));
-    sink.put(O_LAM + 1, (float)((cu.m + cu.mu2) * isc));
-    sink.put(O_LAM + 2, (float)((cu.m + cu.mu3) * isc));
-    sink.put(O_GAP, (float)(cu.g12 * isc));
-    sink.put(O_GAP + 1, (float)(cu.g13 * isc));
-    sink.put(O_GAP + 2, (float)(cu.g32 * isc));
+    {
+        const float lam[3] = {(float)((cu.m + cu.mu1) * isc), (float)((cu.m + cu.mu2) * isc),
+                              (float)((cu.m + cu.mu3) * isc)};
+        const float gap[3] = {(float)(cu.g12 * isc), (float)(cu.g13 * isc), (float)(cu.g32 * isc)};
+        sink.template put_n<3>(O_LAM, lam);
+        sink.template put_n<3>(O_GAP, gap);
+    }
     const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
     bool bad = special || dbl || (split < prm.tau_gap * (l1 > l2 ? l1 : l2));
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
@@ -254,12 +255,10 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
     float phi[3];
     angles_of(R, v, s2sq, w, cw, phi);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) sink.put(O_PHI + k, phi[k]);
+    sink.template put_n<3>(O_PHI, phi);
     float D[9];
     build_D(R, D);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) sink.put(O_D + i, D[i]);
+    sink.template put_n<9>(O_D, D);
     const float fro2 = A11 * A11 + A22 * A22 + A33 * A33 + 2.0f * (A12 * A12 + A13 * A13 + A23 * A23);
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                     (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
@@ -399,11 +398,31 @@ template <typename T> __device__ __forceinline__ T *karg_ptr(uint32_t off) {
     return *(T *const __attribute__((address_space(4))) *)(ka + off);
 }
 
+// N consecutive plane pointers, read with one wide scalar load (one wait
+// instead of one per pointer).
+template <typename T, int N> struct PtrN {
+    T *p[N];
+};
+template <typename T, int N> __device__ __forceinline__ PtrN<T, N> ptrs_at(T *const __attribute__((address_space(4))) *q) {
+    PtrN<T, N> r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.p[i] = q[i];
+    return r;
+}
+template <typename T, int N> __device__ __forceinline__ PtrN<T, N> karg_ptrs(uint32_t off) {
+    typedef __attribute__((address_space(4))) const char *kptr;
+    kptr ka = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+    return ptrs_at<T, N>((T *const __attribute__((address_space(4))) *)(ka + off));
+}
+
 // Output plane pointers of a launch in the kernel-argument segment.
 // n: matrices in this launch.
 template <typename T> struct KernargPlanes {
     uint32_t out_off, flags_off, n;   // byte offsets inside the argument segment
     __device__ __forceinline__ T *out(int k) const { return karg_ptr<T>(out_off + 8 * k); }
+    template <int N> __device__ __forceinline__ PtrN<T, N> outs(int k) const {
+        return karg_ptrs<T, N>(out_off + 8 * k);
+    }
     __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return karg_ptr<uint8_t>(flags_off + 8 * salt); }
 };
 
@@ -412,6 +431,9 @@ template <typename T> struct TablePlanes {
     cptr<Eig3Ptrs<T>> p;
     uint32_t n;
     __device__ __forceinline__ T *out(int k) const { return p->out[k]; }
+    template <int N> __device__ __forceinline__ PtrN<T, N> outs(int k) const {
+        return ptrs_at<T, N>(&p->out[k]);
+    }
     __device__ __forceinline__ uint8_t *flags(int salt = 0) const { return (&p->flags)[salt]; }
 };
 
@@ -433,6 +455,12 @@ template <typename T, typename Planes> struct LaneSink {
     int salt;
     uint32_t off;
     __device__ __forceinline__ void put(int k, T v) const { st_plane<T>(pl.out(k + salt), pl.n, off, v); }
+    // planes k0 .. k0 + N - 1
+    template <int N> __device__ __forceinline__ void put_n(int k0, const T *v) const {
+        const PtrN<T, N> q = pl.template outs<N>(k0 + salt);
+#pragma unroll
+        for (int i = 0; i < N; ++i) st_plane<T>(q.p[i], pl.n, off, v[i]);
+    }
     __device__ __forceinline__ void flag(int f) const {
         st_plane<uint8_t>(pl.flags(salt), pl.n, off, (uint8_t)f);
     }
@@ -484,6 +512,7 @@ template <typename T> struct KernargInputs {
     uint32_t in_off, aos_off;
     int salt;
     __device__ __forceinline__ const T *in(int c) const { return karg_ptr<const T>(in_off + 8 * (c + salt)); }
+    __device__ __forceinline__ PtrN<const T, 6> ins() const { return karg_ptrs<const T, 6>(in_off + 8 * salt); }
     __device__ __forceinline__ const T *aos() const { return karg_ptr<const T>(aos_off + 8 * salt); }
 };
 
@@ -514,11 +543,12 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &
             }
         }
     } else {
+        const PtrN<const T, 6> ptrs = src.ins();
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const uint32_t off = base + k * WAVE + lane;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) in.a[k][c] = ld_plane<T>(src.in(c), n, off);
+            for (int c = 0; c < 6; ++c) in.a[k][c] = ld_plane<T>(ptrs.p[c], n, off);
         }
     }
 }
@@ -901,6 +931,7 @@ template <typename T> struct MixedArgs {
 template <typename T> struct TableInputs {
     cptr<GroupDesc<T>> g;
     __device__ __forceinline__ const T *in(int c) const { return g->p3.in[c]; }
+    __device__ __forceinline__ PtrN<const T, 6> ins() const { return ptrs_at<const T, 6>(&g->p3.in[0]); }
     __device__ __forceinline__ const T *aos() const { return nullptr; }
 };
 
