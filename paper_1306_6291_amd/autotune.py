@@ -233,8 +233,10 @@ def main(argv=None):
     if os.path.exists(args.out):
         with open(args.out) as f:
             tuned = json.load(f)
-    gms = (4, 16, 64) if args.quick else (4, 8, 16, 32, 64)
-    drains = (0, 4, 8) if args.quick else (0, 2, 4, 8, 16)
+    # large grid_mult values make the launch non-persistent (one wave tile
+    # per wave), which measured fastest for the 3x3 kernels
+    gms = (16, 64, 256, 1024) if args.quick else (4, 16, 32, 64, 128, 256, 512, 1024)
+    drains = (0, 8) if args.quick else (0, 4, 8, 16)
     shapes32 = _shapes((64, 128, 256, 512), (1, 2), gms, drains)
     shapes_aos = [s for s in shapes32 if (s["block"], s["mats_per_lane"]) in
                   ((64, 1), (128, 1), (256, 1), (256, 2), (512, 1))]

@@ -82,8 +82,8 @@ ksym_status resolve_opts(ksym_dtype dt, const ksym_opts *in, ksym_opts *out) {
         return fail(KSYM_E_ARG, "block must be 64, 128, 256, 512 or 1024 (got %d)", o.block);
     if (o.mats_per_lane != 1 && o.mats_per_lane != 2 && o.mats_per_lane != 4)
         return fail(KSYM_E_ARG, "mats_per_lane must be 1, 2 or 4 (got %d)", o.mats_per_lane);
-    if (o.grid_mult < 1 || o.grid_mult > 64)
-        return fail(KSYM_E_ARG, "grid_mult must be in 1..64 (got %d)", o.grid_mult);
+    if (o.grid_mult < 1 || o.grid_mult > 1024)
+        return fail(KSYM_E_ARG, "grid_mult must be in 1..1024 (got %d)", o.grid_mult);
     if (o.drain_tiles > (1 << 20)) return fail(KSYM_E_ARG, "drain_tiles must be in 0..2^20");
     if (!(o.tau_res > 0) || !(o.tau_dbl >= 0) || !(o.tau_gap >= 0) || !(o.tau_vec >= 0))
         return fail(KSYM_E_ARG, "thresholds must be finite and non-negative (tau_res > 0)");

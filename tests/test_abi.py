@@ -107,7 +107,7 @@ def test_eig3_argument_errors(lib):
     o.path = 0
     assert f(1, 10, ok, None, None, None, None, None, None, 0, ctypes.byref(o), None) == 2
     # launch-shape options
-    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 65),
+    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 1025),
                        ("drain_tiles", (1 << 20) + 1)):
         lib.ksym_opts_default(0, ctypes.byref(o))
         setattr(o, field, bad)
