@@ -225,12 +225,14 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     lc = 0.0;
     const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
     const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
-    // p = 0 (A = lam I, §5) and non-finite input: the general path below
-    // still runs (it cannot fault, and its stores are provisional) and the
-    // matrix is queued; the drain writes the special outputs.  Keeping every
-    // store on the one straight path lets the compiler count the memory
-    // operations in flight exactly, instead of assuming a path without
-    // stores and waiting for the prefetched inputs at every tile.
+    // Every matrix runs the general path below, so that every store lies on
+    // one straight path: the compiler then counts the memory operations in
+    // flight exactly, instead of assuming a path without stores and waiting
+    // for the prefetched inputs at every tile.  For p = 0 (A = lam I, §5,
+    // which for float32 input means B = 0 exactly) that path yields the
+    // special outputs exactly: all gaps and deviations are 0, the squared
+    // cosines are the empty pairs' (1, 0), so D = I, the angles are 0 and
+    // lam = m.  A non-finite input is queued, and the drain writes NaN.
     const bool special = cu.triple || !fin;
     const int flag = special ? (fin ? FLAG_TRIPLE : FLAG_NONFINITE) : (dbl ? FLAG_DOUBLE : FLAG_GENERAL);
     sink.flag(flag);
@@ -242,7 +244,7 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
         sink.template put_n<3>(O_GAP, gap);
     }
     const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
-    bool bad = special || dbl || (split < prm.tau_gap * (l1 > l2 ? l1 : l2));
+    bool bad = !fin || (!cu.triple && (dbl || split < prm.tau_gap * (l1 > l2 ? l1 : l2)));
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
     // general branch (5.1)-(5.15): the four squared cosines and sines as
     // float64 quotients (u_quotients), the rest of the angle solve in float32
