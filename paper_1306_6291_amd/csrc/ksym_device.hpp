@@ -134,14 +134,16 @@ __device__ __forceinline__ void acos_pair(double r, double &D, double &Dc) {
     const double x = small ? ar : sqrt_small64<1>(z);
     const double T = (double)tail_poly(poly::AT, 6, (float)z);
     const double a = __builtin_fma(x * z, __builtin_fma(z, T, 1.0 / 6.0), x);   // asin(x)
+    double pi = kPi;
+    asm volatile("" : "+s"(pi));   // a scalar constant at each use, not a long-lived vector register
     if (small) {
         const double sa = r < 0.0 ? -a : a;        // asin(r)
-        D = 0.5 * kPi - sa;
-        Dc = 0.5 * kPi + sa;
+        D = 0.5 * pi - sa;
+        Dc = 0.5 * pi + sa;
     } else {
         const double b = 2.0 * a;                  // acos(|r|)
-        D = r < 0.0 ? kPi - b : b;
-        Dc = r < 0.0 ? b : kPi - b;
+        D = r < 0.0 ? pi - b : b;
+        Dc = r < 0.0 ? b : pi - b;
     }
 }
 
@@ -352,6 +354,30 @@ __device__ __forceinline__ URow u_quotients(double d1, double mu1, double mu2, d
     u.s2sq = okv ? qv * rv : 0.0;
     u.w = okw ? pw * rw : 1.0;
     u.cw = okw ? qw * rw : 0.0;
+    return u;
+}
+
+// The float32 path: the same numerators in float64 (they are differences of
+// nearly equal terms), each pair's quotients in float32 from them (a few
+// float32 ulps).
+struct URowF {
+    float v, s2sq, w, cw;
+};
+__device__ __forceinline__ URowF u_quotients_f32(double d1, double mu1, double mu2, double mu3, double g13,
+                                                 double g32, double a12, double a13) {
+    const double F = a12 * a12 + a13 * a13;
+    const double e1 = d1 - mu1, e2 = d1 - mu2, e3 = d1 - mu3;
+    const float pv = (float)fmax(F + e3 * (e1 + g32), 0.0), qv = (float)fmax(-(F + e1 * e2), 0.0);
+    const float pw = (float)fmax((F + e2 * e3) * g32, 0.0), qw = (float)fmax((F + e1 * e3) * g13, 0.0);
+    // an empty pair gives (1, 0); v = 0 gives w = 1, the paper's convention
+    const float tv = pv + qv, tw = pw + qw;
+    const bool okv = tv > 0.0f, okw = tw > 0.0f;
+    const float rv = __builtin_amdgcn_rcpf(okv ? tv : 1.0f), rw = __builtin_amdgcn_rcpf(okw ? tw : 1.0f);
+    URowF u;
+    u.v = okv ? pv * rv : 1.0f;
+    u.s2sq = okv ? qv * rv : 0.0f;
+    u.w = okw ? pw * rw : 1.0f;
+    u.cw = okw ? qw * rw : 0.0f;
     return u;
 }
 

@@ -246,14 +246,15 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
     bool bad = !fin || (!cu.triple && (dbl || split < prm.tau_gap * (l1 > l2 ? l1 : l2)));
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
-    // general branch (5.1)-(5.15): the four squared cosines and sines as
-    // float64 quotients (u_quotients), the rest of the angle solve in float32
-    const URow u = u_quotients<1>(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
-    const float A11 = (float)a[0], A22 = (float)a[1], A33 = (float)a[2];
+    // general branch (5.1)-(5.15): the four squared cosines and sines from
+    // float64 numerators (u_quotients_f32), the rest of the angle solve in
+    // float32
+    const URowF u = u_quotients_f32(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
+    const float A22 = (float)a[1], A33 = (float)a[2];
     const float A12 = (float)a[3], A13 = (float)a[4], A23 = (float)a[5];
     const float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
     const bool plus = !(product_key(a[3], a[4], a[1], a[2], a[5]) < 0.0);
-    const float v = (float)u.v, s2sq = (float)u.s2sq, w = (float)u.w, cw = (float)u.cw;
+    const float v = u.v, s2sq = u.s2sq, w = u.w, cw = u.cw;
     const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
     float phi[3];
     angles_of(R, v, s2sq, w, cw, phi);
@@ -261,7 +262,8 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     float D[9];
     build_D(R, D);
     sink.template put_n<9>(O_D, D);
-    const float fro2 = A11 * A11 + A22 * A22 + A33 * A33 + 2.0f * (A12 * A12 + A13 * A13 + A23 * A23);
+    // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
+    const float fro2 = (float)__builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                     (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
                                     prm.tau_res2_f * fro2, prm.tau_vec_f);
@@ -726,12 +728,12 @@ __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refine
     }
 }
 
-// float32, one matrix per lane, SoA: the refinement path needs a few more
-// registers than the main path; asking for 5 waves per SIMD makes the
-// compiler fit both into 96 VGPRs (without spills) instead of dropping to 4.
+// float32 SoA with one or two matrices per lane: asking for 5 waves per SIMD
+// makes the compiler fit the kernel into 96 VGPRs (the one spill left is
+// reloaded once, after the tile loop) instead of dropping to 4 waves.
 template <typename T, int PATH, int BS, int MPL, bool AOS>
 __global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1 && !AOS) ? 5 : 1)))
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL <= 2 && !AOS) ? 5 : 1)))
 void k_eig3(Eig3Args<T> args) {
     constexpr int NW = BS / WAVE;
     constexpr int WT = WAVE * MPL;
