@@ -115,6 +115,14 @@ __device__ __forceinline__ void sincos_third(double t, double &s, double &c) {
     c = pc;
 }
 
+// A float64 constant that needs both halves of a register pair, made opaque
+// so that it is set in scalar registers at each use: hoisted out of the tile
+// loop it would occupy a vector register pair throughout, or be spilled.
+__device__ __forceinline__ double sconst(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 // Float32-tail versions for the cubic stage of the float32 path: the first
 // two terms of each series are formed in float64 and only the remainder (at
 // most 1.2 % of the value) in float32, with coefficients that are literal
@@ -133,9 +141,8 @@ __device__ __forceinline__ void acos_pair(double r, double &D, double &Dc) {
     const double z = small ? ar * ar : 0.5 * (1.0 - ar);
     const double x = small ? ar : sqrt_small64<1>(z);
     const double T = (double)tail_poly(poly::AT, 6, (float)z);
-    const double a = __builtin_fma(x * z, __builtin_fma(z, T, 1.0 / 6.0), x);   // asin(x)
-    double pi = kPi;
-    asm volatile("" : "+s"(pi));   // a scalar constant at each use, not a long-lived vector register
+    const double a = __builtin_fma(x * z, __builtin_fma(z, T, sconst(1.0 / 6.0)), x);   // asin(x)
+    const double pi = sconst(kPi);
     if (small) {
         const double sa = r < 0.0 ? -a : a;        // asin(r)
         D = 0.5 * pi - sa;
@@ -151,7 +158,7 @@ __device__ __forceinline__ void acos_pair(double r, double &D, double &Dc) {
 __device__ __forceinline__ double sin_third(double t) {
     const double t2 = t * t;
     const double T = (double)tail_poly(poly::ST, 3, (float)t2);
-    return __builtin_fma(t * t2, __builtin_fma(t2, T, -1.0 / 6.0), t);
+    return __builtin_fma(t * t2, __builtin_fma(t2, T, sconst(-1.0 / 6.0)), t);
 }
 
 // atan2(y, x) in float32: reduce to t = min(|x|,|y|)/max(|x|,|y|) in [0, 1],

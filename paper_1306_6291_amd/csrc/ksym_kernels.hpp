@@ -243,8 +243,11 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
         sink.template put_n<3>(O_LAM, lam);
         sink.template put_n<3>(O_GAP, gap);
     }
-    const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
-    bool bad = !fin || (!cu.triple && (dbl || split < prm.tau_gap * (l1 > l2 ? l1 : l2)));
+    bool bad = !fin || (!cu.triple && dbl);
+    if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
+        const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
+        bad = bad || (!cu.triple && split < prm.tau_gap * (l1 > l2 ? l1 : l2));
+    }
     lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
     // general branch (5.1)-(5.15): the four squared cosines and sines from
     // float64 numerators (u_quotients_f32), the rest of the angle solve in
