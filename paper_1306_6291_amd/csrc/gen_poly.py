@@ -13,6 +13,10 @@ rounded to the target precision):
   rho^-k).
 * atan(x) = x + x t Q(t), t = x^2, x in [0, 1] (float32): Q interpolates
   (atan(sqrt t)/sqrt t - 1)/t at the Chebyshev points of [0, 1].
+* atan(t) = t + t u Q64(u), u = t^2, t in [0, tan(pi/8)] (float64): Q64
+  interpolates (atan(sqrt u)/sqrt u - 1)/u at the Chebyshev points of
+  [0, tan(pi/8)^2] (the float64 atan2, after the reduction
+  atan t = pi/4 - atan((1 - t)/(1 + t)) for t > tan(pi/8)).
 * asin(x) = x + x z R(z), z = x^2, x in [0, 1/sqrt 2] (float32): R interpolates
   (asin(sqrt z)/sqrt z - 1)/z at the Chebyshev points of [0, 1/2] (the angles
   phi2, phi3 of the float32 path from their squared sines and cosines).
@@ -121,6 +125,20 @@ def tail(kind, deg):
     return c, err
 
 
+def atan_f64_poly(deg):
+    b = (mp.sqrt(2) - 1) ** 2
+
+    def f(u):
+        if u == 0:
+            return mp.mpf(-1) / 3
+        s = mp.sqrt(u)
+        return (mp.atan(s) / s - 1) / u
+    c = [float(v) for v in cheb_interp(f, mp.mpf(0), b, deg)]
+    err = max_rel_err(lambda x: x + x * x * x * horner([mp.mpf(v) for v in c], x * x),
+                      mp.atan, mp.mpf(0), mp.sqrt(b), npts=801)
+    return c, err
+
+
 def asin_f32_poly(deg):
     def f(z):
         if z == 0:
@@ -152,6 +170,7 @@ def main():
     asin_c, asin_err = asin_poly(11)
     atan_c, atan_err = atan_poly(8)
     asf_c, asf_err = asin_f32_poly(7)
+    at64_c, at64_err = atan_f64_poly(10)
     st_c, st_err = tail("sin", 3)
     at_c, at_err = tail("asin", 6)
     out = []
@@ -169,6 +188,9 @@ def main():
     out.append(f"// atan x = x + x t Q(t), t = x^2, x in [0, 1]; Chebyshev interpolant rounded to float, "
                f"max relative error {float(atan_err):.2e}")
     out.append("constexpr float ATAN[%d] = {%s};" % (len(atan_c), ", ".join(repr(v) + "f" for v in atan_c)))
+    out.append(f"// atan t = t + t u Q64(u), u = t^2, t in [0, tan(pi/8)]; Chebyshev interpolant, "
+               f"max relative error {float(at64_err):.2e}")
+    out.append("constexpr double ATAN64[%d] = {%s};" % (len(at64_c), ", ".join(repr(v) for v in at64_c)))
     out.append(f"// asin x = x + x z R(z), z = x^2, x in [0, 1/sqrt 2]; Chebyshev interpolant rounded to float, "
                f"max relative error {float(asf_err):.2e}")
     out.append("constexpr float ASINF[%d] = {%s};" % (len(asf_c), ", ".join(repr(v) + "f" for v in asf_c)))

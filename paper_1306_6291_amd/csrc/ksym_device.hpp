@@ -19,6 +19,7 @@ constexpr double kSqrt3 = 1.73205080756887729353;
 constexpr double kInvSqrt3 = 0.57735026918962576451;
 
 __device__ __forceinline__ float atan2_fast(float y, float x);
+__device__ __forceinline__ double atan2_f64(double y, double x);
 
 // ---------------------------------------------------------------- math -----
 // float uses the hardware approximations (v_sqrt_f32, v_rsq_f32, v_rcp_f32:
@@ -39,7 +40,7 @@ template <> struct Mth<double> {
     static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    static __device__ __forceinline__ double atan2(double y, double x) { return atan2_f64(y, x); }
     static __device__ __forceinline__ double fabs(double x) { return __builtin_fabs(x); }
 };
 
@@ -322,6 +323,34 @@ template <int NEWTON = 2> __device__ __forceinline__ double rcp64(double x) {
     }
     return y;
 }
+
+// atan2(y, x) in float64: t = min(|x|,|y|) / max(|x|,|y|) in [0, 1]; above
+// tan(pi/8) the identity atan t = pi/4 - atan((1 - t)/(1 + t)) brings the
+// argument into [0, tan(pi/8)], formed as one quotient (max - min)/(max + min);
+// atan t = t + t^3 Q64(t^2) there; then the octant is folded.  Tiny inputs
+// are scaled by a power of two first, so the reciprocal stays in range.  y =
+// -0 counts as +0, so the result lies in (-pi, pi].
+__device__ __forceinline__ double atan2_f64(double y, double x) {
+    const double ax = __builtin_fabs(x), ay = __builtin_fabs(y);
+    double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const double s = mx < 0x1p-900 ? 0x1p600 : 1.0;
+    mn *= s;
+    mx *= s;
+    const bool big = mn > 0.41421356237309503 * mx;   // tan(pi/8)
+    const double num = big ? mx - mn : mn, den = big ? mx + mn : mx;
+    const double t = den > 0.0 ? num * rcp64(den) : 0.0;
+    const double u = t * t;
+    double P = poly::ATAN64[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) P = __builtin_fma(P, u, poly::ATAN64[k]);
+    double a = __builtin_fma(t * u, P, t);
+    const double pi = sconst(kPi);
+    a = big ? 0.25 * pi - a : a;
+    a = (ay > ax) ? 0.5 * pi - a : a;
+    a = (x < 0.0) ? pi - a : a;
+    return (y < 0.0) ? -a : a;
+}
+
 
 // The squared direction cosines of the first row of D, each as its own
 // quotient.  With A = D diag(lam) D^T, u_k = D_1k^2 satisfies sum u_k = 1,
