@@ -274,6 +274,63 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     return flag;
 }
 
+// The float64 checked path, streaming its outputs through a sink like
+// eig3_f32 (fewer live registers than gathering all eighteen first): the
+// float64 cubic stage, the general branch with the squared cosines as float64
+// quotients (u_quotients), and the float64 check.  As in eig3_f32, p = 0
+// takes the general path's exact result (all deviations and gaps 0: D = I,
+// angles 0, lam = m) and a non-finite input is queued for its NaN outputs.
+// Sets refine and lc (the isolated eigenvalue handed to the refinement, a
+// deviation in scaled units) and returns the flag.
+template <typename Sink>
+__device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &prm, const Sink &sink,
+                                         bool &refine, double &lc) {
+    const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
+                     finite(ain[4]) && finite(ain[5]);
+    double amax = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs(ain[c]));
+    const int ex = fin ? scale_exponent(amax) : 0;
+    const double sc = pow2(-ex), isc = pow2(ex);
+    double a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = fin ? ain[c] * sc : 0.0;
+    const Cubic cu = cubic_stage(a[0], a[1], a[2], a[3], a[4], a[5]);
+    const double split = fmin(cu.g13, cu.g32);
+    const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
+    const int flag = !fin ? FLAG_NONFINITE : (cu.triple ? FLAG_TRIPLE : (dbl ? FLAG_DOUBLE : FLAG_GENERAL));
+    sink.flag(flag);
+    {
+        const double lam[3] = {(cu.m + cu.mu1) * isc, (cu.m + cu.mu2) * isc, (cu.m + cu.mu3) * isc};
+        const double gap[3] = {cu.g12 * isc, cu.g13 * isc, cu.g32 * isc};
+        sink.template put_n<3>(O_LAM, lam);
+        sink.template put_n<3>(O_GAP, gap);
+    }
+    bool bad = !fin || (!cu.triple && dbl);
+    if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
+        const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
+        bad = bad || (!cu.triple && split < prm.tau_gap * fmax(l1, l2));
+    }
+    lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
+    const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a[3], a[4]);
+    const bool plus = !(product_key(a[3], a[4], a[1], a[2], a[5]) < 0.0);
+    const Rot<double> R = select_angles<double>(a[3], a[4], a[1], a[2], a[5], cu.g12, cu.g13, cu.g32, u.v,
+                                                u.s2sq, u.w, u.cw, plus);
+    double phi[3];
+    angles_of(R, phi);
+    sink.template put_n<3>(O_PHI, phi);
+    double D[9];
+    build_D(R, D);
+    sink.template put_n<9>(O_D, D);
+    // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
+    const double fro2 = __builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
+    bad = bad || (!cu.triple && check_fails<double>(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], D, cu.mu1,
+                                                    cu.mu2, cu.mu3, cu.g12, cu.g13, cu.g32,
+                                                    prm.tau_res * prm.tau_res * fro2, prm.tau_vec));
+    refine = bad;
+    return flag;
+}
+
 // The refinement of one queued matrix (original entries ain, isolated
 // eigenvalue lc as a deviation from the centre, in the scaled units eig3_one
 // used; the centre is recomputed here with the same arithmetic).  A matrix
@@ -624,6 +681,8 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         double lc;
         if constexpr (PATH == PATH_FP32_FIXUP) {
             flag = eig3_f32(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
+        } else if constexpr (PATH == PATH_FP64_FIXUP) {
+            flag = eig3_f64s(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T, PATH>(A, prm, o);
