@@ -108,7 +108,9 @@ typedef enum {
  *   mats_per_lane  matrices each lane handles per tile: 1, 2 or 4 (3x3
  *                  kernels: 1 or 2).
  *   grid_mult      workgroups per compute unit of the grid-stride launch
- *                  (the grid is min(tiles, grid_mult * CUs)); 1..1024.
+ *                  (the grid is min(tiles, grid_mult * CUs)); 1..1024.  The
+ *                  default 1024 makes the launch non-persistent (one tile
+ *                  per wave) below about 2^18 tiles, which measured fastest.
  *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
  *                  below which a matrix always takes the refinement (0 = off).
  *   tau_res        refinement if some residual ||A d_k - lam_k d_k|| exceeds

@@ -289,7 +289,7 @@ void ksym_opts_default(ksym_dtype dtype, ksym_opts *o) {
     o->path = dtype == KSYM_F64 ? KSYM_PATH_FP64_FIXUP : KSYM_PATH_FP32_FIXUP;
     o->block = 256;
     o->mats_per_lane = 1;
-    o->grid_mult = 16;
+    o->grid_mult = 1024;   // one tile per wave for all but the largest batches
     o->tau_gap = 0.0;
     o->tau_dbl = dtype == KSYM_F64 ? 1e-6 : 1e-9;
     o->drain_tiles = 8;

@@ -918,25 +918,28 @@ template <typename T> struct BwdArgs {
 
 // One lane's adjoint.  Absent cotangents read as zeros; lanes past n read
 // zeros and store nothing (the descriptors' bounds).  Plane pointers come
-// from the argument segment (salt: see karg_ptr).
+// from the argument segment in groups, one wide scalar load each (salt: see
+// karg_ptr), so all 27 plane loads can be issued back to back.
 template <typename T>
 __device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, double eps_rel, int salt) {
     constexpr uint32_t P = (uint32_t)offsetof(BwdArgs<T>, p);
-    auto ptr = [&](uint32_t field, int c) { return karg_ptr<T>(P + field + 8 * (c + salt)); };
+    const PtrN<const T, 12> pin = karg_ptrs<const T, 12>(P + offsetof(BwdPtrs<T>, lam) + 8 * salt);   // lam, D
+    const PtrN<const T, 12> pco = karg_ptrs<const T, 12>(P + offsetof(BwdPtrs<T>, glam) + 8 * salt);  // glam, gD
     T L[3], D[9], gl[3], gD[9], gA[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, lam), c), n, i);
+    for (int c = 0; c < 3; ++c) L[c] = ld_plane<T>(pin.p[c], n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) D[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, D), c), n, i);
+    for (int c = 0; c < 9; ++c) D[c] = ld_plane<T>(pin.p[3 + c], n, i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, glam), c), n, i);
+    for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T>(pco.p[c], n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gD), c), n, i);
+    for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T>(pco.p[3 + c], n, i);
     T g12, g13, g32;
     if (has_gap) {
-        g12 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 0), n, i);
-        g13 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 1), n, i);
-        g32 = ld_plane<T>(ptr(offsetof(BwdPtrs<T>, gap), 2), n, i);
+        const PtrN<const T, 3> pg = karg_ptrs<const T, 3>(P + offsetof(BwdPtrs<T>, gap) + 8 * salt);
+        g12 = ld_plane<T>(pg.p[0], n, i);
+        g13 = ld_plane<T>(pg.p[1], n, i);
+        g32 = ld_plane<T>(pg.p[2], n, i);
     } else {
         // differences of the stored eigenvalues, exact in float64
         g12 = (T)((double)L[0] - (double)L[1]);
@@ -945,8 +948,9 @@ __device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, d
     }
     const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
+    const PtrN<T, 6> po = karg_ptrs<T, 6>(P + offsetof(BwdPtrs<T>, gA) + 8 * salt);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) st_plane<T>(ptr(offsetof(BwdPtrs<T>, gA), c), n, i, gA[c]);
+    for (int c = 0; c < 6; ++c) st_plane<T>(po.p[c], n, i, gA[c]);
 }
 
 template <typename T, int BS, int MPL>

@@ -67,6 +67,7 @@ def test_defaults(lib):
     assert o.path == 0 and o.block == 256 and o.mats_per_lane in (1, 2, 4)
     assert 0 < o.tau_res < 1e-5
     assert o.drain_tiles >= 0 and o.reserved == 0
+    assert 1 <= o.grid_mult <= 1024
     lib.ksym_opts_default(1, ctypes.byref(o))
     assert o.path == 2 and 0 < o.tau_res < 1e-9
 
