@@ -20,10 +20,13 @@ constexpr double kInvSqrt3 = 0.57735026918962576451;
 
 __device__ __forceinline__ float atan2_fast(float y, float x);
 __device__ __forceinline__ double atan2_f64(double y, double x);
+__device__ __forceinline__ double sqrt_any64(double x);
+__device__ __forceinline__ double rsqrt_any64(double x);
 
 // ---------------------------------------------------------------- math -----
 // float uses the hardware approximations (v_sqrt_f32, v_rsq_f32, v_rcp_f32:
-// about 1 ulp); double uses the correctly rounded sequences.
+// about 1 ulp); double uses the hardware reciprocal square root refined by
+// Newton steps (sqrt about 1 ulp) and the correctly rounded division.
 template <typename T> struct Mth;
 
 template <> struct Mth<float> {
@@ -36,8 +39,8 @@ template <> struct Mth<float> {
 };
 
 template <> struct Mth<double> {
-    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return sqrt_any64(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return rsqrt_any64(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double atan2(double y, double x) { return atan2_f64(y, x); }
@@ -84,6 +87,26 @@ template <int NEWTON = 2> __device__ __forceinline__ double sqrt_small64(double 
         s = __builtin_fma(0.5 * y, d, s);
     }
     return z > 0.0 ? s : 0.0;
+}
+
+// 1/sqrt(x) for x > 0 of any magnitude: inputs below 2^-900 are scaled by
+// 2^600 first (exact), which keeps the hardware estimate in range.
+__device__ __forceinline__ double rsqrt_any64(double x) {
+    const bool tiny = x < 0x1p-900;
+    const double y = rsqrt64(tiny ? x * 0x1p600 : x);
+    return tiny ? y * 0x1p300 : y;
+}
+
+// sqrt(x) for x >= 0 of any magnitude (0 for x <= 0, NaN stays NaN):
+// x / sqrt(x) and one correction step, about 1 ulp.
+__device__ __forceinline__ double sqrt_any64(double x) {
+    const bool tiny = x < 0x1p-900;
+    const double xs = tiny ? x * 0x1p600 : x;
+    const double y = rsqrt64(xs > 0.0 ? xs : 1.0);
+    double r = xs * y;
+    r = __builtin_fma(0.5 * y, __builtin_fma(-r, r, xs), r);
+    r = tiny ? r * 0x1p-300 : r;
+    return x > 0.0 ? r : (x == x ? 0.0 : x);
 }
 
 // arccos(r) for r in [-1, 1] through asin: |r| <= 1/2 uses
@@ -645,7 +668,7 @@ __device__ __forceinline__ Refined refine3(double a11, double a22, double a33, d
     }
     double ux, uy, uz;
     if (n > 0.0) {
-        const double inv = 1.0 / ::sqrt(n);
+        const double inv = rsqrt_any64(n);
         ux = cx * inv; uy = cy * inv; uz = cz * inv;
     } else {
         ux = 0.0; uy = 0.0; uz = 1.0;   // A - lc I = 0: any basis diagonalises A
@@ -661,7 +684,7 @@ __device__ __forceinline__ Refined refine3(double a11, double a22, double a33, d
         xx = uy; xy = -ux; xz = 0.0;
     }
     {
-        const double inv = 1.0 / ::sqrt(xx * xx + xy * xy + xz * xz);
+        const double inv = rsqrt_any64(xx * xx + xy * xy + xz * xz);
         xx *= inv; xy *= inv; xz *= inv;
     }
     const double yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
@@ -679,11 +702,15 @@ __device__ __forceinline__ Refined refine3(double a11, double a22, double a33, d
     // one rotation of the 2x2 block by the paper's 2x2 closed form (§3)
     const double dd = b11 - b22;
     const double sg = dd >= 0.0 ? 1.0 : -1.0;
-    const double rr = ::sqrt(dd * dd + 4.0 * b12 * b12);
-    double cphi = 1.0, sphi = 0.0;
-    if (rr > 0.0) {
-        cphi = ::sqrt(0.5 * (1.0 + __builtin_fabs(dd) / rr));
-        sphi = (b12 * sg / rr) / cphi;
+    const double q2 = dd * dd + 4.0 * b12 * b12;
+    double cphi = 1.0, sphi = 0.0, rr = 0.0;
+    if (q2 > 0.0) {
+        const double irr = rsqrt_any64(q2);   // 1 / rr
+        rr = q2 * irr;
+        const double h = 0.5 * (1.0 + __builtin_fabs(dd) * irr);   // in [1/2, 1]
+        const double ih = rsqrt64(h);
+        cphi = h * ih;                                             // sqrt(h)
+        sphi = b12 * sg * irr * ih;                                // (b12 sg / rr) / cphi
     }
     const double mu1 = 0.5 * (b11 + b22 + sg * rr), mu2 = 0.5 * (b11 + b22 - sg * rr);
     // columns: v0 = c x + s y (mu1), v1 = -s x + c y (mu2), v2 = u (lu)
