@@ -82,12 +82,11 @@ template <typename T> struct Out3 {
 
 __device__ __forceinline__ double pow2(int e) { return __builtin_ldexp(1.0, e); }
 
-// One 3x3 matrix through §4-§5.  PATH_FP32_FIXUP / PATH_FP64_FIXUP: general
-// branch plus the float64 check; matrices failing it, near the double-root
-// case or below tau_gap are marked for refinement.  PATH_FP64_PLAIN: general
-// branch, or the paper's double-root branch (5.20)-(5.25) with the output slots
-// restored, no check.
-template <typename T, int PATH>
+// One 3x3 matrix through §4-§5 on the plain float64 path: the general branch
+// with v, w of (5.1)-(5.2) as printed, or the paper's double-root branch
+// (5.20)-(5.25) with the output slots restored, or the triple root; no check.
+// (The checked paths stream their outputs: eig3_f32, eig3_f64s.)
+template <typename T>
 __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, Out3<T> &o) {
     const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
                      finite(ain[4]) && finite(ain[5]);
@@ -115,7 +114,7 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
         const double split = fmin(cu.g13, cu.g32);
         const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
         const T A12 = (T)a12, A13 = (T)a13, A22 = (T)a22, A33 = (T)a33, A23 = (T)a23;
-        if (PATH == PATH_FP64_PLAIN && dbl) {
+        if (dbl) {
             // double root: labels (lam, lam, lam_s), s = cos^2 phi2 (5.21), phi3 = 0;
             // deviations from the centre m keep s accurate when the spread is tiny
             double lm, ls;
@@ -147,22 +146,12 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             o.flag = FLAG_DOUBLE;
         } else {
             // general branch (5.1)-(5.15), with the eigenvalue differences
-            // taken from the float64 stage.  The plain path evaluates v, w as
-            // printed; the checked path forms v, 1 - v, w, 1 - w as separate
-            // quotients (u_quotients), which stay accurate near coincident
-            // eigenvalues.
+            // taken from the float64 stage and v, w evaluated as printed
             const T G12 = (T)cu.g12, G13 = (T)cu.g13, G32 = (T)cu.g32;
-            T v, s2sq, w, cw;
-            if (PATH == PATH_FP64_PLAIN) {
-                const T e1 = (T)(cu.d1 - cu.mu1), e3 = (T)(cu.d1 - cu.mu3);   // A11 - lam1, A11 - lam3
-                v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
-                w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
-                s2sq = T(1) - v;
-                cw = T(1) - w;
-            } else {
-                const URow u = u_quotients(cu.d1, cu.mu1, cu.mu2, cu.mu3, cu.g13, cu.g32, a12, a13);
-                v = (T)u.v; s2sq = (T)u.s2sq; w = (T)u.w; cw = (T)u.cw;
-            }
+            const T e1 = (T)(cu.d1 - cu.mu1), e3 = (T)(cu.d1 - cu.mu3);   // A11 - lam1, A11 - lam3
+            const T v = clamp01(Mth<T>::div(A12 * A12 + A13 * A13 + e3 * (e1 + G32), G32 * G13));
+            const T w = (v == T(0)) ? T(1) : clamp01(Mth<T>::div(e3 + G32 * v, G12 * v));
+            const T s2sq = T(1) - v, cw = T(1) - w;
             const bool plus = !(product_key(a12, a13, a22, a33, a23) < 0.0);
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
             build_D(R, o.v + O_D);
@@ -173,21 +162,7 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             o.v[O_GAP] = (T)(cu.g12 * isc);
             o.v[O_GAP + 1] = (T)(cu.g13 * isc);
             o.v[O_GAP + 2] = (T)(cu.g32 * isc);
-            o.flag = dbl ? FLAG_DOUBLE : FLAG_GENERAL;
-            if (PATH != PATH_FP64_PLAIN) {
-                const double fro2 = a11 * a11 + a22 * a22 + a33 * a33 +
-                                    2.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-                const double lmax = fmax(__builtin_fabs(cu.m + cu.mu1), __builtin_fabs(cu.m + cu.mu2));
-                bool bad = dbl || (split < prm.tau_gap * lmax);
-                double dd[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) dd[i] = (double)o.v[O_D + i];
-                bad = bad || check_fails<double>(cu.d1, cu.d2, cu.d3, a12, a13, a23, dd, cu.mu1, cu.mu2,
-                                                 cu.mu3, cu.g12, cu.g13, cu.g32,
-                                                 prm.tau_res * prm.tau_res * fro2, prm.tau_vec);
-                o.refine = bad;
-                o.lc = (cu.g13 >= cu.g32) ? cu.mu1 : cu.mu2;
-            }
+            o.flag = FLAG_GENERAL;
         }
     }
     if (!fin) {
@@ -685,7 +660,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
             flag = eig3_f64s(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
         } else {
             Out3<T> o;
-            eig3_one<T, PATH>(A, prm, o);
+            eig3_one<T>(A, prm, o);
             put3(pl, salt, off, o);
             flag = o.flag;
             refine = o.refine;
