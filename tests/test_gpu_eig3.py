@@ -150,7 +150,7 @@ def test_f32_launch_shapes_bitwise(ksym):
     for k in ("lam", "D", "phi", "gap", "flags"):
         assert np.array_equal(base[k], again[k], equal_nan=True), k
     for block, mpl in ((64, 1), (64, 2), (128, 1), (128, 2), (256, 1), (256, 2), (512, 1), (512, 2)):
-        for gm in (1, 16):
+        for gm in (1, 16, 1024):
             g = _run(ksym, P32, torch.float32, block=block, mats_per_lane=mpl, grid_mult=gm)
             for k in ("lam", "D", "phi", "gap", "flags"):
                 assert np.array_equal(g[k], base[k], equal_nan=True), (block, mpl, gm, k)
@@ -180,6 +180,41 @@ def test_special_inputs_f32(ksym):
     assert np.all(g["flags"] == 8)
     assert np.all(np.isnan(g["lam"])) and np.all(np.isnan(g["D"]))
     assert int(g["ws"][1]) == 3
+
+
+def test_special_inputs_f64(ksym):
+    """Non-finite entries scattered through a ragged float64 batch: NaN outputs
+    and flag 8 for exactly those matrices on both float64 paths, the checked
+    path counts them, and the finite neighbours are unchanged bitwise."""
+    P = synth.make_plain(3001, 16, seed=808)["planes3"]
+    rng = np.random.default_rng(809)
+    idx = rng.choice(P.shape[1], 40, replace=False)
+    Pb = P.copy()
+    for j, i in enumerate(idx):
+        Pb[j % 6, i] = (np.nan, np.inf, -np.inf)[j % 3]
+    mask = np.zeros(P.shape[1], bool)
+    mask[idx] = True
+    for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
+        base = _run(ksym, P, torch.float64, path=path)
+        g = _run(ksym, Pb, torch.float64, path=path)
+        assert np.all(g["flags"][mask] == 8) and np.all(g["flags"][~mask] != 8), path
+        for k in ("lam", "D", "phi", "gap"):
+            assert np.all(np.isnan(g[k][:, mask])), (path, k)
+            assert np.array_equal(g[k][:, ~mask], base[k][:, ~mask]), (path, k)
+        if path == ksym.PATH_FP64_FIXUP:
+            assert int(g["ws"][1]) == mask.sum()
+
+
+def test_default_launch_shape_f64_bitwise(ksym):
+    """The default float64 launch shape and a large non-persistent grid agree
+    bitwise with a persistent one-workgroup-per-CU-multiple launch."""
+    P = synth.make_precision(30001, seed=4343).astype(np.float64)
+    base = _run(ksym, P, torch.float64, path=ksym.PATH_FP64_FIXUP, grid_mult=1)
+    for opt in ({}, {"grid_mult": 1024}, {"block": 64, "grid_mult": 1024},
+                {"block": 256, "mats_per_lane": 2, "grid_mult": 1024}):
+        g = _run(ksym, P, torch.float64, path=ksym.PATH_FP64_FIXUP, **opt)
+        for k in ("lam", "D", "phi", "gap", "flags"):
+            assert np.array_equal(g[k], base[k]), (opt, k)
 
 
 def test_all_matrices_refined_f32(ksym):
