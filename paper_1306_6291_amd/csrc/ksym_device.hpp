@@ -241,6 +241,8 @@ struct Cubic {
     double g12, g13, g32;     // max-min, max-mid, mid-min (>= 0)
     double sp;                // sqrt(p)
     bool triple;              // p == 0
+    bool fin;                 // p finite: every entry of A is finite (p sums
+                              // squares of all six, scaled to at most 1)
 };
 
 __device__ __forceinline__ void center3(double a11, double a22, double a33, double &m, double &d1,
@@ -271,6 +273,7 @@ __device__ __forceinline__ Cubic cubic_stage(double a11, double a22, double a33,
     // to max |A_ij| in [1/2, 1)) B is so small against m that A is isotropic
     // to working precision, and 1/sqrt(p) would leave the normal range
     c.triple = !(p >= 1e-280);
+    c.fin = __builtin_isfinite(p);
     const double ip = rsqrt64(c.triple ? 1.0 : p);   // 1 / sqrt(p)
     const double sp = c.triple ? 0.0 : p * ip;
     double r = 0.5 * q * (ip * ip * ip);              // q / (2 sqrt(p)^3)
@@ -313,6 +316,7 @@ __device__ __forceinline__ Cubic cubic_stage_gaps(double a11, double a22, double
     const double det = d1 * (d2 * d3 - a23 * a23) - a12 * (a12 * d3 - a13 * a23) +
                        a13 * (a12 * a23 - a13 * d2);
     c.triple = !(p >= 1e-280);
+    c.fin = __builtin_isfinite(p);
     const double ip = rsqrt64<1>(c.triple ? 1.0 : p);
     const double sp = c.triple ? 0.0 : p * ip;
     double r = 13.5 * det * (ip * ip * ip);        // 27 det / (2 sqrt(p)^3)
@@ -623,6 +627,9 @@ __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a2
         bad |= !(n2 <= lim2);
     }
     if (tau_vec > C(0)) {
+        // (the empty asm keeps this a branch on the uniform threshold; the
+        // compiler would otherwise evaluate the test for every matrix)
+        asm volatile("");
         using M = Mth<C>;
         // d_j^T B d_k = d_j^T r_k for j != k (the columns are orthogonal)
         auto dot = [&](int j, int k) { return d[j] * r[k] + d[3 + j] * r[3 + k] + d[6 + j] * r[6 + k]; };

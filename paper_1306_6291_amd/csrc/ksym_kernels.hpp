@@ -184,19 +184,21 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
 template <typename Sink>
 __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &prm, const Sink &sink,
                                         bool &refine, double &lc) {
-    const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
-                     finite(ain[4]) && finite(ain[5]);
+    // max|A_ij| ignores a NaN entry and is infinite for an infinite one (then
+    // the scale is 1); a non-finite entry makes p non-finite (cu.fin) and the
+    // arithmetic below merely carries it along
     float amax = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[0]), __builtin_fabsf(ain[1])),
                                  __builtin_fabsf(ain[2]));
     amax = __builtin_fmaxf(amax, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[3]),
                                                                  __builtin_fabsf(ain[4])),
                                                  __builtin_fabsf(ain[5])));
-    const int ex = fin ? scale_exponent((double)amax) : 0;
+    const int ex = scale_exponent((double)amax);
     const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;   // non-finite: handled below
+    for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;
     const Cubic cu = cubic_stage_gaps(a[0], a[1], a[2], a[3], a[4], a[5]);
+    const bool fin = cu.fin;
     lc = 0.0;
     const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
     const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
@@ -220,6 +222,7 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     }
     bool bad = !fin || (!cu.triple && dbl);
     if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
+        asm volatile("");      // (keeps the branch; see check_fails)
         const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
         bad = bad || (!cu.triple && split < prm.tau_gap * (l1 > l2 ? l1 : l2));
     }
@@ -260,17 +263,17 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
 template <typename Sink>
 __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &prm, const Sink &sink,
                                          bool &refine, double &lc) {
-    const bool fin = finite(ain[0]) && finite(ain[1]) && finite(ain[2]) && finite(ain[3]) &&
-                     finite(ain[4]) && finite(ain[5]);
+    // as in eig3_f32, a non-finite entry shows as a non-finite p (cu.fin)
     double amax = 0.0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs(ain[c]));
-    const int ex = fin ? scale_exponent(amax) : 0;
+    const int ex = scale_exponent(amax);
     const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = fin ? ain[c] * sc : 0.0;
+    for (int c = 0; c < 6; ++c) a[c] = ain[c] * sc;
     const Cubic cu = cubic_stage(a[0], a[1], a[2], a[3], a[4], a[5]);
+    const bool fin = cu.fin;
     const double split = fmin(cu.g13, cu.g32);
     const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
     const int flag = !fin ? FLAG_NONFINITE : (cu.triple ? FLAG_TRIPLE : (dbl ? FLAG_DOUBLE : FLAG_GENERAL));
@@ -283,6 +286,7 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
     }
     bool bad = !fin || (!cu.triple && dbl);
     if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
+        asm volatile("");      // (keeps the branch; see check_fails)
         const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
         bad = bad || (!cu.triple && split < prm.tau_gap * fmax(l1, l2));
     }
@@ -391,27 +395,38 @@ __device__ __forceinline__ rsrc_t plane_rsrc(const void *p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(p ? bytes : 0u),
                                              kBufWord3);
 }
-__device__ __forceinline__ float bload(rsrc_t r, uint32_t off, float) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+// Cache policy of the plane loads and stores (the buffer instructions'
+// cache-policy operand).  Planes are streams, each element read or written
+// once, and the non-temporal policy (the NT bit) keeps them from displacing
+// one another in the caches: a copy with the eig3 plane layout (6 planes in,
+// 15 out) ran about 5 % faster with it.  Two exceptions, both measured:
+//  - stores that the refinement queue overwrites soon after: the drain waits
+//    for the wave's stores to complete, which takes longer for non-temporal
+//    ones (the float64 checked path drains often; it streams its loads only);
+//  - the mixed-batch kernel, whose groups start anywhere, so that a cache
+//    line is often shared by the tiles of two waves: it uses the default.
+constexpr int kCached = 0, kStream = 2;
+template <int POL> __device__ __forceinline__ float bload(rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
 }
-__device__ __forceinline__ double bload(rsrc_t r, uint32_t off, double) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+template <int POL> __device__ __forceinline__ double bload(rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, POL));
 }
-__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+template <int POL> __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, POL);
 }
-__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i32, v), r, (int)off, 0, 0);
+template <int POL> __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i32, v), r, (int)off, 0, POL);
 }
-__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, uint8_t v) {
-    __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)off, 0, 0);
+template <int POL> __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, uint8_t v) {
+    __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)off, 0, POL);
 }
 // Element `i` of plane p (T values) through a plane descriptor of n elements.
-template <typename T> __device__ __forceinline__ T ld_plane(const T *p, uint32_t n, uint32_t i) {
-    return bload(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), T());
+template <typename T, int POL> __device__ __forceinline__ T ld_plane(const T *p, uint32_t n, uint32_t i) {
+    return bload<POL>(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), T());
 }
-template <typename T> __device__ __forceinline__ void st_plane(T *p, uint32_t n, uint32_t i, T v) {
-    bstore(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), v);
+template <typename T, int POL> __device__ __forceinline__ void st_plane(T *p, uint32_t n, uint32_t i, T v) {
+    bstore<POL>(plane_rsrc(p, n * (uint32_t)sizeof(T)), i * (uint32_t)sizeof(T), v);
 }
 
 // Per-lane global stores for the refinement's scattered results, whose plane
@@ -480,28 +495,28 @@ template <typename T> struct TablePlanes {
 // salt, which is 0 at run time but not known to the compiler, so the pointer
 // loads stay here instead of being hoisted out of the tile loop (where they
 // would pin 38 scalar registers for the whole kernel).
-template <typename T, typename Planes>
+template <typename T, int SP, typename Planes>
 __device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, const Out3<T> &o) {
 #pragma unroll
-    for (int k = 0; k < NOUT3; ++k) st_plane<T>(pl.out(k + salt), pl.n, off, o.v[k]);
-    st_plane<uint8_t>(pl.flags(salt), pl.n, off, (uint8_t)o.flag);
+    for (int k = 0; k < NOUT3; ++k) st_plane<T, SP>(pl.out(k + salt), pl.n, off, o.v[k]);
+    st_plane<uint8_t, SP>(pl.flags(salt), pl.n, off, (uint8_t)o.flag);
 }
 
 // Stores of one lane's matrix as its outputs are produced (float32 path).
 // Lanes past n and absent planes are dropped by the descriptors.
-template <typename T, typename Planes> struct LaneSink {
+template <typename T, int SP, typename Planes> struct LaneSink {
     const Planes &pl;
     int salt;
     uint32_t off;
-    __device__ __forceinline__ void put(int k, T v) const { st_plane<T>(pl.out(k + salt), pl.n, off, v); }
+    __device__ __forceinline__ void put(int k, T v) const { st_plane<T, SP>(pl.out(k + salt), pl.n, off, v); }
     // planes k0 .. k0 + N - 1
     template <int N> __device__ __forceinline__ void put_n(int k0, const T *v) const {
         const PtrN<T, N> q = pl.template outs<N>(k0 + salt);
 #pragma unroll
-        for (int i = 0; i < N; ++i) st_plane<T>(q.p[i], pl.n, off, v[i]);
+        for (int i = 0; i < N; ++i) st_plane<T, SP>(q.p[i], pl.n, off, v[i]);
     }
     __device__ __forceinline__ void flag(int f) const {
-        st_plane<uint8_t>(pl.flags(salt), pl.n, off, (uint8_t)f);
+        st_plane<uint8_t, SP>(pl.flags(salt), pl.n, off, (uint8_t)f);
     }
 };
 
@@ -555,7 +570,7 @@ template <typename T> struct KernargInputs {
     __device__ __forceinline__ const T *aos() const { return karg_ptr<const T>(aos_off + 8 * salt); }
 };
 
-template <typename T, int MPL, bool AOS, typename Inputs>
+template <typename T, int MPL, bool AOS, int LP, typename Inputs>
 __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &src, uint32_t n,
                                             uint32_t base) {
     const int lane = lane_id();
@@ -570,14 +585,14 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &
             const uint32_t e0 = base * 6 + j * VEC;
             if (j < (uint32_t)W::NV) {
                 if (e0 + VEC <= lim) {
-                    const v4i32 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(e0 * sizeof(T)), 0, 0);
+                    const v4i32 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(e0 * sizeof(T)), 0, LP);
                     typedef T vec_t __attribute__((ext_vector_type(VEC)));
                     const vec_t y = __builtin_bit_cast(vec_t, x);
 #pragma unroll
                     for (int t = 0; t < VEC; ++t) in.v[u][t] = y[t];
                 } else {
 #pragma unroll
-                    for (int t = 0; t < VEC; ++t) in.v[u][t] = bload(r, (e0 + t) * (uint32_t)sizeof(T), T());
+                    for (int t = 0; t < VEC; ++t) in.v[u][t] = bload<LP>(r, (e0 + t) * (uint32_t)sizeof(T), T());
                 }
             }
         }
@@ -587,7 +602,7 @@ __device__ __forceinline__ void load_wtile3(WIn<T, MPL, AOS> &in, const Inputs &
         for (int k = 0; k < MPL; ++k) {
             const uint32_t off = base + k * WAVE + lane;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) in.a[k][c] = ld_plane<T>(ptrs.p[c], n, off);
+            for (int c = 0; c < 6; ++c) in.a[k][c] = ld_plane<T, LP>(ptrs.p[c], n, off);
         }
     }
 }
@@ -617,7 +632,7 @@ __device__ __forceinline__ unsigned drain_wave(WaveQueue<T, CAP> *q, int cnt, co
 // Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
 // already in registers: compute, store, queue the matrices that need the
 // refinement, and drain the queue.  Wave-uniform control flow.
-template <typename T, int PATH, int MPL, bool AOS, typename Planes, typename PlanesOf>
+template <typename T, int PATH, int MPL, bool AOS, int SP, typename Planes, typename PlanesOf>
 __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
                                            const Eig3Params &prm, const WIn<T, MPL, AOS> &in,
                                            uint32_t n, uint32_t base,
@@ -655,13 +670,13 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         bool refine;
         double lc;
         if constexpr (PATH == PATH_FP32_FIXUP) {
-            flag = eig3_f32(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
+            flag = eig3_f32(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
         } else if constexpr (PATH == PATH_FP64_FIXUP) {
-            flag = eig3_f64s(A, prm, LaneSink<T, Planes>{pl, salt, off}, refine, lc);
+            flag = eig3_f64s(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T>(A, prm, o);
-            put3(pl, salt, off, o);
+            put3<T, SP>(pl, salt, off, o);
             flag = o.flag;
             refine = o.refine;
             lc = o.lc;
@@ -800,15 +815,17 @@ void k_eig3(Eig3Args<T> args) {
     // memory waits the compiler places do not depend on the path into the
     // loop (merged with the entry path they would wait for the prefetch and
     // for the previous tile's stores at every tile).
+    // cache policies: see kStream
+    constexpr int LP = kStream, SP = PATH == PATH_FP64_FIXUP ? kCached : kStream;
     auto step = [&]() {
         const uint32_t tn = t + stride;
-        if (tn < ntiles) load_wtile3<T, MPL, AOS>(nxt, inputs(tn), n, tn * WT);
-        wtile_eig3<T, PATH, MPL, AOS>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
-                                      nonfinite);
+        if (tn < ntiles) load_wtile3<T, MPL, AOS, LP>(nxt, inputs(tn), n, tn * WT);
+        wtile_eig3<T, PATH, MPL, AOS, SP>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
+                                          nonfinite);
         cur = nxt;
     };
     if (t < ntiles) {
-        load_wtile3<T, MPL, AOS>(cur, inputs(t), n, t * WT);
+        load_wtile3<T, MPL, AOS, LP>(cur, inputs(t), n, t * WT);
         step();
         for (t += stride; t < ntiles; t += stride) step();
     }
@@ -827,7 +844,7 @@ template <typename T> struct Eig2Ptrs {
 
 // One 2x2 matrix (§3) and its stores; out = lam1, lam2, D11, D12, D21, D22,
 // phi (absent planes and lanes past n are dropped by the descriptors).
-template <typename T>
+template <typename T, int SP>
 __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], uint8_t *flags,
                                           uint32_t n, uint32_t off) {
     const bool fin = finite(a11) && finite(a22) && finite(a12);
@@ -845,8 +862,8 @@ __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], 
     }
     const T v[7] = {e.l1, e.l2, e.c, -e.s, e.s, e.c, e.phi};
 #pragma unroll
-    for (int k = 0; k < 7; ++k) st_plane<T>(out[k], n, off, v[k]);
-    st_plane<uint8_t>(flags, n, off, fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE);
+    for (int k = 0; k < 7; ++k) st_plane<T, SP>(out[k], n, off, v[k]);
+    st_plane<uint8_t, SP>(flags, n, off, fin ? (uint8_t)0 : (uint8_t)FLAG_NONFINITE);
 }
 
 // One wave tile of 64*MPL 2x2 matrices, straight from and to HBM.
@@ -858,12 +875,12 @@ __device__ __forceinline__ void wtile_eig2(const Eig2Ptrs<T> &p, uint32_t n, uin
     for (int k = 0; k < MPL; ++k) {
         const uint32_t off = base + k * WAVE + lane;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) A[k][c] = ld_plane<T>(p.in[c], n, off);
+        for (int c = 0; c < 3; ++c) A[k][c] = ld_plane<T, kStream>(p.in[c], n, off);
     }
     T *const out[7] = {p.lam[0], p.lam[1], p.D[0], p.D[1], p.D[2], p.D[3], p.phi};
 #pragma unroll
     for (int k = 0; k < MPL; ++k)
-        eig2_lane<T>(A[k][0], A[k][1], A[k][2], out, p.flags, n, base + k * WAVE + lane);
+        eig2_lane<T, kStream>(A[k][0], A[k][1], A[k][2], out, p.flags, n, base + k * WAVE + lane);
 }
 
 template <typename T, int BS, int MPL>
@@ -902,19 +919,19 @@ __device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, d
     const PtrN<const T, 12> pco = karg_ptrs<const T, 12>(P + offsetof(BwdPtrs<T>, glam) + 8 * salt);  // glam, gD
     T L[3], D[9], gl[3], gD[9], gA[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c] = ld_plane<T>(pin.p[c], n, i);
+    for (int c = 0; c < 3; ++c) L[c] = ld_plane<T, kStream>(pin.p[c], n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) D[c] = ld_plane<T>(pin.p[3 + c], n, i);
+    for (int c = 0; c < 9; ++c) D[c] = ld_plane<T, kStream>(pin.p[3 + c], n, i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T>(pco.p[c], n, i);
+    for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T, kStream>(pco.p[c], n, i);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T>(pco.p[3 + c], n, i);
+    for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T, kStream>(pco.p[3 + c], n, i);
     T g12, g13, g32;
     if (has_gap) {
         const PtrN<const T, 3> pg = karg_ptrs<const T, 3>(P + offsetof(BwdPtrs<T>, gap) + 8 * salt);
-        g12 = ld_plane<T>(pg.p[0], n, i);
-        g13 = ld_plane<T>(pg.p[1], n, i);
-        g32 = ld_plane<T>(pg.p[2], n, i);
+        g12 = ld_plane<T, kStream>(pg.p[0], n, i);
+        g13 = ld_plane<T, kStream>(pg.p[1], n, i);
+        g32 = ld_plane<T, kStream>(pg.p[2], n, i);
     } else {
         // differences of the stored eigenvalues, exact in float64
         g12 = (T)((double)L[0] - (double)L[1]);
@@ -925,7 +942,7 @@ __device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, d
     adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
     const PtrN<T, 6> po = karg_ptrs<T, 6>(P + offsetof(BwdPtrs<T>, gA) + 8 * salt);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) st_plane<T>(po.p[c], n, i, gA[c]);
+    for (int c = 0; c < 6; ++c) st_plane<T, kStream>(po.p[c], n, i, gA[c]);
 }
 
 template <typename T, int BS, int MPL>
@@ -982,7 +999,7 @@ template <typename T> struct TableInputs {
 
 template <typename T, int MPL>
 __device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, cptr<GroupDesc<T>> g, uint32_t base) {
-    load_wtile3<T, MPL, false>(in, TableInputs<T>{g}, (uint32_t)g->n, base);
+    load_wtile3<T, MPL, false, kCached>(in, TableInputs<T>{g}, (uint32_t)g->n, base);
 }
 
 // One 2x2 wave tile of a mixed batch from inputs already in registers.
@@ -995,7 +1012,7 @@ __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space
                        g.p3.out[O_D + 2], g.p3.out[O_D + 3], g.p3.out[O_PHI]};
 #pragma unroll
     for (int k = 0; k < MPL; ++k)
-        eig2_lane<T>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, n, base + k * WAVE + lane);
+        eig2_lane<T, kCached>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, n, base + k * WAVE + lane);
 }
 
 // One persistent launch over all groups.  Wave tile t is described by
@@ -1028,8 +1045,8 @@ void k_mixed(MixedArgs<T> a) {
         const auto &g = groups[cur.group];
         const uint32_t n = (uint32_t)g.n;
         if (g.kind == 3)
-            wtile_eig3<T, PATH, MPL, false>(planes_of(cur.group), planes_of, cur.group, a.prm, in_cur, n,
-                                            cur.base, my, qn, qage, refined, nonfinite);
+            wtile_eig3<T, PATH, MPL, false, kCached>(planes_of(cur.group), planes_of, cur.group, a.prm,
+                                                     in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
         else
             wtile_eig2_in<T, MPL>(g, in_cur, cur.base);
         cur = nxt;
