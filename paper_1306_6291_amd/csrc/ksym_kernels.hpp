@@ -736,14 +736,16 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
 // they have finished their tiles: the leftovers are pooled (entry e of the
 // concatenated queues goes to lane e % 64 of wave (e / 64) % NW), so a
 // workgroup pays for one partly filled refinement round instead of one per
-// wave.  Each wave first waits for its own stores, because a refined result
-// may now overwrite a provisional one that another wave wrote.
+// wave.  A wave with queued entries first waits for its own stores, because
+// a refined result may now overwrite a provisional one that this wave wrote
+// and another wave refines; a wave with an empty queue (most of them) has no
+// store that anything overwrites and goes straight to the barrier.
 template <typename T, int MPL, bool AOS, int NW, typename PlanesOf>
 __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
                                             int *qcount, int qn, unsigned &refined) {
     const int w = wave_id();
     const int lane = lane_id();
-    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
+    if (qn > 0) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
     if (lane == 0) qcount[w] = qn;
     __syncthreads();
     int pre[NW + 1];
