@@ -785,10 +785,13 @@ __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refine
 // float32: an occupancy target makes the compiler fit the kernel into the
 // registers of 6 waves per SIMD (80 VGPRs) with one matrix per lane and of
 // 5 waves (96) with two; two matrices per lane at 6 waves would spill, and
-// their queue's LDS allows 5 waves per SIMD anyway.
+// their queue's LDS allows 5 waves per SIMD anyway.  The plain float64 path
+// runs faster at 4 waves (128 VGPRs, a few spills) than at 3; the checked
+// one does not, and neither does the mixed-batch kernel at a higher target.
 template <typename T, int PATH, int BS, int MPL, bool AOS>
 __global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MPL == 1 ? 6 : MPL == 2 ? 5 : 1) : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MPL == 1 ? 6 : MPL == 2 ? 5 : 1)
+                                                  : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1))))
 void k_eig3(Eig3Args<T> args) {
     constexpr int NW = BS / WAVE;
     constexpr int WT = WAVE * MPL;
