@@ -80,7 +80,12 @@ template <typename T> struct Out3 {
     double lc;   // isolated eigenvalue (scaled units) handed to the refinement
 };
 
-__device__ __forceinline__ double pow2(int e) { return __builtin_ldexp(1.0, e); }
+// x * 2^e with one rounding for any e (exact unless the result is subnormal).
+// The scale factors themselves would leave the range: a float64 matrix whose
+// entries are all subnormal has e < -1022, and float32 entries near the top
+// of the range have e = 128.
+__device__ __forceinline__ double sc2(double x, int e) { return __builtin_ldexp(x, e); }
+__device__ __forceinline__ float sc2(float x, int e) { return __builtin_ldexpf(x, e); }
 
 // One 3x3 matrix through §4-§5 on the plain float64 path: the general branch
 // with v, w of (5.1)-(5.2) as printed, or the paper's double-root branch
@@ -94,10 +99,9 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
 #pragma unroll
     for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs((double)ain[c]));
     const int ex = fin ? scale_exponent(amax) : 0;
-    const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = fin ? (double)ain[c] * sc : 0.0;
+    for (int c = 0; c < 6; ++c) a[c] = fin ? sc2((double)ain[c], -ex) : 0.0;
     const double a11 = a[0], a22 = a[1], a33 = a[2], a12 = a[3], a13 = a[4], a23 = a[5];
     const Cubic cu = cubic_stage(a11, a22, a33, a12, a13, a23);
     o.refine = false;
@@ -106,7 +110,7 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
         // §5, p = 0: A = lam I with lam = A11; D = I, angles 0.
 #pragma unroll
         for (int i = 0; i < 9; ++i) o.v[O_D + i] = (i % 4 == 0) ? T(1) : T(0);
-        o.v[O_LAM] = o.v[O_LAM + 1] = o.v[O_LAM + 2] = (T)(cu.m * isc);
+        o.v[O_LAM] = o.v[O_LAM + 1] = o.v[O_LAM + 2] = (T)sc2(cu.m, ex);
         o.v[O_PHI] = o.v[O_PHI + 1] = o.v[O_PHI + 2] = T(0);
         o.v[O_GAP] = o.v[O_GAP + 1] = o.v[O_GAP + 2] = T(0);
         o.flag = FLAG_TRIPLE;
@@ -139,10 +143,10 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
                 L[0] = lm; L[1] = ls; L[2] = lm;
             }
             extract_angles<T>(o.v + O_D, o.v + O_PHI);
-            for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)((cu.m + L[k]) * isc);
-            o.v[O_GAP] = (T)((L[0] - L[1]) * isc);
-            o.v[O_GAP + 1] = (T)((L[0] - L[2]) * isc);
-            o.v[O_GAP + 2] = (T)((L[2] - L[1]) * isc);
+            for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)sc2(cu.m + L[k], ex);
+            o.v[O_GAP] = (T)sc2(L[0] - L[1], ex);
+            o.v[O_GAP + 1] = (T)sc2(L[0] - L[2], ex);
+            o.v[O_GAP + 2] = (T)sc2(L[2] - L[1], ex);
             o.flag = FLAG_DOUBLE;
         } else {
             // general branch (5.1)-(5.15), with the eigenvalue differences
@@ -156,12 +160,12 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
             const Rot<T> R = select_angles<T>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
             build_D(R, o.v + O_D);
             angles_of(R, o.v + O_PHI);
-            o.v[O_LAM] = (T)((cu.m + cu.mu1) * isc);
-            o.v[O_LAM + 1] = (T)((cu.m + cu.mu2) * isc);
-            o.v[O_LAM + 2] = (T)((cu.m + cu.mu3) * isc);
-            o.v[O_GAP] = (T)(cu.g12 * isc);
-            o.v[O_GAP + 1] = (T)(cu.g13 * isc);
-            o.v[O_GAP + 2] = (T)(cu.g32 * isc);
+            o.v[O_LAM] = (T)sc2(cu.m + cu.mu1, ex);
+            o.v[O_LAM + 1] = (T)sc2(cu.m + cu.mu2, ex);
+            o.v[O_LAM + 2] = (T)sc2(cu.m + cu.mu3, ex);
+            o.v[O_GAP] = (T)sc2(cu.g12, ex);
+            o.v[O_GAP + 1] = (T)sc2(cu.g13, ex);
+            o.v[O_GAP + 2] = (T)sc2(cu.g32, ex);
             o.flag = FLAG_GENERAL;
         }
     }
@@ -193,10 +197,9 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
                                                                  __builtin_fabsf(ain[4])),
                                                  __builtin_fabsf(ain[5])));
     const int ex = scale_exponent((double)amax);
-    const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = (double)ain[c] * sc;
+    for (int c = 0; c < 6; ++c) a[c] = sc2((double)ain[c], -ex);
     const Cubic cu = cubic_stage_gaps(a[0], a[1], a[2], a[3], a[4], a[5]);
     const bool fin = cu.fin;
     lc = 0.0;
@@ -214,9 +217,9 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const int flag = special ? (fin ? FLAG_TRIPLE : FLAG_NONFINITE) : (dbl ? FLAG_DOUBLE : FLAG_GENERAL);
     sink.flag(flag);
     {
-        const float lam[3] = {(float)((cu.m + cu.mu1) * isc), (float)((cu.m + cu.mu2) * isc),
-                              (float)((cu.m + cu.mu3) * isc)};
-        const float gap[3] = {(float)(cu.g12 * isc), (float)(cu.g13 * isc), (float)(cu.g32 * isc)};
+        const float lam[3] = {(float)sc2(cu.m + cu.mu1, ex), (float)sc2(cu.m + cu.mu2, ex),
+                              (float)sc2(cu.m + cu.mu3, ex)};
+        const float gap[3] = {(float)sc2(cu.g12, ex), (float)sc2(cu.g13, ex), (float)sc2(cu.g32, ex)};
         sink.template put_n<3>(O_LAM, lam);
         sink.template put_n<3>(O_GAP, gap);
     }
@@ -268,10 +271,9 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
 #pragma unroll
     for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs(ain[c]));
     const int ex = scale_exponent(amax);
-    const double sc = pow2(-ex), isc = pow2(ex);
     double a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = ain[c] * sc;
+    for (int c = 0; c < 6; ++c) a[c] = sc2(ain[c], -ex);
     const Cubic cu = cubic_stage(a[0], a[1], a[2], a[3], a[4], a[5]);
     const bool fin = cu.fin;
     const double split = fmin(cu.g13, cu.g32);
@@ -279,8 +281,8 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
     const int flag = !fin ? FLAG_NONFINITE : (cu.triple ? FLAG_TRIPLE : (dbl ? FLAG_DOUBLE : FLAG_GENERAL));
     sink.flag(flag);
     {
-        const double lam[3] = {(cu.m + cu.mu1) * isc, (cu.m + cu.mu2) * isc, (cu.m + cu.mu3) * isc};
-        const double gap[3] = {cu.g12 * isc, cu.g13 * isc, cu.g32 * isc};
+        const double lam[3] = {sc2(cu.m + cu.mu1, ex), sc2(cu.m + cu.mu2, ex), sc2(cu.m + cu.mu3, ex)};
+        const double gap[3] = {sc2(cu.g12, ex), sc2(cu.g13, ex), sc2(cu.g32, ex)};
         sink.template put_n<3>(O_LAM, lam);
         sink.template put_n<3>(O_GAP, gap);
     }
@@ -323,24 +325,23 @@ __device__ __forceinline__ void refine_one(const T ain[6], double lc, int flag, 
 #pragma unroll
     for (int c = 0; c < 6; ++c) amax = fmax(amax, __builtin_fabs((double)ain[c]));
     const int ex = scale_exponent(amax);
-    const double sc = pow2(-ex), isc = pow2(ex);
     double m, d1, d2, d3;
-    center3((double)ain[0] * sc, (double)ain[1] * sc, (double)ain[2] * sc, m, d1, d2, d3);
-    const Refined rf = refine3(d1, d2, d3, (double)ain[3] * sc, (double)ain[4] * sc,
-                               (double)ain[5] * sc, lc);
+    center3(sc2((double)ain[0], -ex), sc2((double)ain[1], -ex), sc2((double)ain[2], -ex), m, d1, d2, d3);
+    const Refined rf = refine3(d1, d2, d3, sc2((double)ain[3], -ex), sc2((double)ain[4], -ex),
+                               sc2((double)ain[5], -ex), lc);
 #pragma unroll
     for (int i = 0; i < 9; ++i) o.v[O_D + i] = (T)rf.D[i];
     extract_angles<T>(o.v + O_D, o.v + O_PHI);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)((m + rf.lam[k]) * isc);
-    o.v[O_GAP] = (T)(fmax(rf.lam[0] - rf.lam[1], 0.0) * isc);
-    o.v[O_GAP + 1] = (T)(fmax(rf.lam[0] - rf.lam[2], 0.0) * isc);
-    o.v[O_GAP + 2] = (T)(fmax(rf.lam[2] - rf.lam[1], 0.0) * isc);
+    for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)sc2(m + rf.lam[k], ex);
+    o.v[O_GAP] = (T)sc2(fmax(rf.lam[0] - rf.lam[1], 0.0), ex);
+    o.v[O_GAP + 1] = (T)sc2(fmax(rf.lam[0] - rf.lam[2], 0.0), ex);
+    o.v[O_GAP + 2] = (T)sc2(fmax(rf.lam[2] - rf.lam[1], 0.0), ex);
     o.flag = flag | FLAG_FIXUP;
     if (is_special(flag)) {
         const bool fin = flag != FLAG_NONFINITE;
         const T nan = (T)__builtin_nan("");
-        const T lam = fin ? (T)(m * isc) : nan, one = fin ? T(1) : nan, zero = fin ? T(0) : nan;
+        const T lam = fin ? (T)sc2(m, ex) : nan, one = fin ? T(1) : nan, zero = fin ? T(0) : nan;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             o.v[O_LAM + k] = lam;
@@ -858,10 +859,9 @@ __device__ __forceinline__ void eig2_lane(T a11, T a22, T a12, T *const out[7], 
     const double amax = fmax(fmax(__builtin_fabs((double)a11), __builtin_fabs((double)a22)),
                              __builtin_fabs((double)a12));
     const int ex = fin ? scale_exponent(amax) : 0;
-    const T sc = (T)pow2(-ex), isc = (T)pow2(ex);
-    Eig2<T> e = eig2_one<T>(a11 * sc, a22 * sc, a12 * sc);
-    e.l1 *= isc;
-    e.l2 *= isc;
+    Eig2<T> e = eig2_one<T>(sc2(a11, -ex), sc2(a22, -ex), sc2(a12, -ex));
+    e.l1 = sc2(e.l1, ex);
+    e.l2 = sc2(e.l2, ex);
     if (!fin) {
         const T nan = T(__builtin_nan(""));
         e.l1 = e.l2 = e.c = e.s = e.phi = nan;

@@ -217,6 +217,38 @@ def test_default_launch_shape_f64_bitwise(ksym):
             assert np.array_equal(g[k], base[k]), (opt, k)
 
 
+@pytest.mark.parametrize("dtype,k", [("float64", -1040), ("float64", -1000), ("float64", 1021),
+                                     ("float32", -135), ("float32", 120), ("float32", 126)])
+def test_power_of_two_scaling_extremes(ksym, dtype, k):
+    """Every path first scales a matrix by a power of two, so A and B = A 2^-k
+    (exact) give the same D, angles and flags bit for bit, and eigenvalues
+    and gaps that differ by the factor 2^k (one rounding each; a float32
+    result in the subnormal range may differ by one unit there, as it is
+    rounded twice on the host side).  The k reach float64 matrices with
+    subnormal entries only and float32 ones near the top of the range, where
+    the scale factors themselves are not representable."""
+    f64 = dtype == "float64"
+    np_dt = np.float64 if f64 else np.float32
+    P = synth.make_plain(1500, 16, seed=1234)["planes3"].astype(np_dt)
+    P = np.concatenate([P, synth.make_precision(1500, seed=1235).astype(np_dt)], axis=1)
+    A = np.ldexp(P, k).astype(np_dt)
+    B = np.ldexp(A, -k).astype(np_dt)
+    assert np.all(np.isfinite(A)) and np.array_equal(np.ldexp(B, k).astype(np_dt), A)
+    tdt = torch.float64 if f64 else torch.float32
+    for path in ((ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP) if f64 else (None,)):
+        gA = _run(ksym, A, tdt, path=path)
+        gB = _run(ksym, B, tdt, path=path)
+        for key in ("D", "phi", "flags"):
+            assert np.array_equal(gA[key], gB[key]), (path, key)
+        for key in ("lam", "gap"):
+            want = np.ldexp(gB[key], k).astype(np_dt)
+            if f64:
+                assert np.array_equal(gA[key], want), (path, key)
+            else:
+                diff = np.abs(gA[key].astype(np.float64) - want.astype(np.float64))
+                assert diff.max() <= 2.0 ** -149, (key, diff.max())
+
+
 def test_all_matrices_refined_f32(ksym):
     """A batch where every matrix takes the refinement (exact doubles):
     the on-chip queue fills completely at every launch shape."""

@@ -81,6 +81,31 @@ def test_eig2_special_cases_and_shapes(ksym):
             assert np.array_equal(g[k], base[k]), (block, mpl, k)
 
 
+@pytest.mark.parametrize("dtype,k", [("float64", -1040), ("float64", 1022), ("float32", -135),
+                                     ("float32", 128)])
+def test_eig2_power_of_two_scaling_extremes(ksym, dtype, k):
+    """A and B = A 2^-k (exact) give the same D, angle and flags bit for bit
+    and eigenvalues that differ by exactly 2^k, also where the scale factor
+    2^k or 2^-k is not representable (float64 matrices with subnormal
+    entries only; float32 ones with max|A_ij| >= 2^127)."""
+    np_dt = np.float64 if dtype == "float64" else np.float32
+    rng = np.random.default_rng(404)
+    n = 3000
+    # |A11|, |A22| <= 0.6, |A12| <= 0.3 keeps |lam| < 2^k at the top of the range
+    P = np.stack([rng.uniform(-0.6, 0.6, n), rng.uniform(-0.6, 0.6, n), rng.uniform(-0.3, 0.3, n)])
+    P = P.astype(np_dt)
+    A = np.ldexp(P, k).astype(np_dt)
+    B = np.ldexp(A, -k).astype(np_dt)
+    assert np.all(np.isfinite(A)) and np.array_equal(np.ldexp(B, k).astype(np_dt), A)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    gA = to_np(ksym.eig2(to_dev(A, tdt)))
+    gB = to_np(ksym.eig2(to_dev(B, tdt)))
+    for key in ("D", "phi", "flags"):
+        assert np.array_equal(gA[key], gB[key]), key
+    assert np.all(np.isfinite(gA["lam"]))
+    assert np.array_equal(gA["lam"], np.ldexp(gB["lam"], k).astype(np_dt))
+
+
 # ------------------------------------------------------------- adjoint -----
 def test_backward_f64_matches_oracle_adjoint(ksym):
     """The adjoint kernel computes the same float64 formula as the oracle's
