@@ -287,7 +287,9 @@ def test_aos_matches_soa(ksym):
             assert np.array_equal(out[k], soa[k]), (block, mpl, k)
     P64 = synth.make_plain(3001, 16, seed=3)["planes3"]
     soa = _run(ksym, P64, torch.float64, path=ksym.PATH_FP64_FIXUP)
-    out = to_np(ksym.eig3_aos(to_dev(np.ascontiguousarray(P64.T), torch.float64),
+    o64 = ksym.Opts.defaults(ksym.F64)
+    o64.path = ksym.PATH_FP64_FIXUP
+    out = to_np(ksym.eig3_aos(to_dev(np.ascontiguousarray(P64.T), torch.float64), opts=o64,
                               outputs=("lam", "D", "phi", "gap", "flags")))
     for k in ("lam", "D", "phi", "gap", "flags"):
         assert np.array_equal(out[k], soa[k]), k

@@ -302,14 +302,17 @@ def test_field_workload_aos_forward_backward(ksym):
     rec = d["aos"]
     P32 = np.ascontiguousarray(rec.T)
     P64 = P32.astype(np.float64)
-    out = ksym.eig3_aos(to_dev(rec, torch.float32), outputs=("lam", "D", "phi", "gap", "flags"))
+    # one set of options for both layouts (without one, each call would take
+    # its own tuned thresholds, which may differ)
+    o = ksym.Opts.defaults(ksym.F32)
+    out = ksym.eig3_aos(to_dev(rec, torch.float32), opts=o, outputs=("lam", "D", "phi", "gap", "flags"))
     g = to_np(out)
     lam_ref, V_ref = certified_reference(P64)
     check_f32_result(P64, g, lam_ref, V_ref, "field")
     iso = d["iso"]
     assert np.all(g["flags"][iso] == 2)
     assert np.all(g["D"][:, iso] == np.array([1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)[:, None])
-    soa = to_np(ksym.eig3(to_dev(P32, torch.float32), outputs=("lam", "D", "phi", "gap", "flags")))
+    soa = to_np(ksym.eig3(to_dev(P32, torch.float32), opts=o, outputs=("lam", "D", "phi", "gap", "flags")))
     for k in g:
         assert np.array_equal(g[k], soa[k]), k
     gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
