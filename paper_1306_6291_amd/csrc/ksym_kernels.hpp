@@ -789,10 +789,19 @@ __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refine
 // their queue's LDS allows 5 waves per SIMD anyway.  The plain float64 path
 // runs faster at 4 waves (128 VGPRs, a few spills) than at 3; the checked
 // one does not, and neither does the mixed-batch kernel at a higher target.
+// The target never exceeds what the workgroup's LDS allows (160 KB per CU).
+template <typename T, int PATH, int BS, int MPL, bool AOS>
+constexpr int eig3_waves_target() {
+    constexpr int NW = BS / WAVE;
+    constexpr int want = sizeof(T) == 4 ? (MPL == 1 ? 6 : MPL == 2 ? 5 : 1)
+                                        : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1);
+    constexpr size_t lds = NW * (sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>) + sizeof(int));
+    constexpr int by_lds = (int)(163840 / lds) * NW / 4;
+    return want < by_lds ? want : (by_lds > 1 ? by_lds : 1);
+}
 template <typename T, int PATH, int BS, int MPL, bool AOS>
 __global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MPL == 1 ? 6 : MPL == 2 ? 5 : 1)
-                                                  : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu(eig3_waves_target<T, PATH, BS, MPL, AOS>())))
 void k_eig3(Eig3Args<T> args) {
     constexpr int NW = BS / WAVE;
     constexpr int WT = WAVE * MPL;
