@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TLANE = 256 * 64 * 2.4e9 / 1e12   # 39.3 T lane-instructions/s
 BYTES_3X3_F32 = 84      # 24 in + 60 out (lam 12, D 36, phi 12)
 BYTES_3X3_F64 = 168
+BYTES_3X3_LAM_F32 = 36  # eigenvalues-only mode: 24 in + 12 out (lam)
 BYTES_2X2_F32 = 40      # 12 in + 28 out (lam 8, D 16, phi 4)
 BYTES_BWD_F32 = 120     # lam 12 + D 36 + glam 12 + gD 36 in, gA 24 out
 
@@ -184,6 +185,15 @@ def bench_precision(args, torch, ksym, synth):
            "opts": opts.as_dict()}
     if args.accuracy:
         res["accuracy"] = _accuracy(P32, out, args.accuracy, torch)
+    # reduced-output mode on the same matrices: eigenvalues only (no D, no
+    # angles), which runs the eigenvalues-only kernel; reported beside the
+    # metric, not in it
+    lam_only = {"lam": out["lam"]}
+    ms_l, _ = _time_steps(lambda: ksym.eig3(A, opts=opts, out=lam_only), max(3, args.steps // 2),
+                          max(2, args.warmup // 2), torch)
+    res["lam_only"] = {"value": n / (ms_l * 1e-3), "ms_per_step": ms_l, "bytes_per_matrix": BYTES_3X3_LAM_F32,
+                       "achieved_GBs": BYTES_3X3_LAM_F32 * n / (ms_l * 1e-3) / 1e9,
+                       "kernel": "k_eig3_lam (outputs lam only)"}
     # float64 GPU path on the same matrices
     if not args.no_fp64:
         del out
@@ -371,6 +381,8 @@ def main():
             line["cpu_baseline"] = r["cpu"]
         if "fp64" in r:
             line["fp64_path"] = r["fp64"]
+        if "lam_only" in r:
+            line["eigenvalues_only"] = r["lam_only"]
         if "accuracy" in r:
             line["accuracy"] = r["accuracy"]
         print(json.dumps(line), flush=True)

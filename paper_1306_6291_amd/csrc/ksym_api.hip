@@ -111,6 +111,25 @@ template <typename T, int PATH, bool AOS> using Eig3K = void (*)(Eig3Args<T>);
 
 template <typename T, int PATH, bool AOS> Eig3K<T, PATH, AOS> pick_eig3(int bs, int mpl);
 
+// eigenvalues-only kernel (float32 SoA), the same launch shapes as k_eig3<float>
+using LamK = void (*)(Eig3Args<float>);
+LamK pick_eig3_lam(int bs, int mpl) {
+#define KSYM_L(B, M) \
+    if (bs == B && mpl == M) return &k_eig3_lam<B, M>;
+    KSYM_L(64, 1) KSYM_L(64, 2) KSYM_L(128, 1) KSYM_L(128, 2) KSYM_L(256, 1) KSYM_L(256, 2) KSYM_L(512, 1)
+    KSYM_L(512, 2)
+#undef KSYM_L
+    return nullptr;
+}
+
+// true when none of the k planes of an output array is requested
+bool none_requested(void *const *planes, int k) {
+    if (!planes) return true;
+    for (int c = 0; c < k; ++c)
+        if (planes[c]) return false;
+    return true;
+}
+
 template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXUP, false>(int bs, int mpl) {
     KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 2)
@@ -207,7 +226,9 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     (void)ws_bytes;
     void (*k)(Eig3Args<T>) = nullptr;
     if constexpr (sizeof(T) == 4) {
-        k = pick_eig3<float, PATH_FP32_FIXUP, AOS>(o.block, o.mats_per_lane);
+        // no D and no angles: the eigenvalues-only kernel (reduced-output mode)
+        if (!AOS && none_requested(D, 9) && none_requested(phi, 3)) k = pick_eig3_lam(o.block, o.mats_per_lane);
+        else k = pick_eig3<float, PATH_FP32_FIXUP, AOS>(o.block, o.mats_per_lane);
     } else {
         if (o.path == KSYM_PATH_FP64_PLAIN) k = pick_eig3<double, PATH_FP64_PLAIN, AOS>(o.block, o.mats_per_lane);
         else k = pick_eig3<double, PATH_FP64_FIXUP, AOS>(o.block, o.mats_per_lane);

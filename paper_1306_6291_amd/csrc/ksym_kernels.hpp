@@ -849,6 +849,73 @@ void k_eig3(Eig3Args<T> args) {
     add_counters(args.prm.counters, refined, nonfinite);
 }
 
+// ------------------------------------------------------ eigenvalues only ---
+// Reduced-output mode (float32): with no D and no angle planes requested the
+// float64 cubic stage of §4 alone gives the eigenvalues, the gaps and the
+// flag, as accurate as the full path's (its refinement exists for the
+// eigenvectors), so the angle solve, the check and the refinement queue are
+// skipped.  The arithmetic and the stores are those of eig3_f32, so lam, gap
+// and flags are bitwise the full kernel's for every matrix it does not
+// refine; the FIXUP bit is never set.  A non-finite input gets NaN outputs.
+template <typename Sink>
+__device__ __forceinline__ int eig3_lam_f32(const float ain[6], const Eig3Params &prm, const Sink &sink) {
+    float amax = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[0]), __builtin_fabsf(ain[1])),
+                                 __builtin_fabsf(ain[2]));
+    amax = __builtin_fmaxf(amax, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[3]),
+                                                                 __builtin_fabsf(ain[4])),
+                                                 __builtin_fabsf(ain[5])));
+    const int ex = scale_exponent((double)amax);
+    double a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = sc2((double)ain[c], -ex);
+    const Cubic cu = cubic_stage_gaps(a[0], a[1], a[2], a[3], a[4], a[5]);
+    const bool fin = cu.fin;
+    const double split = cu.g13 < cu.g32 ? cu.g13 : cu.g32;
+    const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
+    const bool special = cu.triple || !fin;
+    const int flag = special ? (fin ? FLAG_TRIPLE : FLAG_NONFINITE) : (dbl ? FLAG_DOUBLE : FLAG_GENERAL);
+    sink.flag(flag);
+    const float nan = __builtin_nanf("");
+    const float lam[3] = {fin ? (float)sc2(cu.m + cu.mu1, ex) : nan, fin ? (float)sc2(cu.m + cu.mu2, ex) : nan,
+                          fin ? (float)sc2(cu.m + cu.mu3, ex) : nan};
+    const float gap[3] = {fin ? (float)sc2(cu.g12, ex) : nan, fin ? (float)sc2(cu.g13, ex) : nan,
+                          fin ? (float)sc2(cu.g32, ex) : nan};
+    sink.template put_n<3>(O_LAM, lam);
+    sink.template put_n<3>(O_GAP, gap);
+    return flag;
+}
+
+// Wave tiles of 64*MPL matrices, grid-stride, straight from and to HBM (no
+// queue and no LDS).
+template <int BS, int MPL>
+__global__ __launch_bounds__(BS) void k_eig3_lam(Eig3Args<float> args) {
+    constexpr int NW = BS / WAVE;
+    constexpr int WT = WAVE * MPL;
+    const uint32_t n = (uint32_t)args.prm.n;
+    const uint32_t ntiles = (n + WT - 1) / WT;
+    KernargPlanes<float> pl;
+    pl.out_off = (uint32_t)(offsetof(Eig3Args<float>, p) + offsetof(Eig3Ptrs<float>, out));
+    pl.flags_off = (uint32_t)(offsetof(Eig3Args<float>, p) + offsetof(Eig3Ptrs<float>, flags));
+    pl.n = n;
+    const int lane = lane_id();
+    unsigned nonfinite = 0;
+    for (uint32_t t = blockIdx.x * NW + wave_id(); t < ntiles; t += gridDim.x * NW) {
+        const int salt = (int)(t * (uint32_t)args.prm.zero);
+        WIn<float, MPL, false> in;
+        load_wtile3<float, MPL, false, kStream>(
+            in, KernargInputs<float>{(uint32_t)(offsetof(Eig3Args<float>, p) + offsetof(Eig3Ptrs<float>, in)),
+                                     (uint32_t)offsetof(Eig3Args<float>, aos), salt},
+            n, t * WT);
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) {
+            const uint32_t off = t * WT + k * WAVE + lane;
+            const int flag = eig3_lam_f32(in.a[k], args.prm, LaneSink<float, kStream, KernargPlanes<float>>{pl, salt, off});
+            nonfinite += (unsigned)__popcll(__ballot(off < n && flag == FLAG_NONFINITE));
+        }
+    }
+    add_counters(args.prm.counters, 0, nonfinite);
+}
+
 // ------------------------------------------------------------- 2x2 ---------
 template <typename T> struct Eig2Ptrs {
     const T *in[3];

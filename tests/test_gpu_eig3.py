@@ -7,7 +7,7 @@ import pytest
 import oracle
 import synth
 from tests import helpers as H
-from tests.gpu_common import (LAM_TOL_F64, RES_TOL_F64, VEC_TOL_F64, certified_reference,
+from tests.gpu_common import (LAM_TOL_F32, LAM_TOL_F64, RES_TOL_F64, VEC_TOL_F64, certified_reference,
                               check_f32_result, to_dev, to_np)
 
 pytestmark = pytest.mark.gpu
@@ -247,6 +247,47 @@ def test_power_of_two_scaling_extremes(ksym, dtype, k):
             else:
                 diff = np.abs(gA[key].astype(np.float64) - want.astype(np.float64))
                 assert diff.max() <= 2.0 ** -149, (key, diff.max())
+
+
+def test_eigenvalues_only_mode_f32(ksym):
+    """Reduced-output mode: float32 with no D and no angle planes runs the
+    eigenvalues-only kernel.  Flags are the full path's without the FIXUP
+    bit; lam and gap are bitwise the full path's wherever that path did not
+    refine, and within the float32 tolerance of the certified reference
+    everywhere; ragged sizes and launch shapes give the same bits; a
+    non-finite input gives NaN and flag 8, and is counted."""
+    n = (1 << 17) + 77
+    P32 = synth.make_precision(n, seed=1306631)
+    P64 = P32.astype(np.float64)
+    lam_ref, _ = certified_reference(P64)
+    full = _run(ksym, P32, torch.float32)
+    lam_only = _run(ksym, P32, torch.float32, outputs=("lam", "gap", "flags"))
+    assert "D" not in lam_only and "phi" not in lam_only
+    assert np.array_equal(lam_only["flags"], full["flags"] & ~np.uint8(4))
+    kept = (full["flags"] & 4) == 0
+    assert kept.mean() > 0.99
+    for k in ("lam", "gap"):
+        assert np.array_equal(lam_only[k][:, kept], full[k][:, kept]), k
+    err = H.sorted_lam_err(P64, lam_only["lam"].astype(np.float64), lam_ref)
+    assert err.max() <= LAM_TOL_F32, err.max()
+    assert int(lam_only["ws"][0]) == 0
+    for m in (1, 63, 65, 4999):
+        Pm = np.ascontiguousarray(P32[:, :m])
+        g = _run(ksym, Pm, torch.float32, outputs=("lam", "gap", "flags"))
+        for k in ("lam", "gap", "flags"):
+            assert np.array_equal(g[k], lam_only[k][..., :m]), (m, k)
+    for block, mpl, gm in ((64, 2, 1), (256, 1, 1024), (512, 2, 16)):
+        g = _run(ksym, P32, torch.float32, outputs=("lam", "flags"), block=block, mats_per_lane=mpl,
+                 grid_mult=gm)
+        for k in ("lam", "flags"):
+            assert np.array_equal(g[k], lam_only[k]), (block, mpl, gm, k)
+    bad = np.array([[np.nan, 0, 0, 0, 0, 0], [0, np.inf, 0, 0, 0, 0], [1, 1, 1, 0, -np.inf, 0],
+                    [2, 1, 0, 0.5, 0, 0]], dtype=np.float32).T
+    g = _run(ksym, np.ascontiguousarray(bad), torch.float32, outputs=("lam", "gap", "flags"))
+    assert np.array_equal(g["flags"], np.array([8, 8, 8, 0], np.uint8))
+    assert np.all(np.isnan(g["lam"][:, :3])) and np.all(np.isnan(g["gap"][:, :3]))
+    assert np.all(np.isfinite(g["lam"][:, 3]))
+    assert int(g["ws"][1]) == 3
 
 
 def test_all_matrices_refined_f32(ksym):
