@@ -189,11 +189,13 @@ def bench_precision(args, torch, ksym, synth):
     # angles), which runs the eigenvalues-only kernel; reported beside the
     # metric, not in it
     lam_only = {"lam": out["lam"]}
-    ms_l, _ = _time_steps(lambda: ksym.eig3(A, opts=opts, out=lam_only), max(3, args.steps // 2),
+    opts_l = ksym.tuned_opts("eig3_lam", ksym.F32)
+    ms_l, _ = _time_steps(lambda: ksym.eig3(A, opts=opts_l, out=lam_only), max(3, args.steps // 2),
                           max(2, args.warmup // 2), torch)
     res["lam_only"] = {"value": n / (ms_l * 1e-3), "ms_per_step": ms_l, "bytes_per_matrix": BYTES_3X3_LAM_F32,
                        "achieved_GBs": BYTES_3X3_LAM_F32 * n / (ms_l * 1e-3) / 1e9,
-                       "kernel": "k_eig3_lam (outputs lam only)"}
+                       "kernel": "k_eig3_lam (outputs lam only)", "block": opts_l.block,
+                       "mats_per_lane": opts_l.mats_per_lane, "grid_mult": opts_l.grid_mult}
     # float64 GPU path on the same matrices
     if not args.no_fp64:
         del out

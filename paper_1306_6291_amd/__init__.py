@@ -227,7 +227,10 @@ def eig3(planes, opts=None, path=None, outputs=("lam", "D", "phi", "flags"), out
     refined and non-finite matrices."""
     ptrs, n, ref = _rows(planes, 6)
     dt = _dt(ref)
-    o = _opts(dt, opts, path=path, _kind="eig3")
+    # no D and no angles (float32): the eigenvalues-only kernel, tuned apart
+    wanted = (lambda k: out.get(k) is not None) if out is not None else (lambda k: k in outputs)
+    lam_only = dt == F32 and not wanted("D") and not wanted("phi")
+    o = _opts(dt, opts, path=path, _kind="eig3_lam" if lam_only else "eig3")
     if out is None:
         out = _alloc3(n, ref, outputs)
     lam, D, phi, gap, fl = _out_ptrs3(out)

@@ -19,6 +19,7 @@ Workloads (seeded, synthetic; the generators in synth.py):
   eig3/f64       the precision recipe promoted to float64, checked path
   mixed/f32      2^26 mixed 2x2 / 3x3 in 1024 groups, one graph-captured plan
   eig2/f32       2^24 float32 2x2, U[-1, 1]
+  eig3_lam/f32   the precision recipe, eigenvalues only (no D, no angles)
 
 Run on a GPU:  python -m paper_1306_6291_amd.autotune [--kinds eig3/f32,...] [--quick]
 """
@@ -223,9 +224,35 @@ def tune_eig2(log, shapes):
     return {"ms": ms, "opts": dict(sh), "n": n}
 
 
+def tune_eig3_lam(log, shapes):
+    """The eigenvalues-only mode (float32, no D and no angle planes): launch
+    shapes only (it has no refinement thresholds); the eigenvalues are checked
+    against LAPACK on a sample."""
+    import synth
+    n = 1 << 24
+    P = torch.from_numpy(synth.make_precision(n)).cuda()
+    out = {"lam": torch.empty((3, n), device="cuda")}
+    log(f"[eig3_lam/f32] {len(shapes)} launch shapes")
+    res = _sweep(lambda o: ksym.eig3(P, opts=o, out=out), ksym.F32, shapes, {}, log)
+    ms, sh = res[0]
+    ksym.eig3(P, opts=ksym.Opts.defaults(ksym.F32, **sh), out=out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    idx = torch.from_numpy(np.sort(rng.choice(n, size=1 << 15, replace=False))).cuda()
+    a11, a22, a33, a12, a13, a23 = P[:, idx].double().cpu().numpy()
+    A = np.stack([np.stack([a11, a12, a13], 1), np.stack([a12, a22, a23], 1), np.stack([a13, a23, a33], 1)], 1)
+    lam = np.sort(out["lam"][:, idx].double().cpu().numpy().T, axis=1)
+    fro = np.sqrt((A * A).sum((1, 2)))
+    err = float((np.abs(lam - np.linalg.eigvalsh(A)).max(1) / np.where(fro > 0, fro, 1)).max())
+    if not err <= LAM_TOL:
+        raise RuntimeError(f"eig3_lam/f32: eigenvalue error {err:g} above {LAM_TOL:g}")
+    return {"ms": ms, "opts": dict(sh), "n": n, "accuracy": {"lam_err_max": err}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="ksym autotuner (writes tuned.json)")
-    ap.add_argument("--kinds", default="eig3/f32,eig3_grad/f32,eig3_aos/f32,eig3/f64,mixed/f32,eig2/f32")
+    ap.add_argument("--kinds", default="eig3/f32,eig3_grad/f32,eig3_aos/f32,eig3/f64,mixed/f32,eig2/f32,"
+                                       "eig3_lam/f32")
     ap.add_argument("--quick", action="store_true", help="a smaller search space")
     ap.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
     args = ap.parse_args(argv)
@@ -278,6 +305,9 @@ def main(argv=None):
         elif kind == "eig2/f32":
             rec = tune_eig2(log, _shapes((64, 128, 256, 512, 1024), (1, 2, 4), gms, (0,)))
             rec["workload"] = "2^24 float32 2x2, U[-1,1]"
+        elif kind == "eig3_lam/f32":
+            rec = tune_eig3_lam(log, _shapes((64, 128, 256, 512), (1, 2), gms, (0,)))
+            rec["workload"] = "precision recipe, 2^24 float32, SoA, eigenvalues only"
         else:
             raise SystemExit(f"unknown kind {kind}")
         rec["device"] = dev
