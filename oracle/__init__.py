@@ -48,6 +48,7 @@ def _load():
         _lib.ko_eig2_batch.argtypes = [i64, P, P, P, P, cint]
         _lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
         _lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
+        _lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
         _lib.ko_eig3_dbg.argtypes = [P, dbl, P, P, P, P]
         _lib.ko_eig3_dbg.restype = cint
     return _lib
@@ -133,6 +134,25 @@ def eig3_bwd(lam, D, glam=None, gD=None, eps=0.0, threads=None):
         n, ctypes.cast(_ptrs(L), ctypes.c_void_p), ctypes.cast(_ptrs(Dp), ctypes.c_void_p),
         ctypes.cast(_ptrs(gl), ctypes.c_void_p) if gl else None,
         ctypes.cast(_ptrs(gd), ctypes.c_void_p) if gd else None,
+        ctypes.cast(_ptrs(list(gA)), ctypes.c_void_p), float(eps), threads or default_threads())
+    return gA
+
+
+def eig2_bwd(lam, D, glam=None, gD=None, gphi=None, eps=0.0, threads=None):
+    """2x2 adjoint: plane gradients gA (3, n) = (A11, A22, A12) from the
+    forward outputs and the cotangents of lam, D and phi (None = zero)."""
+    lib = _load()
+    L = _planes(lam, 2); Dp = _planes(D, 4)
+    n = L[0].size
+    gl = _planes(glam, 2) if glam is not None else None
+    gd = _planes(gD, 4) if gD is not None else None
+    gp = np.ascontiguousarray(np.asarray(gphi, dtype=np.float64).reshape(-1)) if gphi is not None else None
+    gA = np.empty((3, n))
+    lib.ko_eig2_bwd_batch(
+        n, ctypes.cast(_ptrs(L), ctypes.c_void_p), ctypes.cast(_ptrs(Dp), ctypes.c_void_p),
+        ctypes.cast(_ptrs(gl), ctypes.c_void_p) if gl else None,
+        ctypes.cast(_ptrs(gd), ctypes.c_void_p) if gd else None,
+        gp.ctypes.data if gp is not None else None,
         ctypes.cast(_ptrs(list(gA)), ctypes.c_void_p), float(eps), threads or default_threads())
     return gA
 

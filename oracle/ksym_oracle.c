@@ -468,10 +468,48 @@ void ko_eig3_bwd(const double lam[3], const double D9[9], const double glam[3],
 }
 
 /* ------------------------------------------------------------------------ */
+/* 2x2 adjoint (not in the paper), the same first-order result for          */
+/* A = D diag(lam1, lam2) D^T with D = R(phi) of eq. (2.5): E = D^T Dbar,    */
+/* Abar = D [diag(lam_bar) + F o E] D^T.  The angle enters through           */
+/* D^T dD = [[0, -dphi], [dphi, 0]], i.e. dphi = d2^T dA d1 / (lam1 - lam2), */
+/* so a cotangent phibar adds phibar to E_21.  Planes gA = (A11, A22, A12),  */
+/* gA12 = Abar_12 + Abar_21.                                                 */
+/* ------------------------------------------------------------------------ */
+void ko_eig2_bwd(const double lam[2], const double D4[4], const double glam[2], const double gD4[4],
+                 double gphi, double eps, double gA[3])
+{
+    double D[2][2], G[2][2], E[2][2], M[2][2], T[2][2], Abar[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            D[i][j] = D4[2 * i + j];
+            G[i][j] = gD4 ? gD4[2 * i + j] : 0.0;
+        }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) E[i][j] = D[0][i] * G[0][j] + D[1][i] * G[1][j];
+    E[1][0] += gphi;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            if (i == j) {
+                M[i][j] = glam ? glam[i] : 0.0;
+            } else {
+                double d = lam[j] - lam[i];
+                M[i][j] = d / (d * d + eps * eps) * E[i][j];
+            }
+        }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) T[i][j] = D[i][0] * M[0][j] + D[i][1] * M[1][j];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) Abar[i][j] = T[i][0] * D[j][0] + T[i][1] * D[j][1];
+    gA[0] = Abar[0][0];
+    gA[1] = Abar[1][1];
+    gA[2] = Abar[0][1] + Abar[1][0];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batch drivers over structure-of-arrays planes, split over host threads.  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int kind;                     /* 3: eig3, 2: eig2, 4: jacobi, 5: bwd */
+    int kind;                     /* 3: eig3, 2: eig2, 4: jacobi, 5: bwd, 6: 2x2 bwd */
     int64_t lo, hi;
     const double *in[24];
     double *out[16];
@@ -516,6 +554,15 @@ static void *ko_worker(void *arg)
             for (int k = 0; k < 9; ++k) gD[k] = j->in[15 + k] ? j->in[15 + k][i] : 0.0;
             ko_eig3_bwd(lam, D, gl, gD, j->eps, gA);
             for (int k = 0; k < 6; ++k) j->out[k][i] = gA[k];
+        } else if (j->kind == 6) {
+            double lam[2], D[4], gl[2], gD[4], gA[3];
+            for (int k = 0; k < 2; ++k) lam[k] = j->in[k][i];
+            for (int k = 0; k < 4; ++k) D[k] = j->in[2 + k][i];
+            for (int k = 0; k < 2; ++k) gl[k] = j->in[6 + k] ? j->in[6 + k][i] : 0.0;
+            for (int k = 0; k < 4; ++k) gD[k] = j->in[8 + k] ? j->in[8 + k][i] : 0.0;
+            const double gp = j->in[12] ? j->in[12][i] : 0.0;
+            ko_eig2_bwd(lam, D, gl, gD, gp, j->eps, gA);
+            for (int k = 0; k < 3; ++k) j->out[k][i] = gA[k];
         }
     }
     return NULL;
@@ -601,6 +648,24 @@ void ko_eig3_bwd_batch(int64_t n, const double *const lam[3], const double *cons
     for (int k = 0; k < 3; ++k) j.in[12 + k] = glam ? glam[k] : NULL;
     for (int k = 0; k < 9; ++k) j.in[15 + k] = gD ? gD[k] : NULL;
     for (int k = 0; k < 6; ++k) j.out[k] = gA[k];
+    j.eps = eps;
+    run_jobs(&j, n, nthreads);
+}
+
+/* eps: absolute gap regulariser; glam / gD / gphi may be NULL (zero cotangent) */
+void ko_eig2_bwd_batch(int64_t n, const double *const lam[2], const double *const D[4],
+                       const double *const glam[2], const double *const gD[4], const double *gphi,
+                       double *const gA[3], double eps, int nthreads)
+{
+    ko_job j;
+    memset(&j, 0, sizeof j);
+    j.kind = 6;
+    for (int k = 0; k < 2; ++k) j.in[k] = lam[k];
+    for (int k = 0; k < 4; ++k) j.in[2 + k] = D[k];
+    for (int k = 0; k < 2; ++k) j.in[6 + k] = glam ? glam[k] : NULL;
+    for (int k = 0; k < 4; ++k) j.in[8 + k] = gD ? gD[k] : NULL;
+    j.in[12] = gphi;
+    for (int k = 0; k < 3; ++k) j.out[k] = gA[k];
     j.eps = eps;
     run_jobs(&j, n, nthreads);
 }

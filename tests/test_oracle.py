@@ -387,3 +387,73 @@ def test_adjoint_regulariser_limit():
     c = oracle.eig3_bwd(o["lam"], o["D"], None, d["G"], 1e12)
     assert np.abs(a - b).max() < 1e-9 * np.abs(a).max()
     assert np.abs(c).max() < 1e-10
+
+
+def test_eig2_adjoint_against_central_differences():
+    """2x2 adjoint of L = sum w*lam + sum G*D + g*phi (oracle) against central
+    differences of the oracle's 2x2 forward (§3, pinned above), on matrices
+    with well-separated eigenvalues and angles away from the ends of their
+    range (where phi and D jump)."""
+    rng = np.random.default_rng(41)
+    n = 600
+    P = rng.uniform(-1, 1, (3, n))
+    f0 = oracle.eig2(P)
+    lam, D, phi = f0["lam"], f0["D"], f0["phi"]
+    w = rng.standard_normal((2, n))
+    G = rng.standard_normal((4, n))
+    g = rng.standard_normal(n)
+    gA = oracle.eig2_bwd(lam, D, w, G, g, eps=0.0)
+    h = 1e-6
+
+    def loss(Pp):
+        f = oracle.eig2(Pp)
+        return (w * f["lam"]).sum(0) + (G * f["D"]).sum(0) + g * f["phi"]
+
+    fd = np.empty_like(gA)
+    for k in range(3):
+        Pp = P.copy(); Pp[k] += h
+        Pm = P.copy(); Pm[k] -= h
+        fd[k] = (loss(Pp) - loss(Pm)) / (2 * h)
+    # no jump of phi inside the stencil, eigenvalues apart
+    smooth = np.all(np.abs(fd) < 1e3, axis=0) & (np.abs(lam[0] - lam[1]) > 0.05)
+    assert smooth.sum() > 500
+    rel = np.linalg.norm(fd - gA, axis=0)[smooth] / np.linalg.norm(gA, axis=0)[smooth]
+    assert rel.max() < 1e-6, rel.max()
+    # each cotangent on its own (the angle term separately pins its sign and scale)
+    for cot in ((w, None, None), (None, G, None), (None, None, g)):
+        gA1 = oracle.eig2_bwd(lam, D, *cot, eps=0.0)
+
+        def loss1(Pp, cot=cot):
+            f = oracle.eig2(Pp)
+            out = np.zeros(n)
+            if cot[0] is not None:
+                out += (cot[0] * f["lam"]).sum(0)
+            if cot[1] is not None:
+                out += (cot[1] * f["D"]).sum(0)
+            if cot[2] is not None:
+                out += cot[2] * f["phi"]
+            return out
+
+        for k in range(3):
+            Pp = P.copy(); Pp[k] += h
+            Pm = P.copy(); Pm[k] -= h
+            fdk = (loss1(Pp) - loss1(Pm)) / (2 * h)
+            err = np.abs(fdk - gA1[k])[smooth]
+            assert err.max() < 1e-6 * (1 + np.abs(gA1[k][smooth]).max()), (k, err.max())
+
+
+def test_eig2_adjoint_regulariser_limit():
+    """eps -> 0 recovers the unregularised 2x2 adjoint; a large eps leaves only
+    the eigenvalue part."""
+    rng = np.random.default_rng(42)
+    P = rng.uniform(-1, 1, (3, 300))
+    o = oracle.eig2(P)
+    w = rng.standard_normal((2, 300))
+    G = rng.standard_normal((4, 300))
+    g = rng.standard_normal(300)
+    a = oracle.eig2_bwd(o["lam"], o["D"], w, G, g, eps=0.0)
+    b = oracle.eig2_bwd(o["lam"], o["D"], w, G, g, eps=1e-12)
+    c = oracle.eig2_bwd(o["lam"], o["D"], w, G, g, eps=1e12)
+    lam_only = oracle.eig2_bwd(o["lam"], o["D"], w, None, None, eps=0.0)
+    assert np.abs(a - b).max() < 1e-9 * np.abs(a).max()
+    assert np.abs(c - lam_only).max() < 1e-10

@@ -50,6 +50,10 @@ MUTANTS = [
     ("bwd transposed E", "M[i][j] = d / (d * d + eps * eps) * E[i][j];", "M[i][j] = d / (d * d + eps * eps) * E[j][i];"),
     ("bwd off-diagonal plane", "gA[4] = Abar[0][2] + Abar[2][0];", "gA[4] = Abar[0][2] + Abar[0][2];"),
     ("bwd gap sign", "double d = lam[j] - lam[i];", "double d = lam[i] - lam[j];"),
+    ("eig2 bwd angle slot", "E[1][0] += gphi;", "E[0][1] += gphi;"),
+    ("eig2 bwd off-diagonal plane", "gA[2] = Abar[0][1] + Abar[1][0];", "gA[2] = Abar[0][1];"),
+    ("eig2 bwd E transposed", "E[i][j] = D[0][i] * G[0][j] + D[1][i] * G[1][j];",
+     "E[i][j] = D[i][0] * G[0][j] + D[i][1] * G[1][j];"),
 ]
 
 
@@ -127,6 +131,28 @@ def _pins():
         fd[k] = (loss(Pp) - loss(Pm)) / (2 * h)
     if not (np.linalg.norm(fd - gA, axis=0) / np.linalg.norm(gA, axis=0)).max() < 1e-6:
         fails.append("adjoint")
+    # 2x2 adjoint (lam, D and phi cotangents) vs central differences of the 2x2 forward
+    rng2 = np.random.default_rng(504)
+    P2r = rng2.uniform(-1, 1, (3, 200))
+    f2 = oracle.eig2(P2r)
+    w2, G2, g2c = rng2.standard_normal((2, 200)), rng2.standard_normal((4, 200)), rng2.standard_normal(200)
+    gA2 = oracle.eig2_bwd(f2["lam"], f2["D"], w2, G2, g2c, eps=0.0)
+
+    def loss2(Pp):
+        f = oracle.eig2(Pp)
+        return (w2 * f["lam"]).sum(0) + (G2 * f["D"]).sum(0) + g2c * f["phi"]
+
+    fd2 = np.empty_like(gA2)
+    for k in range(3):
+        Pp, Pm = P2r.copy(), P2r.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fd2[k] = (loss2(Pp) - loss2(Pm)) / (2 * h)
+    sm = np.all(np.abs(fd2) < 1e3, axis=0) & (np.abs(f2["lam"][0] - f2["lam"][1]) > 0.05)
+    if sm.sum() < 150:
+        fails.append("adjoint2 (forward too rough)")
+    elif not (np.linalg.norm(fd2 - gA2, axis=0)[sm] / np.linalg.norm(gA2, axis=0)[sm]).max() < 1e-6:
+        fails.append("adjoint2")
     return fails
 
 
@@ -142,6 +168,7 @@ def _with_lib(path):
     lib.ko_eig2_batch.argtypes = [i64, P, P, P, P, cint]
     lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
     lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
+    lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
     lib.ko_eig3_dbg.argtypes = [P, dbl, P, P, P, P]
     lib.ko_eig3_dbg.restype = cint
     try:
