@@ -214,6 +214,26 @@ ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos,
                           const ksym_opts *opts, void *stream);
 
 /*
+ * Adjoint of ksym_eig2 (not in the paper: first-order perturbation theory of
+ * the symmetric eigenproblem, with D = R(phi) of eq. (2.5)).  From the forward
+ * outputs lam (2 planes) and D (4 planes {D11, D12, D21, D22}, as ksym_eig2
+ * writes them) and the cotangents glam (2 planes), gD (4 planes) and gphi (one
+ * plane) of a scalar loss L, it writes the plane gradients gA = {dL/dA11,
+ * dL/dA22, dL/dA12} (3 planes; A12 is one parameter, so the gradient of the
+ * symmetric matrix is summed over both off-diagonal entries):
+ *   E = D^T gD with E_21 += gphi (D^T dD = [[0, -dphi], [dphi, 0]]),
+ *   Abar = D [diag(glam) + F o E] D^T,
+ *   F_12 = -F_21 = (lam2 - lam1) / ((lam2 - lam1)^2 + eps^2), eps = eps_rel * ||lam||.
+ * A NULL cotangent array or plane counts as zero; lam, D and gA are required.
+ * phi is differentiable away from the ends of its range (where it wraps by pi
+ * and D changes sign); gphi across such a wrap is the caller's matter.
+ * Allocates nothing; asynchronous on `stream`.
+ */
+ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const lam[2],
+                               const void *const D[4], const void *const glam[2], const void *const gD[4],
+                               const void *gphi, void *const gA[3], double eps_rel, void *stream);
+
+/*
  * 3x3 adjoint (not in the paper; first-order perturbation theory of the
  * symmetric eigenproblem).  From the saved forward outputs lam (3 planes) and D
  * (9 planes) and the cotangents glam = dL/dlam (3 planes) and gD = dL/dD

@@ -86,6 +86,8 @@ _lib.ksym_eig3_aos.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P,
                                ctypes.c_size_t, ctypes.POINTER(Opts), _P]
 _lib.ksym_eig3_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                     ctypes.c_double, _P]
+_lib.ksym_eig2_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                    ctypes.c_double, _P]
 _lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
                                   ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_size_t)]
@@ -96,6 +98,7 @@ _lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINT
 _lib.ksym_plan_destroy.argtypes = [_P]
 _lib.ksym_plan_destroy.restype = None
 for _f in ("ksym_eig2", "ksym_zero_counters", "ksym_eig3", "ksym_eig3_aos", "ksym_eig3_backward",
+           "ksym_eig2_backward",
            "ksym_plan_create", "ksym_plan_run", "ksym_plan_capture", "ksym_plan_replay",
            "ksym_plan_info"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -271,6 +274,29 @@ def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None):
         out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
     _check(_lib.ksym_eig3_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gp, gl, gd,
                                    _ptr_array(_rows(out, 6)[0]), float(eps_rel), _stream(ref)))
+    return out
+
+
+def eig2_backward(lam, D, glam=None, gD=None, gphi=None, eps_rel=None, out=None):
+    """Adjoint of eig2 for the plane gradients gA (3, n) = (A11, A22, A12) from
+    the forward outputs lam (2, n), D (4, n) and the cotangents of lam, D and
+    phi (None = zero); see include/ksym.h."""
+    lp, n, ref = _rows(lam, 2)
+    dt = _dt(ref)
+    if eps_rel is None:
+        eps_rel = 1e-6 if dt == F32 else 1e-12
+    Dp = _rows(D, 4)[0]
+    gl = _ptr_array(_rows(glam, 2)[0]) if glam is not None else None
+    gd = _ptr_array(_rows(gD, 4)[0]) if gD is not None else None
+    gp = None
+    if gphi is not None:
+        if gphi.dtype != ref.dtype or not gphi.is_contiguous() or gphi.numel() != n:
+            raise ValueError("gphi must be a contiguous (n,) tensor of the planes' dtype")
+        gp = gphi.data_ptr()
+    if out is None:
+        out = torch.empty((3, n), dtype=ref.dtype, device=ref.device)
+    _check(_lib.ksym_eig2_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gl, gd, gp,
+                                   _ptr_array(_rows(out, 3)[0]), float(eps_rel), _stream(ref)))
     return out
 
 

@@ -434,6 +434,55 @@ ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos, void *
     return eig3_common(true, dtype, n, nullptr, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, opts, stream);
 }
 
+ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const lam[2],
+                               const void *const D[4], const void *const glam[2], const void *const gD[4],
+                               const void *gphi, void *const gA[3], double eps_rel, void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (!(eps_rel >= 0.0) || eps_rel > 1e30) return fail(KSYM_E_ARG, "eps_rel must be finite and >= 0");
+    if (n == 0) return KSYM_OK;
+    const size_t es = esize(dtype);
+    if (!lam || !D || !gA) return fail(KSYM_E_ARG, "lam, D and gA are required");
+    for (int c = 0; c < 2; ++c)
+        if (!lam[c] || !aligned(lam[c], es)) return fail(KSYM_E_ARG, "lam[%d] NULL or misaligned", c);
+    for (int c = 0; c < 4; ++c)
+        if (!D[c] || !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] NULL or misaligned", c);
+    for (int c = 0; c < 3; ++c)
+        if (!gA[c] || !aligned(gA[c], es)) return fail(KSYM_E_ARG, "gA[%d] NULL or misaligned", c);
+    if (glam)
+        for (int c = 0; c < 2; ++c)
+            if (glam[c] && !aligned(glam[c], es)) return fail(KSYM_E_ARG, "glam[%d] misaligned", c);
+    if (gD)
+        for (int c = 0; c < 4; ++c)
+            if (gD[c] && !aligned(gD[c], es)) return fail(KSYM_E_ARG, "gD[%d] misaligned", c);
+    if (gphi && !aligned(gphi, es)) return fail(KSYM_E_ARG, "gphi misaligned");
+    constexpr int BS = 256;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
+            const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+            Bwd2Args<T> ba;
+            memset(&ba, 0, sizeof ba);
+            for (int c = 0; c < 2; ++c) ba.p.lam[c] = (const T *)lam[c] + start;
+            for (int c = 0; c < 4; ++c) ba.p.D[c] = (const T *)D[c] + start;
+            for (int c = 0; c < 2; ++c) ba.p.glam[c] = glam && glam[c] ? (const T *)glam[c] + start : nullptr;
+            for (int c = 0; c < 4; ++c) ba.p.gD[c] = gD && gD[c] ? (const T *)gD[c] + start : nullptr;
+            ba.p.gphi = gphi ? (const T *)gphi + start : nullptr;
+            for (int c = 0; c < 3; ++c) ba.p.gA[c] = (T *)gA[c] + start;
+            ba.n = (uint32_t)len;
+            ba.eps_rel = eps_rel;
+            int grid = 0;
+            ksym_status st = grid_for(len, BS, 1024, &grid);
+            if (st != KSYM_OK) return st;
+            hipError_t e = launch(&k_eig2_bwd<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ba);
+            if (e != hipSuccess) return hip_fail(e, "launch k_eig2_bwd");
+        }
+        return KSYM_OK;
+    };
+    return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
 ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const lam[3],
                                const void *const D[9], const void *const gap[3],
                                const void *const glam[3], const void *const gD[9], void *const gA[6],

@@ -831,4 +831,25 @@ __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD
     gA[5] = G(1, 2);
 }
 
+// ------------------------------------------------------- 2x2 adjoint -------
+// The same first-order result for A = D diag(lam1, lam2) D^T with D = R(phi),
+// eq. (2.5) (planes D11, D12, D21, D22): E = D^T gD, and the angle cotangent
+// enters as E_21 += gphi, since D^T dD = [[0, -dphi], [dphi, 0]] gives
+// dphi = d2^T dA d1 / (lam1 - lam2).  M = diag(glam) + F o E with F_12 =
+// (lam2 - lam1) / ((lam2 - lam1)^2 + eps^2) = -F_21; Abar = D M D^T and
+// gA = (Abar_11, Abar_22, Abar_12 + Abar_21).  d = lam2 - lam1.
+template <typename T>
+__device__ __forceinline__ void adjoint2(const T D[4], const T gl[2], const T gD[4], T gphi, T d, T eps2,
+                                         T gA[3]) {
+    const T e12 = D[0] * gD[1] + D[2] * gD[3];
+    const T e21 = D[1] * gD[0] + D[3] * gD[2] + gphi;
+    const T f = Mth<T>::div(d, d * d + eps2);
+    const T m00 = gl[0], m01 = f * e12, m10 = -f * e21, m11 = gl[1];
+    const T t00 = D[0] * m00 + D[1] * m10, t01 = D[0] * m01 + D[1] * m11;
+    const T t10 = D[2] * m00 + D[3] * m10, t11 = D[2] * m01 + D[3] * m11;
+    gA[0] = t00 * D[0] + t01 * D[1];
+    gA[1] = t10 * D[2] + t11 * D[3];
+    gA[2] = (t00 * D[2] + t01 * D[3]) + (t10 * D[0] + t11 * D[1]);
+}
+
 }  // namespace ksym

@@ -1040,6 +1040,47 @@ __global__ __launch_bounds__(BS) void k_eig3_bwd(BwdArgs<T> a) {
     }
 }
 
+// ---------------------------------------------------- 2x2 adjoint ----------
+template <typename T> struct Bwd2Ptrs {
+    const T *lam[2];
+    const T *D[4];
+    const T *glam[2];   // absent cotangents: null planes, read as zeros
+    const T *gD[4];
+    const T *gphi;
+    T *gA[3];
+};
+
+template <typename T> struct Bwd2Args {
+    Bwd2Ptrs<T> p;
+    uint32_t n;
+    int32_t pad;
+    double eps_rel;
+};
+
+// One matrix per lane, grid-stride; the planes are streams.  eps = eps_rel *
+// ||lam||; the gap lam2 - lam1 is taken in float64 (exact for float32).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_eig2_bwd(Bwd2Args<T> a) {
+    const uint32_t n = a.n;
+    for (uint32_t i = blockIdx.x * BS + threadIdx.x; i - threadIdx.x < n; i += gridDim.x * BS) {
+        T L[2], D[4], gl[2], gD[4], gA[3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) L[c] = ld_plane<T, kStream>(a.p.lam[c], n, i);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) D[c] = ld_plane<T, kStream>(a.p.D[c], n, i);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) gl[c] = ld_plane<T, kStream>(a.p.glam[c], n, i);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gD[c] = ld_plane<T, kStream>(a.p.gD[c], n, i);
+        const T gphi = ld_plane<T, kStream>(a.p.gphi, n, i);
+        const T d = (T)((double)L[1] - (double)L[0]);
+        const T eps = (T)a.eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1]);
+        adjoint2<T>(D, gl, gD, gphi, d, eps * eps, gA);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st_plane<T, kStream>(a.p.gA[c], n, i, gA[c]);
+    }
+}
+
 // ------------------------------------------------ mixed persistent batch ---
 template <typename T> struct GroupDesc {
     int64_t n;        // at most KSYM_CHUNK (the host splits larger groups)

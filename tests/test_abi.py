@@ -162,6 +162,25 @@ def test_backward_argument_errors(lib):
     assert f(5, 4, L, D, None, None, None, gA, 1e-6, None) == 2
 
 
+def test_eig2_backward_argument_errors(lib):
+    P = ctypes.c_void_p
+    f = lib.ksym_eig2_backward
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, P]
+    f.restype = ctypes.c_int
+    L, D, gA = _planes(2), _planes(4), _planes(3)
+    assert f(0, -1, L, D, None, None, None, gA, 1e-6, None) == 1
+    assert f(0, 4, None, D, None, None, None, gA, 1e-6, None) == 1
+    assert f(0, 4, L, None, None, None, None, gA, 1e-6, None) == 1
+    assert f(0, 4, L, D, None, None, None, None, 1e-6, None) == 1
+    assert f(0, 4, L, D, None, None, None, gA, -1.0, None) == 1
+    assert f(0, 4, L, D, None, None, None, gA, float("nan"), None) == 1
+    assert f(0, 0, None, None, None, None, None, None, 1e-6, None) == 0
+    misaligned = (ctypes.c_void_p * 2)(0x1000, 0x1002)
+    assert f(0, 4, L, D, misaligned, None, None, gA, 1e-6, None) == 1
+    assert f(0, 4, L, D, None, None, ctypes.c_void_p(0x1001), gA, 1e-6, None) == 1
+    assert f(5, 4, L, D, None, None, None, gA, 1e-6, None) == 2
+
+
 def test_plan_argument_errors(lib):
     P = ctypes.c_void_p
     f = lib.ksym_plan_create

@@ -106,6 +106,45 @@ def test_eig2_power_of_two_scaling_extremes(ksym, dtype, k):
     assert np.array_equal(gA["lam"], np.ldexp(gB["lam"], k).astype(np_dt))
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_eig2_backward_matches_oracle_adjoint(ksym, dtype):
+    """The 2x2 adjoint kernel (cotangents of lam, D and phi) against the
+    oracle's adjoint on the same forward outputs: unregularised over a ragged
+    batch, with the regulariser eps = eps_rel ||lam|| on a sample (one oracle
+    call per matrix), and with absent cotangents counting as zero."""
+    rng = np.random.default_rng(61)
+    n = 5000 + 37
+    P = rng.uniform(-1, 1, (3, n))
+    tdt = getattr(torch, dtype)
+    f = ksym.eig2(to_dev(P, tdt))
+    lam, D = f["lam"], f["D"]
+    L = lam.double().cpu().numpy()
+    Dn = D.double().cpu().numpy()
+    w, G, g = rng.standard_normal((2, n)), rng.standard_normal((4, n)), rng.standard_normal(n)
+    wt, Gt, gt = to_dev(w, tdt), to_dev(G, tdt), to_dev(g, tdt)
+    w64, G64, g64 = (x.double().cpu().numpy() for x in (wt, Gt, gt))
+    tol = 1e-4 if dtype == "float32" else 1e-10
+
+    def rel(a, b):
+        return (np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)).max()
+
+    gA = ksym.eig2_backward(lam, D, wt, Gt, gt, eps_rel=0.0).cpu().numpy().astype(np.float64)
+    ref = oracle.eig2_bwd(L, Dn, w64, G64, g64, eps=0.0)
+    assert rel(gA, ref) < tol, rel(gA, ref)
+    # angle cotangent alone; lam and D cotangents absent
+    gA = ksym.eig2_backward(lam, D, gphi=gt, eps_rel=0.0).cpu().numpy().astype(np.float64)
+    ref = oracle.eig2_bwd(L, Dn, None, None, g64, eps=0.0)
+    assert rel(gA, ref) < tol, rel(gA, ref)
+    # regulariser: eps = eps_rel * ||lam|| per matrix
+    eps_rel = 0.3
+    gA = ksym.eig2_backward(lam, D, wt, Gt, gt, eps_rel=eps_rel).cpu().numpy().astype(np.float64)
+    idx = np.arange(0, n, 97)
+    eps = eps_rel * np.sqrt((L ** 2).sum(0))
+    ref = np.stack([oracle.eig2_bwd(L[:, i:i + 1], Dn[:, i:i + 1], w64[:, i:i + 1], G64[:, i:i + 1],
+                                    g64[i:i + 1], eps=eps[i], threads=1)[:, 0] for i in idx], 1)
+    assert rel(gA[:, idx], ref) < tol, rel(gA[:, idx], ref)
+
+
 # ------------------------------------------------------------- adjoint -----
 def test_backward_f64_matches_oracle_adjoint(ksym):
     """The adjoint kernel computes the same float64 formula as the oracle's
