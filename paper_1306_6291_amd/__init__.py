@@ -329,6 +329,30 @@ def eig3_autograd(planes, eps_rel=None, opts=None):
     return Eig3Function.apply(planes, eps_rel, opts)
 
 
+class Eig2Function(torch.autograd.Function):
+    """lam, D, phi = Eig2Function.apply(planes, eps_rel): differentiable in lam,
+    D and phi through the 2x2 adjoint kernel.  planes is a (3, n) tensor."""
+
+    @staticmethod
+    def forward(ctx, planes, eps_rel=None, opts=None):
+        out = eig2(planes.contiguous(), opts=opts)
+        ctx.save_for_backward(out["lam"], out["D"])
+        ctx.eps_rel = eps_rel
+        return out["lam"], out["D"], out["phi"]
+
+    @staticmethod
+    def backward(ctx, glam, gD, gphi):
+        lam, D = ctx.saved_tensors
+        gA = eig2_backward(lam, D, glam.contiguous() if glam is not None else None,
+                           gD.contiguous() if gD is not None else None,
+                           gphi.contiguous() if gphi is not None else None, eps_rel=ctx.eps_rel)
+        return gA, None, None
+
+
+def eig2_autograd(planes, eps_rel=None, opts=None):
+    return Eig2Function.apply(planes, eps_rel, opts)
+
+
 # ------------------------------------------------------- mixed plans --------
 class Plan:
     """Mixed persistent batch of 2x2 and 3x3 groups (one kernel launch).

@@ -256,6 +256,38 @@ def test_autograd_function(ksym):
     assert rel.max() < 1e-6, rel.max()
 
 
+def test_eig2_autograd_function(ksym):
+    """Eig2Function: torch.autograd through the 2x2 adjoint kernel, float64,
+    for a loss in lam, D and phi, against central differences of the GPU
+    forward itself (matrices whose angle stays inside its range)."""
+    rng = np.random.default_rng(207)
+    n = 512
+    P0 = rng.uniform(-1, 1, (3, n))
+    P = to_dev(P0, torch.float64).requires_grad_(True)
+    w, G, g = (to_dev(rng.standard_normal(s), torch.float64) for s in ((2, n), (4, n), (n,)))
+    lam, D, phi = ksym.eig2_autograd(P, eps_rel=0.0)
+    ((w * lam).sum() + (G * D).sum() + (g * phi).sum()).backward()
+    grad = P.grad.cpu().numpy()
+    base = P.detach()
+
+    def L(Pp):
+        l2, D2, p2 = ksym.eig2_autograd(Pp, eps_rel=0.0)
+        return ((w * l2).sum(0) + (G * D2).sum(0) + g * p2).cpu().numpy()
+
+    h = 1e-6
+    fd = np.empty_like(grad)
+    for k in range(3):
+        Pp, Pm = base.clone(), base.clone()
+        Pp[k] += h
+        Pm[k] -= h
+        fd[k] = (L(Pp) - L(Pm)) / (2 * h)
+    lam0 = lam.detach().cpu().numpy()
+    smooth = np.all(np.abs(fd) < 1e3, axis=0) & (np.abs(lam0[0] - lam0[1]) > 0.05)
+    assert smooth.sum() > 400
+    rel = np.linalg.norm(fd - grad, axis=0)[smooth] / np.linalg.norm(grad, axis=0)[smooth]
+    assert rel.max() < 1e-6, rel.max()
+
+
 # ------------------------------------------------------------ mixed plan ---
 def _mixed_case(ksym, total=200000, ngroups=64, seed=206):
     sizes, kinds = synth.mixed_group_sizes(total, ngroups, lo=100, hi=1e4, seed=seed)
