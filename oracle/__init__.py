@@ -49,6 +49,8 @@ def _load():
         _lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
         _lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
         _lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
+        _lib.ko_compose3_batch.argtypes = [i64, P, P, P, cint]
+        _lib.ko_compose2_batch.argtypes = [i64, P, P, P, cint]
         _lib.ko_eig3_dbg.argtypes = [P, dbl, P, P, P, P]
         _lib.ko_eig3_dbg.restype = cint
     return _lib
@@ -155,6 +157,31 @@ def eig2_bwd(lam, D, glam=None, gD=None, gphi=None, eps=0.0, threads=None):
         gp.ctypes.data if gp is not None else None,
         ctypes.cast(_ptrs(list(gA)), ctypes.c_void_p), float(eps), threads or default_threads())
     return gA
+
+
+def compose3(lam, phi, threads=None):
+    """Inverse map, eq. (2.6): planes A (6, n) = D diag(lam) D^T with
+    D = R1(phi1) R2(phi2) R3(phi3), from lam (3, n) and phi (3, n)."""
+    lib = _load()
+    L = _planes(lam, 3); F = _planes(phi, 3)
+    n = L[0].size
+    A = np.empty((6, n))
+    lib.ko_compose3_batch(n, ctypes.cast(_ptrs(L), ctypes.c_void_p), ctypes.cast(_ptrs(F), ctypes.c_void_p),
+                          ctypes.cast(_ptrs(list(A)), ctypes.c_void_p), threads or default_threads())
+    return A
+
+
+def compose2(lam, phi, threads=None):
+    """Inverse map, eq. (2.5): planes A (3, n) = (A11, A22, A12) of
+    R(phi) diag(lam) R(phi)^T, from lam (2, n) and phi (n,)."""
+    lib = _load()
+    L = _planes(lam, 2)
+    n = L[0].size
+    f = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+    A = np.empty((3, n))
+    lib.ko_compose2_batch(n, ctypes.cast(_ptrs(L), ctypes.c_void_p), f.ctypes.data,
+                          ctypes.cast(_ptrs(list(A)), ctypes.c_void_p), threads or default_threads())
+    return A
 
 
 class Debug3(ctypes.Structure):

@@ -506,10 +506,45 @@ void ko_eig2_bwd(const double lam[2], const double D4[4], const double glam[2], 
 }
 
 /* ------------------------------------------------------------------------ */
+/* The inverse map, from the definitions: A = D diag(lam) D^T with          */
+/* D = R1(phi1) R2(phi2) R3(phi3) (eq. (2.6)) for 3x3, D = R(phi) (eq. (2.5)) */
+/* for 2x2.  Planes A = (A11, A22, A33, A12, A13, A23) and (A11, A22, A12).  */
+/* ------------------------------------------------------------------------ */
+void ko_compose3(const double lam[3], const double phi[3], double A[6])
+{
+    double D[3][3], M[3][3];
+    euler_to_D(phi[0], phi[1], phi[2], D);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += D[i][k] * lam[k] * D[j][k];
+            M[i][j] = s;
+        }
+    A[0] = M[0][0];
+    A[1] = M[1][1];
+    A[2] = M[2][2];
+    A[3] = M[0][1];
+    A[4] = M[0][2];
+    A[5] = M[1][2];
+}
+
+void ko_compose2(const double lam[2], double phi, double A[3])
+{
+    const double c = cos(phi), s = sin(phi);
+    const double D[2][2] = {{c, -s}, {s, c}};
+    double M[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) M[i][j] = D[i][0] * lam[0] * D[j][0] + D[i][1] * lam[1] * D[j][1];
+    A[0] = M[0][0];
+    A[1] = M[1][1];
+    A[2] = M[0][1];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batch drivers over structure-of-arrays planes, split over host threads.  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int kind;                     /* 3: eig3, 2: eig2, 4: jacobi, 5: bwd, 6: 2x2 bwd */
+    int kind;                     /* 3: eig3, 2: eig2, 4: jacobi, 5: bwd, 6: 2x2 bwd, 7/8: compose 3x3/2x2 */
     int64_t lo, hi;
     const double *in[24];
     double *out[16];
@@ -563,6 +598,17 @@ static void *ko_worker(void *arg)
             const double gp = j->in[12] ? j->in[12][i] : 0.0;
             ko_eig2_bwd(lam, D, gl, gD, gp, j->eps, gA);
             for (int k = 0; k < 3; ++k) j->out[k][i] = gA[k];
+        } else if (j->kind == 7) {
+            double lam[3], phi[3], A[6];
+            for (int k = 0; k < 3; ++k) lam[k] = j->in[k][i];
+            for (int k = 0; k < 3; ++k) phi[k] = j->in[3 + k][i];
+            ko_compose3(lam, phi, A);
+            for (int k = 0; k < 6; ++k) j->out[k][i] = A[k];
+        } else if (j->kind == 8) {
+            double lam[2], A[3];
+            for (int k = 0; k < 2; ++k) lam[k] = j->in[k][i];
+            ko_compose2(lam, j->in[2][i], A);
+            for (int k = 0; k < 3; ++k) j->out[k][i] = A[k];
         }
     }
     return NULL;
@@ -667,5 +713,29 @@ void ko_eig2_bwd_batch(int64_t n, const double *const lam[2], const double *cons
     j.in[12] = gphi;
     for (int k = 0; k < 3; ++k) j.out[k] = gA[k];
     j.eps = eps;
+    run_jobs(&j, n, nthreads);
+}
+
+void ko_compose3_batch(int64_t n, const double *const lam[3], const double *const phi[3],
+                       double *const A[6], int nthreads)
+{
+    ko_job j;
+    memset(&j, 0, sizeof j);
+    j.kind = 7;
+    for (int k = 0; k < 3; ++k) j.in[k] = lam[k];
+    for (int k = 0; k < 3; ++k) j.in[3 + k] = phi[k];
+    for (int k = 0; k < 6; ++k) j.out[k] = A[k];
+    run_jobs(&j, n, nthreads);
+}
+
+void ko_compose2_batch(int64_t n, const double *const lam[2], const double *phi, double *const A[3],
+                       int nthreads)
+{
+    ko_job j;
+    memset(&j, 0, sizeof j);
+    j.kind = 8;
+    for (int k = 0; k < 2; ++k) j.in[k] = lam[k];
+    j.in[2] = phi;
+    for (int k = 0; k < 3; ++k) j.out[k] = A[k];
     run_jobs(&j, n, nthreads);
 }

@@ -457,3 +457,38 @@ def test_eig2_adjoint_regulariser_limit():
     lam_only = oracle.eig2_bwd(o["lam"], o["D"], w, None, None, eps=0.0)
     assert np.abs(a - b).max() < 1e-9 * np.abs(a).max()
     assert np.abs(c - lam_only).max() < 1e-10
+
+
+def test_compose_round_trips_and_closed_forms():
+    """The inverse map (eqs. (2.5)-(2.6)): composing the forward's own outputs
+    gives back the input (3x3 and 2x2, random and Haar spectra); zero angles
+    give diag(lam); a quarter turn of the third angle swaps the first two
+    axes; trace and Frobenius norm are those of diag(lam)."""
+    # the round trip is as good as the forward's own residual (the closed form
+    # loses accuracy near coincident eigenvalues); mostly at rounding level
+    for P in (synth.make_plain(3000, 16, seed=51)["planes3"],
+              synth.make_precision(3000, seed=52).astype(np.float64)):
+        o = oracle.eig3(P)
+        A = oracle.compose3(o["lam"], o["phi"])
+        res = H.residual3(P, o["lam"], o["D"])
+        err = np.abs(A - P).max(0) / H.fro3(P)
+        assert np.all(err <= 4 * res + 1e-13), (err - 4 * res).max()
+        assert np.median(err) < 1e-15
+    rng = np.random.default_rng(53)
+    lam = rng.uniform(-1, 1, (3, 500))
+    A0 = oracle.compose3(lam, np.zeros((3, 500)))
+    assert np.array_equal(A0[:3], lam) and np.all(A0[3:] == 0)
+    Aq = oracle.compose3(lam, np.stack([np.zeros(500), np.zeros(500), np.full(500, np.pi / 2)]))
+    assert np.abs(Aq[:3] - lam[[1, 0, 2]]).max() < 1e-15 and np.abs(Aq[3:]).max() < 1e-15
+    phi = np.stack([rng.uniform(-np.pi, np.pi, 500), rng.uniform(-np.pi / 2, np.pi / 2, 500),
+                    rng.uniform(-np.pi / 2, np.pi / 2, 500)])
+    Ar = oracle.compose3(lam, phi)
+    assert np.abs(Ar[:3].sum(0) - lam.sum(0)).max() < 1e-14
+    fro2 = (Ar[:3] ** 2).sum(0) + 2 * (Ar[3:] ** 2).sum(0)
+    assert np.abs(fro2 - (lam ** 2).sum(0)).max() < 1e-14
+    P2 = rng.uniform(-1, 1, (3, 2000))
+    o2 = oracle.eig2(P2)
+    A2 = oracle.compose2(o2["lam"], o2["phi"])
+    assert np.abs(A2 - P2).max() < 1e-14
+    A20 = oracle.compose2(lam[:2], np.zeros(500))
+    assert np.array_equal(A20[:2], lam[:2]) and np.all(A20[2] == 0)

@@ -54,6 +54,9 @@ MUTANTS = [
     ("eig2 bwd off-diagonal plane", "gA[2] = Abar[0][1] + Abar[1][0];", "gA[2] = Abar[0][1];"),
     ("eig2 bwd E transposed", "E[i][j] = D[0][i] * G[0][j] + D[1][i] * G[1][j];",
      "E[i][j] = D[i][0] * G[0][j] + D[i][1] * G[1][j];"),
+    ("compose3 transposed", "s += D[i][k] * lam[k] * D[j][k];", "s += D[k][i] * lam[k] * D[k][j];"),
+    ("compose2 angle sign", "const double D[2][2] = {{c, -s}, {s, c}};", "const double D[2][2] = {{c, s}, {-s, c}};"),
+    ("compose3 plane order", "A[4] = M[0][2];\n    A[5] = M[1][2];", "A[4] = M[1][2];\n    A[5] = M[0][2];"),
 ]
 
 
@@ -153,6 +156,15 @@ def _pins():
         fails.append("adjoint2 (forward too rough)")
     elif not (np.linalg.norm(fd2 - gA2, axis=0)[sm] / np.linalg.norm(gA2, axis=0)[sm]).max() < 1e-6:
         fails.append("adjoint2")
+    # inverse maps: round trips through the forward
+    Pc = synth.make_plain(300, 16, seed=505)["planes3"]
+    oc = oracle.eig3(Pc)
+    err = np.abs(oracle.compose3(oc["lam"], oc["phi"]) - Pc).max(0) / H.fro3(Pc)
+    if not np.all(err <= 4 * H.residual3(Pc, oc["lam"], oc["D"]) + 1e-13):
+        fails.append("compose3")
+    o2c = oracle.eig2(P2r)
+    if not np.abs(oracle.compose2(o2c["lam"], o2c["phi"]) - P2r).max() < 1e-14:
+        fails.append("compose2")
     return fails
 
 
@@ -169,6 +181,8 @@ def _with_lib(path):
     lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
     lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
     lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
+    lib.ko_compose3_batch.argtypes = [i64, P, P, P, cint]
+    lib.ko_compose2_batch.argtypes = [i64, P, P, P, cint]
     lib.ko_eig3_dbg.argtypes = [P, dbl, P, P, P, P]
     lib.ko_eig3_dbg.restype = cint
     try:
