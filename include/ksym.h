@@ -214,6 +214,21 @@ ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos,
                           const ksym_opts *opts, void *stream);
 
 /*
+ * Inverse maps, from the definitions (2.5)-(2.6) (the other side of the
+ * forward, not a step of the paper's method): A = D diag(lam) D^T with
+ * D = R1(phi1) R2(phi2) R3(phi3) for 3x3, D = R(phi) for 2x2.  lam and phi are
+ * laid out as ksym_eig3 / ksym_eig2 write them (any slot order of lam, as
+ * long as phi describes the matching D); A receives the unique-entry planes
+ * {A11, A22, A33, A12, A13, A23} or {A11, A22, A12}, the forward's input
+ * layout.  For on-device generation and round trips.  All planes required.
+ * Allocates nothing; asynchronous on `stream`.
+ */
+ksym_status ksym_compose3(ksym_dtype dtype, int64_t n, const void *const lam[3], const void *const phi[3],
+                          void *const A[6], void *stream);
+ksym_status ksym_compose2(ksym_dtype dtype, int64_t n, const void *const lam[2], const void *phi,
+                          void *const A[3], void *stream);
+
+/*
  * Adjoint of ksym_eig2 (not in the paper: first-order perturbation theory of
  * the symmetric eigenproblem, with D = R(phi) of eq. (2.5)).  From the forward
  * outputs lam (2 planes) and D (4 planes {D11, D12, D21, D22}, as ksym_eig2

@@ -88,6 +88,8 @@ _lib.ksym_eig3_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P
                                     ctypes.c_double, _P]
 _lib.ksym_eig2_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                     ctypes.c_double, _P]
+_lib.ksym_compose3.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P]
+_lib.ksym_compose2.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P]
 _lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
                                   ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_size_t)]
@@ -98,7 +100,7 @@ _lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINT
 _lib.ksym_plan_destroy.argtypes = [_P]
 _lib.ksym_plan_destroy.restype = None
 for _f in ("ksym_eig2", "ksym_zero_counters", "ksym_eig3", "ksym_eig3_aos", "ksym_eig3_backward",
-           "ksym_eig2_backward",
+           "ksym_eig2_backward", "ksym_compose3", "ksym_compose2",
            "ksym_plan_create", "ksym_plan_run", "ksym_plan_capture", "ksym_plan_replay",
            "ksym_plan_info"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -297,6 +299,31 @@ def eig2_backward(lam, D, glam=None, gD=None, gphi=None, eps_rel=None, out=None)
         out = torch.empty((3, n), dtype=ref.dtype, device=ref.device)
     _check(_lib.ksym_eig2_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gl, gd, gp,
                                    _ptr_array(_rows(out, 3)[0]), float(eps_rel), _stream(ref)))
+    return out
+
+
+def compose3(lam, phi, out=None):
+    """Inverse map, eq. (2.6): the planes (6, n) of A = D diag(lam) D^T with
+    D = R1(phi1) R2(phi2) R3(phi3), from lam (3, n) and phi (3, n)."""
+    lp, n, ref = _rows(lam, 3)
+    fp = _rows(phi, 3)[0]
+    if out is None:
+        out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
+    _check(_lib.ksym_compose3(_dt(ref), n, _ptr_array(lp), _ptr_array(fp), _ptr_array(_rows(out, 6)[0]),
+                              _stream(ref)))
+    return out
+
+
+def compose2(lam, phi, out=None):
+    """Inverse map, eq. (2.5): the planes (3, n) = (A11, A22, A12) of
+    R(phi) diag(lam) R(phi)^T, from lam (2, n) and phi (n,)."""
+    lp, n, ref = _rows(lam, 2)
+    if phi.dtype != ref.dtype or not phi.is_contiguous() or phi.numel() != n:
+        raise ValueError("phi must be a contiguous (n,) tensor of lam's dtype")
+    if out is None:
+        out = torch.empty((3, n), dtype=ref.dtype, device=ref.device)
+    _check(_lib.ksym_compose2(_dt(ref), n, _ptr_array(lp), phi.data_ptr(), _ptr_array(_rows(out, 3)[0]),
+                              _stream(ref)))
     return out
 
 

@@ -434,6 +434,55 @@ ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos, void *
     return eig3_common(true, dtype, n, nullptr, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, opts, stream);
 }
 
+static ksym_status compose_impl(int k, ksym_dtype dtype, int64_t n, const void *const lam[], const void *const phi[],
+                                void *const A[], void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (n == 0) return KSYM_OK;
+    const size_t es = esize(dtype);
+    const int nl = k, nf = k == 3 ? 3 : 1, na = k == 3 ? 6 : 3;
+    if (!lam || !phi || !A) return fail(KSYM_E_ARG, "lam, phi and A are required");
+    for (int c = 0; c < nl; ++c)
+        if (!lam[c] || !aligned(lam[c], es)) return fail(KSYM_E_ARG, "lam[%d] NULL or misaligned", c);
+    for (int c = 0; c < nf; ++c)
+        if (!phi[c] || !aligned(phi[c], es)) return fail(KSYM_E_ARG, "phi[%d] NULL or misaligned", c);
+    for (int c = 0; c < na; ++c)
+        if (!A[c] || !aligned(A[c], es)) return fail(KSYM_E_ARG, "A[%d] NULL or misaligned", c);
+    constexpr int BS = 256;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        for (int64_t start = 0; start < n; start += KSYM_CHUNK) {
+            const int64_t len = n - start < KSYM_CHUNK ? n - start : KSYM_CHUNK;
+            ComposeArgs<T> ca;
+            memset(&ca, 0, sizeof ca);
+            for (int c = 0; c < nl; ++c) ca.p.lam[c] = (const T *)lam[c] + start;
+            for (int c = 0; c < nf; ++c) ca.p.phi[c] = (const T *)phi[c] + start;
+            for (int c = 0; c < na; ++c) ca.p.A[c] = (T *)A[c] + start;
+            ca.n = (uint32_t)len;
+            int grid = 0;
+            ksym_status st = grid_for(len, BS, 1024, &grid);
+            if (st != KSYM_OK) return st;
+            hipError_t e = k == 3 ? launch(&k_compose3<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ca)
+                                  : launch(&k_compose2<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ca);
+            if (e != hipSuccess) return hip_fail(e, "launch k_compose");
+        }
+        return KSYM_OK;
+    };
+    return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+ksym_status ksym_compose3(ksym_dtype dtype, int64_t n, const void *const lam[3], const void *const phi[3],
+                          void *const A[6], void *stream) {
+    return compose_impl(3, dtype, n, lam, phi, A, stream);
+}
+
+ksym_status ksym_compose2(ksym_dtype dtype, int64_t n, const void *const lam[2], const void *phi,
+                          void *const A[3], void *stream) {
+    const void *const phis[1] = {phi};
+    return compose_impl(2, dtype, n, lam, phi ? phis : nullptr, A, stream);
+}
+
 ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const lam[2],
                                const void *const D[4], const void *const glam[2], const void *const gD[4],
                                const void *gphi, void *const gA[3], double eps_rel, void *stream) {

@@ -1081,6 +1081,62 @@ __global__ __launch_bounds__(BS) void k_eig2_bwd(Bwd2Args<T> a) {
     }
 }
 
+// ----------------------------------------------------- inverse maps -------
+// A = D diag(lam) D^T from the angles: D = R1(phi1) R2(phi2) R3(phi3), eq.
+// (2.6) (build_D, as the forward), or D = R(phi), eq. (2.5).  Planes as the
+// forward reads them; one matrix per lane, grid-stride, streamed.
+template <typename T> struct ComposePtrs {
+    const T *lam[3];
+    const T *phi[3];
+    T *A[6];
+};
+template <typename T> struct ComposeArgs {
+    ComposePtrs<T> p;
+    uint32_t n;
+    int32_t pad;
+};
+
+__device__ __forceinline__ void sincos_t(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ __forceinline__ void sincos_t(double x, double &s, double &c) { sincos(x, &s, &c); }
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_compose3(ComposeArgs<T> a) {
+    const uint32_t n = a.n;
+    for (uint32_t i = blockIdx.x * BS + threadIdx.x; i - threadIdx.x < n; i += gridDim.x * BS) {
+        T L[3], F[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L[c] = ld_plane<T, kStream>(a.p.lam[c], n, i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[c] = ld_plane<T, kStream>(a.p.phi[c], n, i);
+        Rot<T> R;
+        sincos_t(F[0], R.s1, R.c1);
+        sincos_t(F[1], R.s2, R.c2);
+        sincos_t(F[2], R.s3, R.c3);
+        T D[9];
+        build_D(R, D);
+        // A_ij = sum_k D_ik lam_k D_jk over the unique entries (11, 22, 33, 12, 13, 23)
+        constexpr int I[6] = {0, 1, 2, 0, 0, 1}, J[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const T *r = D + 3 * I[e], *q = D + 3 * J[e];
+            st_plane<T, kStream>(a.p.A[e], n, i, r[0] * L[0] * q[0] + r[1] * L[1] * q[1] + r[2] * L[2] * q[2]);
+        }
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_compose2(ComposeArgs<T> a) {
+    const uint32_t n = a.n;
+    for (uint32_t i = blockIdx.x * BS + threadIdx.x; i - threadIdx.x < n; i += gridDim.x * BS) {
+        const T l1 = ld_plane<T, kStream>(a.p.lam[0], n, i), l2 = ld_plane<T, kStream>(a.p.lam[1], n, i);
+        T s, c;
+        sincos_t(ld_plane<T, kStream>(a.p.phi[0], n, i), s, c);
+        st_plane<T, kStream>(a.p.A[0], n, i, c * c * l1 + s * s * l2);
+        st_plane<T, kStream>(a.p.A[1], n, i, s * s * l1 + c * c * l2);
+        st_plane<T, kStream>(a.p.A[2], n, i, c * s * (l1 - l2));
+    }
+}
+
 // ------------------------------------------------ mixed persistent batch ---
 template <typename T> struct GroupDesc {
     int64_t n;        // at most KSYM_CHUNK (the host splits larger groups)

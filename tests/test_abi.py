@@ -181,6 +181,26 @@ def test_eig2_backward_argument_errors(lib):
     assert f(5, 4, L, D, None, None, None, gA, 1e-6, None) == 2
 
 
+def test_compose_argument_errors(lib):
+    P = ctypes.c_void_p
+    f3, f2 = lib.ksym_compose3, lib.ksym_compose2
+    for f in (f3, f2):
+        f.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P]
+        f.restype = ctypes.c_int
+    L3, F3, A6 = _planes(3), _planes(3), _planes(6)
+    assert f3(0, -1, L3, F3, A6, None) == 1
+    assert f3(0, 4, None, F3, A6, None) == 1
+    assert f3(0, 4, L3, None, A6, None) == 1
+    assert f3(0, 4, L3, F3, None, None) == 1
+    assert f3(0, 4, L3, _planes(3, misalign=True), A6, None) == 1
+    assert f3(0, 0, None, None, None, None) == 0
+    assert f3(7, 4, L3, F3, A6, None) == 2
+    L2, A3 = _planes(2), _planes(3)
+    assert f2(0, 4, L2, None, A3, None) == 1
+    assert f2(0, 4, L2, ctypes.c_void_p(0x10001), A3, None) == 1
+    assert f2(0, 4, None, ctypes.c_void_p(0x10000), A3, None) == 1
+
+
 def test_plan_argument_errors(lib):
     P = ctypes.c_void_p
     f = lib.ksym_plan_create

@@ -145,6 +145,50 @@ def test_eig2_backward_matches_oracle_adjoint(ksym, dtype):
     assert rel(gA[:, idx], ref) < tol, rel(gA[:, idx], ref)
 
 
+# -------------------------------------------------------- inverse maps -----
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_compose_matches_oracle(ksym, dtype):
+    """The inverse maps (eqs. (2.5)-(2.6)) against the oracle's on the same
+    eigenvalues and angles, ragged sizes."""
+    rng = np.random.default_rng(71)
+    tdt = getattr(torch, dtype)
+    tol = 1e-14 if dtype == "float64" else 2e-6
+    for n in (1, 1000 + 3):
+        lam = rng.uniform(-1, 1, (3, n))
+        phi = np.stack([rng.uniform(-np.pi, np.pi, n), rng.uniform(-np.pi / 2, np.pi / 2, n),
+                        rng.uniform(-np.pi / 2, np.pi / 2, n)])
+        lt, ft = to_dev(lam, tdt), to_dev(phi, tdt)
+        A = ksym.compose3(lt, ft).cpu().numpy().astype(np.float64)
+        ref = oracle.compose3(lt.double().cpu().numpy(), ft.double().cpu().numpy())
+        assert np.abs(A - ref).max() < tol * 3, np.abs(A - ref).max()
+        A2 = ksym.compose2(lt[:2].contiguous(), ft[0].contiguous()).cpu().numpy().astype(np.float64)
+        ref2 = oracle.compose2(lt[:2].double().cpu().numpy(), ft[0].double().cpu().numpy())
+        assert np.abs(A2 - ref2).max() < tol * 2, np.abs(A2 - ref2).max()
+
+
+def test_compose_round_trip_full_scale(ksym):
+    """2^22 float32 matrices generated on the device from eigenvalues and
+    angles, decomposed again: the eigenvalues come back within the float32
+    tolerance and the outputs compose to the generated matrices within the
+    residual tolerance."""
+    n = 1 << 22
+    g = torch.Generator(device="cuda").manual_seed(72)
+    lam = torch.rand((3, n), device="cuda", generator=g, dtype=torch.float32) * 2 - 1
+    u = torch.rand((3, n), device="cuda", generator=g, dtype=torch.float32)
+    phi = torch.stack([(u[0] * 2 - 1) * math.pi, (u[1] - 0.5) * math.pi, (u[2] - 0.5) * math.pi]).contiguous()
+    A = ksym.compose3(lam, phi)
+    out = ksym.eig3(A, opts=ksym.Opts.defaults(ksym.F32), outputs=("lam", "D", "phi", "flags"))
+    A64 = A.double()
+    fro = torch.sqrt((A64[:3] ** 2).sum(0) + 2 * (A64[3:] ** 2).sum(0))
+    ls, _ = torch.sort(out["lam"].double(), dim=0)
+    l0, _ = torch.sort(lam.double(), dim=0)
+    # the float32 A is the input: its eigenvalues differ from lam by its rounding
+    assert float(((ls - l0).abs().amax(0) / fro).max()) < 2e-6
+    back = ksym.compose3(out["lam"], out["phi"]).double()
+    assert float(((back - A64).abs().amax(0) / fro).max()) < 1e-5
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------- adjoint -----
 def test_backward_f64_matches_oracle_adjoint(ksym):
     """The adjoint kernel computes the same float64 formula as the oracle's
