@@ -332,8 +332,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the matrices are independent and this build "
-              "has no multi-GPU path (see DESIGN.md on sharding). Run with --gpus 1.",
+        print("bench.py measures one GPU: the matrices are independent, and the library "
+              "has no multi-GPU path. Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -342,19 +342,14 @@ def test_f64_paths_on_precision_recipe(ksym):
     residual <= 1e-11 ||A||_F everywhere; the plain path meets the float32
     tolerances away from its known weak spot (relative gaps below 1e-3, where
     the closed-form angle solve loses accuracy even in float64)."""
-    import os
     n = (1 << 16) + 5
     P32, kinds = synth.make_precision(n, seed=1306631, return_kinds=True)
     P64 = P32.astype(np.float64)
     for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
         g = _run(ksym, P64, torch.float64, path=path)
         bad = ~np.isfinite(g["D"]).all(0) | ~np.isfinite(g["lam"]).all(0) | ~np.isfinite(g["phi"]).all(0)
-        if bad.any():
-            os.makedirs("gpurun_out", exist_ok=True)
-            idx = np.nonzero(bad)[0][:50]
-            np.savetxt(f"gpurun_out/nan_inputs_path{path}.txt", P64[:, idx].T, fmt="%.17g")
-            np.savetxt(f"gpurun_out/nan_kinds_path{path}.txt", kinds[idx], fmt="%d")
-        assert not bad.any(), (path, int(bad.sum()), np.bincount(kinds[bad], minlength=6))
+        assert not bad.any(), (path, int(bad.sum()), np.bincount(kinds[bad], minlength=6),
+                               P64[:, np.nonzero(bad)[0][:3]].T.tolist())
         assert H.orth_err(g["D"]).max() < 1e-14
         assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
         res = H.residual3(P64, g["lam"], g["D"])
