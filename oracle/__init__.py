@@ -47,7 +47,7 @@ def _load():
         _lib.ko_eig3_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
         _lib.ko_eig2_batch.argtypes = [i64, P, P, P, P, cint]
         _lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
-        _lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
+        _lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, P, P, dbl, dbl, cint]
         _lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
         _lib.ko_compose3_batch.argtypes = [i64, P, P, P, cint]
         _lib.ko_compose2_batch.argtypes = [i64, P, P, P, cint]
@@ -123,20 +123,27 @@ def jacobi3(planes, threads=None):
     return {"lam": lam, "V": V, "lam_lo": lo}
 
 
-def eig3_bwd(lam, D, glam=None, gD=None, eps=0.0, threads=None):
+def eig3_bwd(lam, D, glam=None, gD=None, eps=0.0, threads=None, phi=None, gphi=None, delta=0.0):
     """Adjoint: plane gradients gA (6, n) from the forward outputs and the
-    cotangents (None = zero).  eps is the absolute gap regulariser."""
+    cotangents (None = zero).  eps is the absolute gap regulariser; with phi
+    and gphi (the angles and their cotangents) the angle term is included,
+    delta regularising 1/cos(phi2)."""
     lib = _load()
     L = _planes(lam, 3); Dp = _planes(D, 9)
     n = L[0].size
     gl = _planes(glam, 3) if glam is not None else None
     gd = _planes(gD, 9) if gD is not None else None
+    ang = phi is not None and gphi is not None
+    ph = _planes(phi, 3) if ang else None
+    gp = _planes(gphi, 3) if ang else None
     gA = np.empty((6, n))
     lib.ko_eig3_bwd_batch(
         n, ctypes.cast(_ptrs(L), ctypes.c_void_p), ctypes.cast(_ptrs(Dp), ctypes.c_void_p),
         ctypes.cast(_ptrs(gl), ctypes.c_void_p) if gl else None,
         ctypes.cast(_ptrs(gd), ctypes.c_void_p) if gd else None,
-        ctypes.cast(_ptrs(list(gA)), ctypes.c_void_p), float(eps), threads or default_threads())
+        ctypes.cast(_ptrs(ph), ctypes.c_void_p) if ph else None,
+        ctypes.cast(_ptrs(gp), ctypes.c_void_p) if gp else None,
+        ctypes.cast(_ptrs(list(gA)), ctypes.c_void_p), float(eps), float(delta), threads or default_threads())
     return gA
 
 

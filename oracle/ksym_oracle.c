@@ -420,9 +420,16 @@ void ko_jacobi3_ld(const double A6[6], double lam_out[3], double V_out[9],
 /*   F_ij = (lam_j - lam_i) / ((lam_j - lam_i)^2 + eps^2), F_ii = 0,          */
 /* and the six plane gradients gA_ii = Abar_ii, gA_ij = Abar_ij + Abar_ji.   */
 /* eps = 0 gives the exact 1 / (lam_j - lam_i).                              */
+/* Angle cotangents (phi, gphi non-NULL): with D = R1 R2 R3 (eq. (2.6)) and  */
+/* R_k = exp(phi_k [e_k]x), D^T dD = [w]x with w = M dphi, the columns of M  */
+/* R3^T R2^T e1 = (c2 c3, -c2 s3, s2), R3^T e2 = (s3, c3, 0), e3; so gphi     */
+/* acts as wbar = M^-T gphi added to (E_32, E_13, E_21) of E = D^T Dbar.      */
+/* M^-T divides by c2 = cos phi2 (gimbal lock at c2 = 0), regularised as    */
+/* c2 / (c2^2 + delta^2).                                                    */
 /* ------------------------------------------------------------------------ */
 void ko_eig3_bwd(const double lam[3], const double D9[9], const double glam[3],
-                 const double gD9[9], double eps, double gA[6])
+                 const double gD9[9], const double phi[3], const double gphi[3], double eps, double delta,
+                 double gA[6])
 {
     double D[3][3], G[3][3], E[3][3], M[3][3], T[3][3], Abar[3][3];
     for (int i = 0; i < 3; ++i)
@@ -437,6 +444,14 @@ void ko_eig3_bwd(const double lam[3], const double D9[9], const double glam[3],
             for (int k = 0; k < 3; ++k) s += D[k][i] * G[k][j];
             E[i][j] = s;
         }
+    if (phi && gphi) {
+        const double c2 = cos(phi[1]), s2 = sin(phi[1]), c3 = cos(phi[2]), s3 = sin(phi[2]);
+        const double u = (gphi[0] - s2 * gphi[2]) * c2 / (c2 * c2 + delta * delta);
+        const double v = gphi[1];
+        E[2][1] += c3 * u + s3 * v;
+        E[0][2] += -s3 * u + c3 * v;
+        E[1][0] += gphi[2];
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             if (i == j) {
@@ -546,9 +561,9 @@ void ko_compose2(const double lam[2], double phi, double A[3])
 typedef struct {
     int kind;                     /* 3: eig3, 2: eig2, 4: jacobi, 5: bwd, 6: 2x2 bwd, 7/8: compose 3x3/2x2 */
     int64_t lo, hi;
-    const double *in[24];
+    const double *in[32];
     double *out[16];
-    double tau, eps;
+    double tau, eps, delta;
     int8_t *flags;
 } ko_job;
 
@@ -582,12 +597,15 @@ static void *ko_worker(void *arg)
             for (int k = 0; k < 3; ++k)
                 if (j->out[12 + k]) j->out[12 + k][i] = (double)(ld[k] - (long double)lam[k]);
         } else if (j->kind == 5) {
-            double lam[3], D[9], gl[3], gD[9], gA[6];
+            double lam[3], D[9], gl[3], gD[9], ph[3], gp[3], gA[6];
             for (int k = 0; k < 3; ++k) lam[k] = j->in[k][i];
             for (int k = 0; k < 9; ++k) D[k] = j->in[3 + k][i];
             for (int k = 0; k < 3; ++k) gl[k] = j->in[12 + k] ? j->in[12 + k][i] : 0.0;
             for (int k = 0; k < 9; ++k) gD[k] = j->in[15 + k] ? j->in[15 + k][i] : 0.0;
-            ko_eig3_bwd(lam, D, gl, gD, j->eps, gA);
+            const int ang = j->in[24] && j->in[27];
+            for (int k = 0; k < 3; ++k) ph[k] = ang ? j->in[24 + k][i] : 0.0;
+            for (int k = 0; k < 3; ++k) gp[k] = ang ? j->in[27 + k][i] : 0.0;
+            ko_eig3_bwd(lam, D, gl, gD, ang ? ph : NULL, ang ? gp : NULL, j->eps, j->delta, gA);
             for (int k = 0; k < 6; ++k) j->out[k][i] = gA[k];
         } else if (j->kind == 6) {
             double lam[2], D[4], gl[2], gD[4], gA[3];
@@ -681,10 +699,13 @@ void ko_jacobi3_batch(int64_t n, const double *const in[6], double *const lam[3]
     run_jobs(&j, n, nthreads);
 }
 
-/* eps: absolute gap regulariser; glam / gD may be NULL (zero cotangent) */
+/* eps: absolute gap regulariser; glam / gD may be NULL (zero cotangent);
+   phi and gphi (both or neither): the angle cotangents, delta the gimbal
+   regulariser */
 void ko_eig3_bwd_batch(int64_t n, const double *const lam[3], const double *const D[9],
                        const double *const glam[3], const double *const gD[9],
-                       double *const gA[6], double eps, int nthreads)
+                       const double *const phi[3], const double *const gphi[3],
+                       double *const gA[6], double eps, double delta, int nthreads)
 {
     ko_job j;
     memset(&j, 0, sizeof j);
@@ -693,8 +714,11 @@ void ko_eig3_bwd_batch(int64_t n, const double *const lam[3], const double *cons
     for (int k = 0; k < 9; ++k) j.in[3 + k] = D[k];
     for (int k = 0; k < 3; ++k) j.in[12 + k] = glam ? glam[k] : NULL;
     for (int k = 0; k < 9; ++k) j.in[15 + k] = gD ? gD[k] : NULL;
+    for (int k = 0; k < 3; ++k) j.in[24 + k] = (phi && gphi) ? phi[k] : NULL;
+    for (int k = 0; k < 3; ++k) j.in[27 + k] = (phi && gphi) ? gphi[k] : NULL;
     for (int k = 0; k < 6; ++k) j.out[k] = gA[k];
     j.eps = eps;
+    j.delta = delta;
     run_jobs(&j, n, nthreads);
 }
 

@@ -492,3 +492,51 @@ def test_compose_round_trips_and_closed_forms():
     assert np.abs(A2 - P2).max() < 1e-14
     A20 = oracle.compose2(lam[:2], np.zeros(500))
     assert np.array_equal(A20[:2], lam[:2]) and np.all(A20[2] == 0)
+
+
+def test_adjoint_with_angle_cotangents_against_central_differences():
+    """3x3 adjoint with cotangents of the Euler angles (eq. (2.6)), alone and
+    with lam and D, against central differences of the oracle's forward, on
+    matrices with separated eigenvalues, away from gimbal lock (cos phi2 = 0)
+    and from the ends of the angle ranges; the gimbal regulariser's limits."""
+    d = synth.make_grad(800, seed=43, dtype=np.float64, min_gap=5e-2)
+    P = d["planes3"]
+    o = oracle.eig3(P)
+    lam, D, phi = o["lam"], o["D"], o["phi"]
+    rng = np.random.default_rng(44)
+    n = P.shape[1]
+    w, G, gp = rng.standard_normal((3, n)), rng.standard_normal((9, n)), rng.standard_normal((3, n))
+    h = 1e-6
+
+    def fd_of(loss):
+        fd = np.empty((6, n))
+        for k in range(6):
+            Pp = P.copy(); Pp[k] += h
+            Pm = P.copy(); Pm[k] -= h
+            fd[k] = (loss(Pp) - loss(Pm)) / (2 * h)
+        return fd
+
+    away = (np.cos(phi[1]) > 0.2) & (np.abs(np.abs(phi[0]) - np.pi) > 0.1) & (np.abs(np.abs(phi[2]) - np.pi / 2) > 0.1)
+    for use_rest in (False, True):
+        gA = oracle.eig3_bwd(lam, D, w if use_rest else None, G if use_rest else None, eps=0.0,
+                             phi=phi, gphi=gp)
+
+        def loss(Pp, use_rest=use_rest):
+            f = oracle.eig3(Pp)
+            out = (gp * f["phi"]).sum(0)
+            if use_rest:
+                out = out + (w * f["lam"]).sum(0) + (G * f["D"]).sum(0)
+            return out
+
+        fd = fd_of(loss)
+        ok = away & np.all(np.abs(fd) < 1e3, axis=0)
+        assert ok.sum() > 300
+        rel = np.linalg.norm(fd - gA, axis=0)[ok] / np.linalg.norm(gA, axis=0)[ok]
+        assert rel.max() < 1e-5, (use_rest, rel.max())
+    a = oracle.eig3_bwd(lam, D, None, None, eps=0.0, phi=phi, gphi=gp, delta=0.0)
+    b = oracle.eig3_bwd(lam, D, None, None, eps=0.0, phi=phi, gphi=gp, delta=1e-12)
+    assert np.abs(a - b)[:, away].max() < 1e-9 * np.abs(a[:, away]).max()
+    # a huge delta leaves only the parts of gphi that do not divide by cos(phi2)
+    c = oracle.eig3_bwd(lam, D, None, None, eps=0.0, phi=phi, gphi=np.stack([gp[0], 0 * gp[1], 0 * gp[2]]),
+                        delta=1e12)
+    assert np.abs(c).max() < 1e-9

@@ -56,6 +56,9 @@ MUTANTS = [
      "E[i][j] = D[i][0] * G[0][j] + D[i][1] * G[1][j];"),
     ("compose3 transposed", "s += D[i][k] * lam[k] * D[j][k];", "s += D[k][i] * lam[k] * D[k][j];"),
     ("compose2 angle sign", "const double D[2][2] = {{c, -s}, {s, c}};", "const double D[2][2] = {{c, s}, {-s, c}};"),
+    ("bwd angle column sign", "E[0][2] += -s3 * u + c3 * v;", "E[0][2] += s3 * u + c3 * v;"),
+    ("bwd angle gimbal term", "const double u = (gphi[0] - s2 * gphi[2]) * c2",
+     "const double u = (gphi[0] + s2 * gphi[2]) * c2"),
     ("compose3 plane order", "A[4] = M[0][2];\n    A[5] = M[1][2];", "A[4] = M[1][2];\n    A[5] = M[0][2];"),
 ]
 
@@ -156,6 +159,25 @@ def _pins():
         fails.append("adjoint2 (forward too rough)")
     elif not (np.linalg.norm(fd2 - gA2, axis=0)[sm] / np.linalg.norm(gA2, axis=0)[sm]).max() < 1e-6:
         fails.append("adjoint2")
+    # angle cotangents of the 3x3 adjoint vs central differences of the forward's angles
+    da = synth.make_grad(120, seed=506, dtype=np.float64, min_gap=5e-2)
+    Pa = da["planes3"]
+    oa = oracle.eig3(Pa)
+    gpa = np.random.default_rng(507).standard_normal((3, Pa.shape[1]))
+    gAa = oracle.eig3_bwd(oa["lam"], oa["D"], None, None, eps=0.0, phi=oa["phi"], gphi=gpa)
+    fda = np.empty_like(gAa)
+    for k in range(6):
+        Pp, Pm = Pa.copy(), Pa.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fda[k] = ((gpa * oracle.eig3(Pp)["phi"]).sum(0) - (gpa * oracle.eig3(Pm)["phi"]).sum(0)) / (2 * h)
+    pa = oa["phi"]
+    oka = ((np.cos(pa[1]) > 0.2) & (np.abs(np.abs(pa[0]) - np.pi) > 0.1)
+           & (np.abs(np.abs(pa[2]) - np.pi / 2) > 0.1) & np.all(np.abs(fda) < 1e3, axis=0))
+    if oka.sum() < 40:
+        fails.append("adjoint angles (too few smooth cases)")
+    elif not (np.linalg.norm(fda - gAa, axis=0)[oka] / np.linalg.norm(gAa, axis=0)[oka]).max() < 1e-5:
+        fails.append("adjoint angles")
     # inverse maps: round trips through the forward
     Pc = synth.make_plain(300, 16, seed=505)["planes3"]
     oc = oracle.eig3(Pc)
@@ -179,7 +201,7 @@ def _with_lib(path):
     lib.ko_eig3_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
     lib.ko_eig2_batch.argtypes = [i64, P, P, P, P, cint]
     lib.ko_jacobi3_batch.argtypes = [i64, P, P, P, P, cint]
-    lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]
+    lib.ko_eig3_bwd_batch.argtypes = [i64, P, P, P, P, P, P, P, dbl, dbl, cint]
     lib.ko_eig2_bwd_batch.argtypes = [i64, P, P, P, P, P, P, dbl, cint]
     lib.ko_compose3_batch.argtypes = [i64, P, P, P, cint]
     lib.ko_compose2_batch.argtypes = [i64, P, P, P, cint]
