@@ -214,6 +214,23 @@ ksym_status ksym_eig3_aos(ksym_dtype dtype, int64_t n, const void *a_aos,
                           const ksym_opts *opts, void *stream);
 
 /*
+ * ksym_eig3_backward with the cotangent gphi (3 planes) of the Euler angles
+ * phi (3 planes, as ksym_eig3 writes them; both required) added to those of
+ * lam and D.  With D = R1 R2 R3 (eq. (2.6)) and R_k = exp(phi_k [e_k]x), the
+ * body rates w of D^T dD = [w]x are w = M dphi, M's columns (c2 c3, -c2 s3,
+ * s2), (s3, c3, 0), (0, 0, 1) (ck, sk: cosine and sine of phi_k); gphi acts
+ * as M^-T gphi added to (E_32, E_13, E_21) of E = D^T gD.  M^-T divides by
+ * c2 = cos phi2, which vanishes at gimbal lock; it is regularised as
+ * c2 / (c2^2 + eps_rel^2).  The angles wrap at the ends of their ranges, where
+ * they are not differentiable.  Otherwise as ksym_eig3_backward.
+ */
+ksym_status ksym_eig3_backward_angles(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                                      const void *const D[9], const void *const phi[3],
+                                      const void *const gap[3], const void *const glam[3],
+                                      const void *const gD[9], const void *const gphi[3], void *const gA[6],
+                                      double eps_rel, void *stream);
+
+/*
  * Inverse maps, from the definitions (2.5)-(2.6) (the other side of the
  * forward, not a step of the paper's method): A = D diag(lam) D^T with
  * D = R1(phi1) R2(phi2) R3(phi3) for 3x3, D = R(phi) for 2x2.  lam and phi are

@@ -88,6 +88,8 @@ _lib.ksym_eig3_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P
                                     ctypes.c_double, _P]
 _lib.ksym_eig2_backward.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                     ctypes.c_double, _P]
+_lib.ksym_eig3_backward_angles.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                           ctypes.c_double, _P]
 _lib.ksym_compose3.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P]
 _lib.ksym_compose2.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P]
 _lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
@@ -100,7 +102,7 @@ _lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINT
 _lib.ksym_plan_destroy.argtypes = [_P]
 _lib.ksym_plan_destroy.restype = None
 for _f in ("ksym_eig2", "ksym_zero_counters", "ksym_eig3", "ksym_eig3_aos", "ksym_eig3_backward",
-           "ksym_eig2_backward", "ksym_compose3", "ksym_compose2",
+           "ksym_eig2_backward", "ksym_compose3", "ksym_compose2", "ksym_eig3_backward_angles",
            "ksym_plan_create", "ksym_plan_run", "ksym_plan_capture", "ksym_plan_replay",
            "ksym_plan_info"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -262,8 +264,10 @@ def eig3_aos(records, opts=None, path=None, outputs=("lam", "D", "phi", "flags")
     return out
 
 
-def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None):
-    """Adjoint of eig3 for the plane gradients gA (6, n); see include/ksym.h."""
+def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None, phi=None, gphi=None):
+    """Adjoint of eig3 for the plane gradients gA (6, n); see include/ksym.h.
+    With gphi (the cotangent of the Euler angles) the angles phi are needed
+    too, and ksym_eig3_backward_angles runs."""
     lp, n, ref = _rows(lam, 3)
     dt = _dt(ref)
     if eps_rel is None:
@@ -274,6 +278,13 @@ def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None):
     gp = _ptr_array(_rows(gap, 3)[0]) if gap is not None else None
     if out is None:
         out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
+    if gphi is not None:
+        if phi is None:
+            raise ValueError("gphi needs the angles phi")
+        _check(_lib.ksym_eig3_backward_angles(dt, n, _ptr_array(lp), _ptr_array(Dp), _ptr_array(_rows(phi, 3)[0]),
+                                              gp, gl, gd, _ptr_array(_rows(gphi, 3)[0]),
+                                              _ptr_array(_rows(out, 6)[0]), float(eps_rel), _stream(ref)))
+        return out
     _check(_lib.ksym_eig3_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gp, gl, gd,
                                    _ptr_array(_rows(out, 6)[0]), float(eps_rel), _stream(ref)))
     return out
@@ -354,6 +365,31 @@ class Eig3Function(torch.autograd.Function):
 
 def eig3_autograd(planes, eps_rel=None, opts=None):
     return Eig3Function.apply(planes, eps_rel, opts)
+
+
+class Eig3AnglesFunction(torch.autograd.Function):
+    """lam, D, phi = Eig3AnglesFunction.apply(planes, eps_rel): differentiable
+    in lam, D and the Euler angles (regularised at gimbal lock; the angles are
+    not differentiable where they wrap)."""
+
+    @staticmethod
+    def forward(ctx, planes, eps_rel=None, opts=None):
+        out = eig3(planes.contiguous(), opts=opts, outputs=("lam", "D", "phi", "gap"))
+        ctx.save_for_backward(out["lam"], out["D"], out["phi"], out["gap"])
+        ctx.eps_rel = eps_rel
+        return out["lam"], out["D"], out["phi"]
+
+    @staticmethod
+    def backward(ctx, glam, gD, gphi):
+        lam, D, phi, gap = ctx.saved_tensors
+        gA = eig3_backward(lam, D, glam.contiguous() if glam is not None else None,
+                           gD.contiguous() if gD is not None else None, gap=gap, eps_rel=ctx.eps_rel,
+                           phi=phi, gphi=gphi.contiguous() if gphi is not None else None)
+        return gA, None, None
+
+
+def eig3_autograd_angles(planes, eps_rel=None, opts=None):
+    return Eig3AnglesFunction.apply(planes, eps_rel, opts)
 
 
 class Eig2Function(torch.autograd.Function):

@@ -532,11 +532,11 @@ ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const la
     return dtype == KSYM_F32 ? go(float()) : go(double());
 }
 
-ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const lam[3],
-                               const void *const D[9], const void *const gap[3],
-                               const void *const glam[3], const void *const gD[9], void *const gA[6],
-                               double eps_rel, void *stream) {
-    g_err.clear();
+static ksym_status eig3_backward_impl(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                                      const void *const D[9], const void *const phi[3], const void *const gap[3],
+                                      const void *const glam[3], const void *const gD[9],
+                                      const void *const gphi[3], void *const gA[6], double eps_rel,
+                                      void *stream) {
     if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
     if (n < 0) return fail(KSYM_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
     if (!(eps_rel >= 0.0) || eps_rel > 1e30) return fail(KSYM_E_ARG, "eps_rel must be finite and >= 0");
@@ -558,6 +558,12 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
     if (gD)
         for (int c = 0; c < 9; ++c)
             if (!gD[c] || !aligned(gD[c], es)) return fail(KSYM_E_ARG, "gD[%d] NULL or misaligned", c);
+    if (phi)
+        for (int c = 0; c < 3; ++c)
+            if (!phi[c] || !aligned(phi[c], es)) return fail(KSYM_E_ARG, "phi[%d] NULL or misaligned", c);
+    if (gphi)
+        for (int c = 0; c < 3; ++c)
+            if (!gphi[c] || !aligned(gphi[c], es)) return fail(KSYM_E_ARG, "gphi[%d] NULL or misaligned", c);
     ksym_opts o;
     ksym_opts_default(dtype, &o);
     o.mats_per_lane = 1;
@@ -574,6 +580,8 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
             for (int c = 0; c < 3; ++c) p.glam[c] = glam ? (const T *)glam[c] + start : nullptr;
             for (int c = 0; c < 9; ++c) p.gD[c] = gD ? (const T *)gD[c] + start : nullptr;
             for (int c = 0; c < 6; ++c) p.gA[c] = (T *)gA[c] + start;
+            for (int c = 0; c < 3; ++c) p.phi[c] = phi ? (const T *)phi[c] + start : nullptr;
+            for (int c = 0; c < 3; ++c) p.gphi[c] = gphi ? (const T *)gphi[c] + start : nullptr;
             int grid = 0;
             ksym_status st = grid_for(len, o.block * o.mats_per_lane, o.grid_mult, &grid);
             if (st != KSYM_OK) return st;
@@ -589,6 +597,24 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
         return KSYM_OK;
     };
     return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                               const void *const D[9], const void *const gap[3],
+                               const void *const glam[3], const void *const gD[9], void *const gA[6],
+                               double eps_rel, void *stream) {
+    g_err.clear();
+    return eig3_backward_impl(dtype, n, lam, D, nullptr, gap, glam, gD, nullptr, gA, eps_rel, stream);
+}
+
+ksym_status ksym_eig3_backward_angles(ksym_dtype dtype, int64_t n, const void *const lam[3],
+                                      const void *const D[9], const void *const phi[3],
+                                      const void *const gap[3], const void *const glam[3],
+                                      const void *const gD[9], const void *const gphi[3], void *const gA[6],
+                                      double eps_rel, void *stream) {
+    g_err.clear();
+    if (!phi || !gphi) return fail(KSYM_E_ARG, "phi and gphi are required (ksym_eig3_backward has neither)");
+    return eig3_backward_impl(dtype, n, lam, D, phi, gap, glam, gD, gphi, gA, eps_rel, stream);
 }
 
 // ------------------------------------------------------------- plans ------

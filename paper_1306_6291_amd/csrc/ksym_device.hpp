@@ -793,10 +793,11 @@ template <typename T> __device__ __forceinline__ Eig2<T> eig2_one(T a11, T a22, 
 // antisymmetric, S_ij = F_ij (E_ij - E_ji) for E = D^T gD; then gA_ij =
 // (D S D^T)_ij off the diagonal and gA_ii = (D S D^T)_ii / 2.
 // Slots: 0 = max, 1 = min, 2 = mid; gaps g12 = lam0 - lam1, g13 = lam0 - lam2,
-// g32 = lam2 - lam1.
+// g32 = lam2 - lam1.  wb: the body-rate cotangent of the Euler angles (see
+// angle_body_cotangent), added to (E_32, E_13, E_21); zeros without angles.
 template <typename T>
 __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD[9], T g12, T g13,
-                                         T g32, T eps2, T gA[6]) {
+                                         T g32, T eps2, const T wb[3], T gA[6]) {
     using M = Mth<T>;
     // K_ij = E_ij - E_ji = sum_r (D_ri gD_rj - D_rj gD_ri)
     T K01 = T(0), K02 = T(0), K12 = T(0);
@@ -806,6 +807,9 @@ __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD
         K02 += D[3 * r] * gD[3 * r + 2] - D[3 * r + 2] * gD[3 * r];
         K12 += D[3 * r + 1] * gD[3 * r + 2] - D[3 * r + 2] * gD[3 * r + 1];
     }
+    K01 -= wb[2];
+    K02 += wb[1];
+    K12 -= wb[0];
     // F_01 = (lam1 - lam0)/(..) = -g12/(g12^2+eps2); F_02 = -g13/(..); F_12 = (lam2 - lam1)/(..) = g32/(..)
     const T S01 = -M::div(g12, g12 * g12 + eps2) * K01;
     const T S02 = -M::div(g13, g13 * g13 + eps2) * K02;
@@ -829,6 +833,21 @@ __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD
     gA[3] = G(0, 1);
     gA[4] = G(0, 2);
     gA[5] = G(1, 2);
+}
+
+// The Euler angles' cotangent gphi as a cotangent of the body rates w of
+// D^T dD = [w]x (D = R1 R2 R3, eq. (2.6), R_k = exp(phi_k [e_k]x)): w = M dphi
+// with columns (c2 c3, -c2 s3, s2), (s3, c3, 0), (0, 0, 1), so wb = M^-T gphi.
+// M^-T divides by c2 = cos phi2 (gimbal lock at c2 = 0), regularised as
+// c2 / (c2^2 + delta2).
+template <typename T>
+__device__ __forceinline__ void angle_body_cotangent(T c2, T s2, T c3, T s3, const T gphi[3], T delta2,
+                                                     T wb[3]) {
+    const T u = (gphi[0] - s2 * gphi[2]) * Mth<T>::div(c2, c2 * c2 + delta2);
+    const T v = gphi[1];
+    wb[0] = c3 * u + s3 * v;
+    wb[1] = -s3 * u + c3 * v;
+    wb[2] = gphi[2];
 }
 
 // ------------------------------------------------------- 2x2 adjoint -------

@@ -974,6 +974,10 @@ __global__ __launch_bounds__(BS) void k_eig2(Eig2Ptrs<T> p, uint32_t n) {
 }
 
 // -------------------------------------------------------- adjoint ----------
+// sine and cosine in the element type
+__device__ __forceinline__ void sincos_t(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ __forceinline__ void sincos_t(double x, double &s, double &c) { sincos(x, &s, &c); }
+
 template <typename T> struct BwdPtrs {
     const T *lam[3];
     const T *D[9];
@@ -981,6 +985,8 @@ template <typename T> struct BwdPtrs {
     const T *glam[3];
     const T *gD[9];
     T *gA[6];
+    const T *phi[3];    // the Euler angles and their cotangent (both or none)
+    const T *gphi[3];
 };
 
 template <typename T> struct BwdArgs {
@@ -995,7 +1001,8 @@ template <typename T> struct BwdArgs {
 // from the argument segment in groups, one wide scalar load each (salt: see
 // karg_ptr), so all 27 plane loads can be issued back to back.
 template <typename T>
-__device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, double eps_rel, int salt) {
+__device__ __forceinline__ void bwd_lane(bool has_gap, bool has_ang, uint32_t i, uint32_t n, double eps_rel,
+                                         int salt) {
     constexpr uint32_t P = (uint32_t)offsetof(BwdArgs<T>, p);
     const PtrN<const T, 12> pin = karg_ptrs<const T, 12>(P + offsetof(BwdPtrs<T>, lam) + 8 * salt);   // lam, D
     const PtrN<const T, 12> pco = karg_ptrs<const T, 12>(P + offsetof(BwdPtrs<T>, glam) + 8 * salt);  // glam, gD
@@ -1021,7 +1028,19 @@ __device__ __forceinline__ void bwd_lane(bool has_gap, uint32_t i, uint32_t n, d
         g32 = (T)((double)L[2] - (double)L[1]);
     }
     const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
-    adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, gA);
+    T wb[3] = {T(0), T(0), T(0)};
+    if (has_ang) {   // uniform
+        const PtrN<const T, 6> pa = karg_ptrs<const T, 6>(P + offsetof(BwdPtrs<T>, phi) + 8 * salt);
+        const T f2 = ld_plane<T, kStream>(pa.p[1], n, i), f3 = ld_plane<T, kStream>(pa.p[2], n, i);
+        const T gphi[3] = {ld_plane<T, kStream>(pa.p[3], n, i), ld_plane<T, kStream>(pa.p[4], n, i),
+                           ld_plane<T, kStream>(pa.p[5], n, i)};
+        T s2, c2, s3, c3;
+        sincos_t(f2, s2, c2);
+        sincos_t(f3, s3, c3);
+        const T d = (T)eps_rel;
+        angle_body_cotangent<T>(c2, s2, c3, s3, gphi, d * d, wb);
+    }
+    adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, wb, gA);
     const PtrN<T, 6> po = karg_ptrs<T, 6>(P + offsetof(BwdPtrs<T>, gA) + 8 * salt);
 #pragma unroll
     for (int c = 0; c < 6; ++c) st_plane<T, kStream>(po.p[c], n, i, gA[c]);
@@ -1033,10 +1052,12 @@ __global__ __launch_bounds__(BS) void k_eig3_bwd(BwdArgs<T> a) {
     const uint32_t n = a.n;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
     const bool has_gap = a.p.gap[0] && a.p.gap[1] && a.p.gap[2];
+    const bool has_ang = a.p.phi[0] && a.p.phi[1] && a.p.phi[2] && a.p.gphi[0] && a.p.gphi[1] && a.p.gphi[2];
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int salt = (int)(t * (uint32_t)a.zero);
 #pragma unroll
-        for (int k = 0; k < MPL; ++k) bwd_lane<T>(has_gap, t * TILE + k * BS + threadIdx.x, n, a.eps_rel, salt);
+        for (int k = 0; k < MPL; ++k)
+            bwd_lane<T>(has_gap, has_ang, t * TILE + k * BS + threadIdx.x, n, a.eps_rel, salt);
     }
 }
 
@@ -1096,8 +1117,6 @@ template <typename T> struct ComposeArgs {
     int32_t pad;
 };
 
-__device__ __forceinline__ void sincos_t(float x, float &s, float &c) { sincosf(x, &s, &c); }
-__device__ __forceinline__ void sincos_t(double x, double &s, double &c) { sincos(x, &s, &c); }
 
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_compose3(ComposeArgs<T> a) {

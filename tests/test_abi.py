@@ -181,6 +181,20 @@ def test_eig2_backward_argument_errors(lib):
     assert f(5, 4, L, D, None, None, None, gA, 1e-6, None) == 2
 
 
+def test_backward_angles_argument_errors(lib):
+    P = ctypes.c_void_p
+    f = lib.ksym_eig3_backward_angles
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_double, P]
+    f.restype = ctypes.c_int
+    L, D, F, GP, gA = _planes(3), _planes(9), _planes(3), _planes(3), _planes(6)
+    assert f(0, 4, L, D, None, None, None, None, GP, gA, 1e-6, None) == 1     # phi required
+    assert f(0, 4, L, D, F, None, None, None, None, gA, 1e-6, None) == 1      # gphi required
+    assert f(0, 4, L, D, _planes(3, misalign=True), None, None, None, GP, gA, 1e-6, None) == 1
+    assert f(0, -1, L, D, F, None, None, None, GP, gA, 1e-6, None) == 1
+    assert f(0, 4, L, D, F, None, None, None, GP, gA, -1.0, None) == 1
+    assert f(3, 4, L, D, F, None, None, None, GP, gA, 1e-6, None) == 2
+
+
 def test_compose_argument_errors(lib):
     P = ctypes.c_void_p
     f3, f2 = lib.ksym_compose3, lib.ksym_compose2

@@ -332,6 +332,72 @@ def test_eig2_autograd_function(ksym):
     assert rel.max() < 1e-6, rel.max()
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_backward_with_angle_cotangents_matches_oracle(ksym, dtype):
+    """ksym_eig3_backward_angles (cotangents of lam, D and the Euler angles,
+    gap and gimbal regularisers) against the oracle's adjoint on the same
+    forward outputs; without the angle cotangent it equals the plain call."""
+    d = synth.make_grad(3001, seed=208, dtype=np.float64, min_gap=1e-2)
+    tdt = getattr(torch, dtype)
+    opts = ksym.Opts.defaults(ksym.F32 if dtype == "float32" else ksym.F64)
+    out = ksym.eig3(to_dev(d["planes3"], tdt), opts=opts, outputs=("lam", "D", "phi", "gap"))
+    rng = np.random.default_rng(209)
+    n = d["planes3"].shape[1]
+    w, G, gp = (to_dev(rng.standard_normal(s), tdt) for s in ((3, n), (9, n), (3, n)))
+    eps_rel = 1e-6 if dtype == "float32" else 1e-12
+    gA = ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], eps_rel=eps_rel, phi=out["phi"],
+                            gphi=gp).cpu().numpy().astype(np.float64)
+    lam = out["lam"].double().cpu().numpy()
+    eps = eps_rel * np.sqrt((lam ** 2).sum(0))
+    idx = np.arange(0, n, 11)
+    cols = lambda t: t.double().cpu().numpy()
+    L, Dn, F, W, Gn, GP = (cols(t) for t in (out["lam"], out["D"], out["phi"], w, G, gp))
+    ref = np.stack([oracle.eig3_bwd(L[:, i:i + 1], Dn[:, i:i + 1], W[:, i:i + 1], Gn[:, i:i + 1], eps=eps[i],
+                                    threads=1, phi=F[:, i:i + 1], gphi=GP[:, i:i + 1], delta=eps_rel)[:, 0]
+                    for i in idx], 1)
+    rel = np.linalg.norm(gA[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    tol = 1e-4 if dtype == "float32" else 1e-9
+    assert rel.max() < tol, rel.max()
+    plain = ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], eps_rel=eps_rel)
+    zero = ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], eps_rel=eps_rel, phi=out["phi"],
+                              gphi=torch.zeros_like(gp))
+    assert torch.equal(plain, zero)
+
+
+def test_autograd_angles_function(ksym):
+    """Eig3AnglesFunction: torch.autograd for a loss in lam, D and the Euler
+    angles, float64, against central differences of the GPU forward, away
+    from gimbal lock and the angle wraps."""
+    d = synth.make_grad(256, seed=210, dtype=np.float64, min_gap=5e-2)
+    P = to_dev(d["planes3"], torch.float64).requires_grad_(True)
+    rng = np.random.default_rng(211)
+    n = 256
+    w, G, gp = (to_dev(rng.standard_normal(s), torch.float64) for s in ((3, n), (9, n), (3, n)))
+    opts = ksym.Opts.defaults(ksym.F64)
+    lam, D, phi = ksym.eig3_autograd_angles(P, eps_rel=0.0, opts=opts)
+    ((w * lam).sum() + (G * D).sum() + (gp * phi).sum()).backward()
+    grad = P.grad.cpu().numpy()
+    base = P.detach()
+
+    def L(Pp):
+        l2, D2, p2 = ksym.eig3_autograd_angles(Pp, eps_rel=0.0, opts=opts)
+        return ((w * l2).sum(0) + (G * D2).sum(0) + (gp * p2).sum(0)).cpu().numpy()
+
+    h = 1e-6
+    fd = np.empty_like(grad)
+    for k in range(6):
+        Pp, Pm = base.clone(), base.clone()
+        Pp[k] += h
+        Pm[k] -= h
+        fd[k] = (L(Pp) - L(Pm)) / (2 * h)
+    f = phi.detach().cpu().numpy()
+    ok = ((np.cos(f[1]) > 0.2) & (np.abs(np.abs(f[0]) - np.pi) > 0.1) & (np.abs(np.abs(f[2]) - np.pi / 2) > 0.1)
+          & np.all(np.abs(fd) < 1e3, axis=0))
+    assert ok.sum() > 100
+    rel = np.linalg.norm(fd - grad, axis=0)[ok] / np.linalg.norm(grad, axis=0)[ok]
+    assert rel.max() < 1e-5, rel.max()
+
+
 # ------------------------------------------------------------ mixed plan ---
 def _mixed_case(ksym, total=200000, ngroups=64, seed=206):
     sizes, kinds = synth.mixed_group_sizes(total, ngroups, lo=100, hi=1e4, seed=seed)
