@@ -81,6 +81,60 @@ def check_f32_result(P, out, lam_ref, V_ref, label=""):
     # slot order (max, min, mid)
     assert np.all(lam[0] >= lam[2]) and np.all(lam[2] >= lam[1]), label
     # angles reproduce D (eq. (2.6)) to float32 rounding
-    R = H.rot_from_angles(out["phi"].astype(np.float64))
-    assert np.abs(R - H.as_mats(D)).max() < 2e-5, label
+    if "phi" in out:
+        R = H.rot_from_angles(out["phi"].astype(np.float64))
+        assert np.abs(R - H.as_mats(D)).max() < 2e-5, label
     return stats
+
+
+def props3_gpu(A, lam, D, chunk=1 << 22):
+    """Properties of a 3x3 result that hold at any batch size, evaluated on
+    the device in float64 over every matrix: the largest residual
+    max_k ||A d_k - lam_k d_k|| / ||A||_F, the largest |D^T D - I| and
+    |det D - 1|, and whether every matrix keeps the slot order (max, min,
+    mid).  A: (6, n) planes (A11, A22, A33, A12, A13, A23) or a view of
+    them; lam (3, n); D (9, n) row-major."""
+    import torch
+    n = lam.shape[1]
+    res_max, orth_max, det_max, order = 0.0, 0.0, 0.0, True
+    eye = torch.eye(3, dtype=torch.float64, device=lam.device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        a11, a22, a33, a12, a13, a23 = A[:, s:e].double()
+        M = torch.stack([torch.stack([a11, a12, a13], 1), torch.stack([a12, a22, a23], 1),
+                         torch.stack([a13, a23, a33], 1)], 1)
+        Dm = D[:, s:e].double().T.reshape(-1, 3, 3).contiguous()
+        L = lam[:, s:e].double().T
+        fro = torch.sqrt((M * M).sum((1, 2))).clamp_min(1e-300)
+        r = torch.linalg.vector_norm(torch.bmm(M, Dm) - Dm * L[:, None, :], dim=1).amax(1) / fro
+        assert torch.isfinite(r).all()
+        res_max = max(res_max, float(r.max()))
+        orth = (torch.bmm(Dm.transpose(1, 2).contiguous(), Dm) - eye).abs()
+        orth_max = max(orth_max, float(orth.amax()))
+        det = (Dm[:, 0, 0] * (Dm[:, 1, 1] * Dm[:, 2, 2] - Dm[:, 1, 2] * Dm[:, 2, 1])
+               - Dm[:, 0, 1] * (Dm[:, 1, 0] * Dm[:, 2, 2] - Dm[:, 1, 2] * Dm[:, 2, 0])
+               + Dm[:, 0, 2] * (Dm[:, 1, 0] * Dm[:, 2, 1] - Dm[:, 1, 1] * Dm[:, 2, 0]))
+        det_max = max(det_max, float((det - 1).abs().max()))
+        order = order and bool((L[:, 0] >= L[:, 2]).all()) and bool((L[:, 2] >= L[:, 1]).all())
+    return {"res": res_max, "orth": orth_max, "det": det_max, "order": order}
+
+
+def props2_gpu(A, lam, D, phi):
+    """The 2x2 counterpart over every matrix, in float64 on the device: the
+    largest residual relative to ||A||_F, the largest deviation of D from
+    R(phi) = [[cos, -sin], [sin, cos]] (eq. (2.5)), and the largest |phi|.
+    A: (3, n) planes (A11, A22, A12); lam (2, n); D (4, n); phi (n,)."""
+    import torch
+    if lam.shape[1] == 0:
+        return {"res": 0.0, "rot": 0.0, "phi_abs": 0.0}
+    a11, a22, a12 = A.double()
+    M = torch.stack([torch.stack([a11, a12], 1), torch.stack([a12, a22], 1)], 1)
+    Dm = D.double().T.reshape(-1, 2, 2).contiguous()
+    L = lam.double().T
+    fro = torch.sqrt((M * M).sum((1, 2))).clamp_min(1e-300)
+    r = torch.linalg.vector_norm(torch.bmm(M, Dm) - Dm * L[:, None, :], dim=1).amax(1) / fro
+    assert torch.isfinite(r).all()
+    p = phi.double()
+    c, s = torch.cos(p), torch.sin(p)
+    rot = (D.double() - torch.stack([c, -s, s, c])).abs().amax()
+    return {"res": float(r.max()), "rot": float(rot), "phi_abs": float(p.abs().max())}

@@ -10,7 +10,8 @@ import pytest
 import oracle
 import synth
 from tests import helpers as H
-from tests.gpu_common import certified_reference, check_f32_result, to_dev, to_np
+from tests.gpu_common import (DET_TOL_F32, ORTH_TOL_F32, RES_TOL_F32, certified_reference,
+                              check_f32_result, props2_gpu, props3_gpu, to_dev, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -473,12 +474,33 @@ def test_mixed_plan_graph_replays(ksym):
 
 
 # --------------------------------------------------- AoS tensor field -----
+def _oracle_adjoint_at(out, w, G, idx, eps_rel=1e-6):
+    """The oracle adjoint at the sampled columns idx of a forward result
+    `out` (lam, D and the saved gaps g12, g13, g32), as the GPU adjoint
+    evaluates it when handed the gaps: F depends on the eigenvalues only
+    through their differences, and the kernel takes those from the gaps
+    instead of the rounded lam, so the oracle is given the eigenvalues
+    (lam1, lam1 - g13 - g32, lam1 - g13), whose differences are the gaps.
+    The regulariser is the GPU's, eps = eps_rel ||lam||.  Returns gA_ref
+    (6, len(idx))."""
+    ti = torch.from_numpy(idx).cuda()
+    lam = out["lam"][:, ti].cpu().numpy().astype(np.float64)
+    D = out["D"][:, ti].cpu().numpy().astype(np.float64)
+    gap = out["gap"][:, ti].cpu().numpy().astype(np.float64)
+    lam_d = np.stack([lam[0], lam[0] - gap[1] - gap[2], lam[0] - gap[1]])
+    w = w[:, idx].astype(np.float64)
+    G = G[:, idx].astype(np.float64)
+    eps = eps_rel * np.sqrt((lam ** 2).sum(0))
+    return np.stack([oracle.eig3_bwd(lam_d[:, i:i + 1], D[:, i:i + 1], w[:, i:i + 1], G[:, i:i + 1],
+                                     eps=eps[i], threads=1)[:, 0] for i in range(len(idx))], 1)
+
+
 def test_field_workload_aos_forward_backward(ksym):
     """The tensor-field recipe on a 32^3 grid: SPD tensors with eigenvalues in
     [1e-4, 1e-2], smooth rotations, 5 % isotropic voxels, array-of-structures
     input.  Forward meets the float32 tolerances; isotropic voxels come out
     as lam I with D = I; SoA and AoS agree bitwise; the adjoint matches the
-    oracle's on the same outputs."""
+    oracle's on the same outputs and saved gaps."""
     d = synth.make_field(32, 32, 32, seed=208)
     rec = d["aos"]
     P32 = np.ascontiguousarray(rec.T)
@@ -498,13 +520,8 @@ def test_field_workload_aos_forward_backward(ksym):
         assert np.array_equal(g[k], soa[k]), k
     gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
                             to_dev(d["G"], torch.float32), gap=out["gap"]).cpu().numpy()
-    lam = g["lam"].astype(np.float64)
-    eps = 1e-6 * np.sqrt((lam ** 2).sum(0))
-    idx = np.arange(0, lam.shape[1], 13)
-    ref = np.stack([oracle.eig3_bwd(lam[:, i:i + 1], g["D"][:, i:i + 1].astype(np.float64),
-                                    d["w"][:, i:i + 1].astype(np.float64),
-                                    d["G"][:, i:i + 1].astype(np.float64), eps=eps[i], threads=1)[:, 0]
-                    for i in idx], 1)
+    idx = np.arange(0, g["lam"].shape[1], 13)
+    ref = _oracle_adjoint_at(out, d["w"], d["G"], idx)
     rel = np.linalg.norm(gA[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert rel.max() < 1e-4, rel.max()
 
@@ -521,27 +538,9 @@ def test_precision_workload_full_size_sampled(ksym):
     opts = ksym.tuned_opts("eig3", ksym.F32)
     out = ksym.eig3(A, opts=opts, outputs=("lam", "D", "phi", "flags"))
     torch.cuda.synchronize()
-    res_max, orth_max, det_max = 0.0, 0.0, 0.0
-    for s in range(0, n, 1 << 22):
-        e = s + (1 << 22)
-        Pc = A[:, s:e].double()
-        a11, a22, a33, a12, a13, a23 = Pc
-        M = torch.stack([torch.stack([a11, a12, a13], 1), torch.stack([a12, a22, a23], 1),
-                         torch.stack([a13, a23, a33], 1)], 1)
-        D = out["D"][:, s:e].double().T.reshape(-1, 3, 3).contiguous()
-        L = out["lam"][:, s:e].double().T
-        fro = torch.sqrt((M * M).sum((1, 2))).clamp_min(1e-300)
-        r = torch.linalg.vector_norm(torch.bmm(M, D) - D * L[:, None, :], dim=1).amax(1) / fro
-        assert torch.isfinite(r).all()
-        res_max = max(res_max, float(r.max()))
-        orth = (torch.bmm(D.transpose(1, 2).contiguous(), D) - torch.eye(3, dtype=torch.float64, device="cuda")).abs()
-        orth_max = max(orth_max, float(orth.amax()))
-        det = (D[:, 0, 0] * (D[:, 1, 1] * D[:, 2, 2] - D[:, 1, 2] * D[:, 2, 1])
-               - D[:, 0, 1] * (D[:, 1, 0] * D[:, 2, 2] - D[:, 1, 2] * D[:, 2, 0])
-               + D[:, 0, 2] * (D[:, 1, 0] * D[:, 2, 1] - D[:, 1, 1] * D[:, 2, 0]))
-        det_max = max(det_max, float((det - 1).abs().max()))
-        assert bool((L[:, 0] >= L[:, 2]).all()) and bool((L[:, 2] >= L[:, 1]).all())
-    assert res_max <= 1e-5 and orth_max <= 1e-5 and det_max <= 1e-5, (res_max, orth_max, det_max)
+    pr = props3_gpu(A, out["lam"], out["D"])
+    assert pr["order"], pr
+    assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
     rng = np.random.default_rng(209)
     idx = np.sort(rng.choice(n, size=1 << 15, replace=False))
     P64 = P32[:, idx].astype(np.float64)
@@ -549,3 +548,144 @@ def test_precision_workload_full_size_sampled(ksym):
     ti = torch.from_numpy(idx).cuda()
     g = {k: v[:, ti].cpu().numpy() if v.dim() == 2 else v[ti].cpu().numpy() for k, v in out.items()}
     check_f32_result(P64, g, lam_ref, V_ref, "full-size sample")
+
+
+# ------------------------------ full-size mixed, gradient and field workloads -----
+def test_mixed_workload_full_size_sampled(ksym):
+    """2^26 mixed matrices (30 % 2x2, 70 % 3x3, N(0,1) entries) in 1024 groups
+    of log-uniform sizes, run as the benchmark runs them: one plan with the
+    tuned options, captured in a HIP graph and replayed.  Every matrix of every
+    group is checked on the GPU in float64 (residual, orthogonality, det and
+    slot order for 3x3; residual and D = R(phi) for 2x2); 8 sampled matrices
+    per group are checked one by one against the oracle with the float32
+    tolerances."""
+    total = 1 << 26
+    sizes, kinds = synth.mixed_group_sizes(total)
+    rng = np.random.default_rng(synth.BASE_SEED + 1002)
+    pick = np.random.default_rng(210)
+    groups, samples = [], []
+    for s, k in zip(sizes, kinds):
+        s, k = int(s), int(k)
+        P = rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)
+        idx = np.sort(pick.choice(s, size=min(8, s), replace=False))
+        samples.append((idx, P[:, idx].copy()))
+        t = to_dev(P, torch.float32)
+        del P
+        if k == 3:
+            out = {"lam": torch.empty((3, s), device="cuda"), "D": torch.empty((9, s), device="cuda"),
+                   "phi": torch.empty((3, s), device="cuda")}
+        else:
+            out = {"lam": torch.empty((2, s), device="cuda"), "D": torch.empty((4, s), device="cuda"),
+                   "phi": torch.empty((s,), device="cuda")}
+        groups.append((k, t, out))
+    plan = ksym.Plan(groups, opts=ksym.tuned_opts("mixed", ksym.F32))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture(stream)
+    torch.cuda.synchronize()
+    plan.replay(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    s3 = {"P": [], "lam": [], "D": [], "phi": []}
+    s2 = {"P": [], "lam": [], "D": [], "phi": []}
+    for (k, t, out), (idx, Ps) in zip(groups, samples):
+        if k == 3:
+            pr = props3_gpu(t, out["lam"], out["D"])
+            assert pr["order"], pr
+            assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
+        else:
+            pr = props2_gpu(t, out["lam"], out["D"], out["phi"])
+            assert pr["res"] <= RES_TOL_F32 and pr["rot"] <= 3e-7 and pr["phi_abs"] <= math.pi / 4 + 1e-6, pr
+        ti = torch.from_numpy(idx).cuda()
+        acc = s3 if k == 3 else s2
+        acc["P"].append(Ps)
+        for key in ("lam", "D", "phi"):
+            v = out[key]
+            acc[key].append((v[:, ti] if v.dim() == 2 else v[ti]).cpu().numpy())
+    plan.close()
+    g3 = {key: np.concatenate(v, axis=-1) for key, v in s3.items()}
+    P64 = g3.pop("P").astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    check_f32_result(P64, g3, lam_ref, V_ref, "mixed full-size 3x3 sample")
+    g2 = {key: np.concatenate(v, axis=-1) for key, v in s2.items()}
+    P64 = g2.pop("P").astype(np.float64)
+    ref = oracle.eig2(P64)
+    A2 = _mats2(P64)
+    f = np.linalg.norm(A2.reshape(-1, 4), axis=1)
+    lam_err = (np.abs(g2["lam"].astype(np.float64) - ref["lam"]).max(0) / f).max()
+    phi_err = np.abs(g2["phi"].astype(np.float64) - ref["phi"]).max()
+    assert lam_err < 2e-6 and phi_err < 1e-6, (lam_err, phi_err)
+
+
+def test_gradient_workload_full_size_sampled(ksym):
+    """2^22 matrices of the gradient recipe in the benchmark's launch
+    configuration (tuned options with the pair certificate tau_vec, outputs
+    lam, D and the gaps, then the adjoint with the saved gaps).  Every
+    forward result is checked on the GPU in float64; 2^12 sampled matrices
+    are checked against the certified reference, and their gradients against
+    the oracle adjoint on the exact eigenpairs (signs aligned to the GPU's),
+    per matrix ||dA - dA_ref||_F <= 1e-4 ||dA_ref||_F."""
+    n = 1 << 22
+    d = synth.make_grad(n)
+    A = to_dev(d["planes3"], torch.float32)
+    opts = ksym.tuned_opts("eig3_grad", ksym.F32)
+    out = {"lam": torch.empty((3, n), device="cuda"), "D": torch.empty((9, n), device="cuda"),
+           "gap": torch.empty((3, n), device="cuda")}
+    ksym.eig3(A, opts=opts, out=out)
+    gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
+                            to_dev(d["G"], torch.float32), gap=out["gap"])
+    torch.cuda.synchronize()
+    pr = props3_gpu(A, out["lam"], out["D"])
+    assert pr["order"], pr
+    assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
+    assert bool(torch.isfinite(gA).all())
+    idx = np.sort(np.random.default_rng(211).choice(n, size=1 << 12, replace=False))
+    ti = torch.from_numpy(idx).cuda()
+    P64 = d["planes3"][:, idx].astype(np.float64)
+    g = {k: out[k][:, ti].cpu().numpy() for k in ("lam", "D")}
+    lam_ref, V_ref = certified_reference(P64)
+    check_f32_result(P64, g, lam_ref, V_ref, "gradient full-size sample")
+    L, V = _aligned_reference(P64, g["lam"].astype(np.float64), g["D"].astype(np.float64))
+    ref = oracle.eig3_bwd(L, V, d["w"][:, idx].astype(np.float64), d["G"][:, idx].astype(np.float64), eps=0.0)
+    got = gA[:, ti].cpu().numpy()
+    rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert rel.max() <= 1e-4, (rel.max(), np.percentile(rel, 99.9))
+
+
+def test_field_workload_full_size_sampled(ksym):
+    """The 256^3 tensor field in the benchmark's launch configuration
+    (array-of-structures input, tuned options, outputs lam, D and the gaps,
+    then the adjoint with the saved gaps).  Every voxel is checked on the GPU
+    in float64; isotropic voxels come out exactly as lam I with D = I; 2^13
+    sampled voxels are checked against the certified reference, and 2^11 of
+    their gradients against the oracle adjoint on the same outputs."""
+    nx = 256
+    d = synth.make_field(nx, nx, nx)
+    n = nx ** 3
+    rec = to_dev(d["aos"], torch.float32)
+    opts = ksym.tuned_opts("eig3_aos", ksym.F32)
+    out = {"lam": torch.empty((3, n), device="cuda"), "D": torch.empty((9, n), device="cuda"),
+           "gap": torch.empty((3, n), device="cuda")}
+    ksym.eig3_aos(rec, opts=opts, out=out)
+    gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
+                            to_dev(d["G"], torch.float32), gap=out["gap"])
+    torch.cuda.synchronize()
+    pr = props3_gpu(rec.T, out["lam"], out["D"])
+    assert pr["order"], pr
+    assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
+    assert bool(torch.isfinite(gA).all())
+    iso = torch.from_numpy(d["iso"]).cuda()
+    eye = torch.tensor([1, 0, 0, 0, 1, 0, 0, 0, 1], dtype=torch.float32, device="cuda")[:, None]
+    assert bool((out["D"][:, iso] == eye).all())
+    assert bool((out["lam"][:, iso] == rec[iso, 0][None, :]).all())
+    pick = np.random.default_rng(212)
+    idx = np.sort(pick.choice(n, size=1 << 13, replace=False))
+    ti = torch.from_numpy(idx).cuda()
+    P64 = d["aos"][idx].T.astype(np.float64)
+    g = {k: out[k][:, ti].cpu().numpy() for k in ("lam", "D")}
+    lam_ref, V_ref = certified_reference(P64)
+    check_f32_result(P64, g, lam_ref, V_ref, "field full-size sample")
+    sub = idx[:: 4]
+    ref = _oracle_adjoint_at(out, d["w"], d["G"], sub)
+    got = gA[:, torch.from_numpy(sub).cuda()].cpu().numpy()
+    rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert rel.max() < 1e-4, rel.max()
