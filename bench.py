@@ -119,6 +119,32 @@ def _time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def _step_stats(fn, steps, torch):
+    """Per-step durations (ms) of `steps` further calls, each between its own
+    pair of HIP events on the current stream: median and minimum.  Run after
+    the timed region, so the headline mean is not affected."""
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(st)
+        fn()
+        b.record(st)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median": float(np.median(t)), "min": float(t.min()), "steps": steps}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _accuracy(P32, out, n_sample, torch, seed=0):
     """Accuracy of a result, without the oracle: residual max_k ||A d_k -
     lam_k d_k|| / ||A||_F and max |D^T D - I| over every matrix (float64 on the
@@ -175,6 +201,7 @@ def bench_precision(args, torch, ksym, synth):
     ms, wall = _time_steps(step, args.steps, args.warmup, torch)
     value = n / (ms * 1e-3)
     achieved = BYTES_3X3_F32 * n / (ms * 1e-3) / 1e9
+    per_step = _step_stats(step, min(args.steps, 50), torch)
     # refined fraction and flags, one extra untimed call with the counters
     ws = ksym.workspace()
     flags = torch.empty((n,), dtype=torch.uint8, device=dev)
@@ -182,7 +209,8 @@ def bench_precision(args, torch, ksym, synth):
     torch.cuda.synchronize()
     refined = int(ws[0].item())
     res = {"ms": ms, "wall": wall, "value": value, "achieved": achieved, "refined": refined, "n": n,
-           "opts": opts.as_dict()}
+           "opts": opts.as_dict(), "per_step": per_step,
+           "input_sha256": hashlib.sha256(np.ascontiguousarray(P32).data).hexdigest()[:16]}
     if args.accuracy:
         res["accuracy"] = _accuracy(P32, out, args.accuracy, torch)
     # reduced-output mode on the same matrices: eigenvalues only (no D, no
@@ -227,7 +255,8 @@ def bench_precision(args, torch, ksym, synth):
         dt = time.perf_counter() - t0
         res["cpu"] = {"value": m / dt, "unit": "matrices/s", "cores": th, "kind": "oracle",
                       "sample": f"first {m} matrices of this workload promoted to float64; "
-                                f"C float64 oracle of paper §4-§5, {th} host threads, {dt:.2f}s wall"}
+                                f"C float64 oracle of paper §4-§5, {th} host threads, {dt:.2f}s wall",
+                      "cpu_model": _cpu_model(), "compiler_flags": " ".join(oracle.CFLAGS)}
     return res
 
 
@@ -366,7 +395,8 @@ def main():
                        "n": r["n"], "path": "float32 angle solve, float64 cubic step, float64 check + refinement",
                        "block": r["opts"]["block"], "mats_per_lane": r["opts"]["mats_per_lane"],
                        "grid_mult": r["opts"]["grid_mult"], "tau_res": r["opts"]["tau_res"],
-                       "refined_fraction": r["refined"] / r["n"]},
+                       "refined_fraction": r["refined"] / r["n"], "input_sha256": r["input_sha256"]},
+            "ms_per_step_dist": r["per_step"],
             "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": r["achieved"] / HBM_PEAK_GBS,
                          "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
