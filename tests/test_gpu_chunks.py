@@ -114,6 +114,48 @@ def test_backward_across_chunks(ksym):
         assert torch.equal(_cols(gA, a, b), ref), (a, b)
 
 
+def test_backward_angles_and_2x2_backward_across_chunks(ksym):
+    """The 3x3 adjoint with the Euler angles' cotangent, and the 2x2 adjoint
+    with the angle's cotangent."""
+    n = CHUNK + 65
+    lam, D = _randn((3, n), 310), _randn((9, n), 311)
+    phi, gphi = _randn((3, n), 312), _randn((3, n), 313)
+    gA = ksym.eig3_backward(lam, D, None, None, phi=phi, gphi=gphi)
+    torch.cuda.synchronize()
+    for a, b in _windows(CHUNK, n):
+        ref = ksym.eig3_backward(_cols(lam, a, b), _cols(D, a, b), None, None,
+                                 phi=_cols(phi, a, b), gphi=_cols(gphi, a, b))
+        assert torch.equal(_cols(gA, a, b), ref), (a, b)
+    del lam, D, phi, gphi, gA
+    torch.cuda.empty_cache()
+    n2 = CHUNK + 17
+    lam2, D2, w2 = _randn((2, n2), 314), _randn((4, n2), 315), _randn((2, n2), 316)
+    G2, gp2 = _randn((4, n2), 317), _randn((n2,), 318)
+    gA2 = ksym.eig2_backward(lam2, D2, w2, G2, gp2)
+    torch.cuda.synchronize()
+    for a, b in _windows(CHUNK, n2):
+        ref = ksym.eig2_backward(_cols(lam2, a, b), _cols(D2, a, b), _cols(w2, a, b), _cols(G2, a, b),
+                                 _cols(gp2, a, b))
+        assert torch.equal(_cols(gA2, a, b), ref), (a, b)
+
+
+def test_compose_across_chunks(ksym):
+    """The inverse maps (lam, phi) -> A, 3x3 and 2x2."""
+    n = CHUNK + 129
+    lam, phi = _randn((3, n), 319), _randn((3, n), 320)
+    A = ksym.compose3(lam, phi)
+    torch.cuda.synchronize()
+    for a, b in _windows(CHUNK, n):
+        assert torch.equal(_cols(A, a, b), ksym.compose3(_cols(lam, a, b), _cols(phi, a, b))), (a, b)
+    del lam, phi, A
+    torch.cuda.empty_cache()
+    lam2, phi2 = _randn((2, n), 321), _randn((n,), 322)
+    A2 = ksym.compose2(lam2, phi2)
+    torch.cuda.synchronize()
+    for a, b in _windows(CHUNK, n):
+        assert torch.equal(_cols(A2, a, b), ksym.compose2(_cols(lam2, a, b), _cols(phi2, a, b))), (a, b)
+
+
 def test_plan_group_across_chunks(ksym):
     """A mixed plan whose 2x2 group is larger than one chunk (the plan splits
     it into several table entries) beside a small 3x3 group."""
