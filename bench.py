@@ -11,7 +11,9 @@ the failing matrices in float64 inside the same kernel.
 
 Printed: one JSON line with matrices/s, the roofline of the kernel (HBM,
 algorithmic bytes 84 per matrix), the CPU oracle's throughput on the host cores,
-the float64 GPU path on the same matrices, and accuracy on a sample.
+the float64 GPU path on the same matrices, accuracy on a sample, the median
+and minimum of single launches, and the throughput at two further seeds of the
+same recipe (timed step only; --seeds).
 
 Other workloads for measurement (--workload): mixed (2^26 mixed 2x2/3x3 in
 1024 groups, one persistent launch replayed from a HIP graph), grad (2^22
@@ -224,6 +226,18 @@ def bench_precision(args, torch, ksym, synth):
                        "achieved_GBs": BYTES_3X3_LAM_F32 * n / (ms_l * 1e-3) / 1e9,
                        "kernel": "k_eig3_lam (outputs lam only)", "block": opts_l.block,
                        "mats_per_lane": opts_l.mats_per_lane, "grid_mult": opts_l.grid_mult}
+    # the same recipe at further seeds (timed step only), beside the headline
+    if args.seeds > 1 and not args.n:
+        vals = [value]
+        for k in range(1, args.seeds):
+            Pk = synth.make_precision(n, seed=synth.BASE_SEED + 1 + 1000 * k)
+            A.copy_(torch.from_numpy(Pk))
+            del Pk
+            ms_k, _ = _time_steps(step, args.steps, max(20, args.warmup // 4), torch)
+            vals.append(n / (ms_k * 1e-3))
+        A.copy_(torch.from_numpy(P32))
+        res["seeds"] = {"values": vals, "min": min(vals), "max": max(vals),
+                        "seeds": [synth.BASE_SEED + 1 + 1000 * k for k in range(args.seeds)]}
     # float64 GPU path on the same matrices
     if not args.no_fp64:
         del out
@@ -355,6 +369,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--accuracy", type=int, default=1 << 16,
                     help="matrices sampled for the eigenvalue check of the accuracy report (0 = skip)")
+    ap.add_argument("--seeds", type=int, default=3,
+                    help="precision workload: also time the recipe at this many seeds in all "
+                         "(the first is the headline's), to show the spread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
@@ -415,6 +432,8 @@ def main():
             line["fp64_path"] = r["fp64"]
         if "lam_only" in r:
             line["eigenvalues_only"] = r["lam_only"]
+        if "seeds" in r:
+            line["seed_spread"] = r["seeds"]
         if "accuracy" in r:
             line["accuracy"] = r["accuracy"]
         print(json.dumps(line), flush=True)
