@@ -689,3 +689,34 @@ def test_field_workload_full_size_sampled(ksym):
     got = gA[:, torch.from_numpy(sub).cuda()].cpu().numpy()
     rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert rel.max() < 1e-4, rel.max()
+
+
+# ------------------------------------------------------- usage example -----
+def test_python_usage_example(ksym):
+    """The Python usage shown for the library: default calls, the
+    eigenvalues-only mode, the 2x2 forward, autograd through the adjoint,
+    and the inverse map back to the planes (each matrix within 1e-4 ||A||_F,
+    the float32 residual and orthogonality bounds combined)."""
+    n = 1 << 16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(401)
+    A = torch.randn(6, n, device="cuda", generator=g)
+    out = ksym.eig3(A)
+    assert out["lam"].shape == (3, n) and out["D"].shape == (9, n) and out["phi"].shape == (3, n)
+    assert out["flags"].shape == (n,)
+    lam = ksym.eig3(A, outputs=("lam",))["lam"]
+    # bitwise the full path's wherever it did not refine (flag bit 4)
+    kept = (out["flags"] & 4) == 0
+    assert torch.equal(lam[:, kept], out["lam"][:, kept])
+    B = torch.randn(3, n, device="cuda", generator=g)
+    r2 = ksym.eig2(B)
+    assert r2["lam"].shape == (2, n) and r2["D"].shape == (4, n) and r2["phi"].shape == (n,)
+    Ag = A.clone().requires_grad_()
+    lam_g, D_g = ksym.eig3_autograd(Ag)
+    (lam_g.sum() + D_g.sum()).backward()
+    assert Ag.grad.shape == (6, n) and bool(torch.isfinite(Ag.grad).all())
+    A2 = ksym.compose3(out["lam"], out["phi"])
+    P = A.double()
+    fro = torch.sqrt((P[:3] ** 2).sum(0) + 2 * (P[3:] ** 2).sum(0))
+    err = torch.sqrt(((A2.double() - P)[:3] ** 2).sum(0) + 2 * ((A2.double() - P)[3:] ** 2).sum(0))
+    assert float((err / fro).max()) <= 1e-4
