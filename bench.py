@@ -313,8 +313,9 @@ def bench_mixed(args, torch, ksym, synth):
         plan.replay(cur)
 
     ms, wall = _time_steps(step, args.steps, args.warmup, torch)
+    per_step = _step_stats(step, min(args.steps, 50), torch)
     frac2 = float(sizes[kinds == 2].sum()) / total
-    return {"ms": ms, "wall": wall, "value": total / (ms * 1e-3), "n": total,
+    return {"ms": ms, "wall": wall, "value": total / (ms * 1e-3), "n": total, "ms_per_step_dist": per_step,
             "achieved": bytes_alg / (ms * 1e-3) / 1e9, "bytes_alg": bytes_alg, "frac2x2": frac2,
             "plan": plan.info(), "refined": int(plan.ws[0].item())}
 
