@@ -27,7 +27,7 @@ TUNED_PATH = os.path.join(_HERE, "tuned.json")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_1306_6291_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_1306_6291_amd/build.py` "
         "(hipcc, gfx950).  There is no fallback implementation.")
 
 _lib = ctypes.CDLL(LIB_PATH)

@@ -1,6 +1,7 @@
 """Build the ksym HIP library (libksym.so) for gfx950 with hipcc.
 
-Usage: python -m paper_1306_6291_amd.build  (or call build_library()).
+Usage: python paper_1306_6291_amd/build.py  (or call build_library()).  Run it by
+path: importing the package itself needs the built library.
 """
 
 from __future__ import annotations

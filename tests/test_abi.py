@@ -22,7 +22,12 @@ def _declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_1306_6291_amd import build as b
+        # build.py by path: the package's __init__ refuses to import without the library
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "_ksym_build", os.path.join(ROOT, "paper_1306_6291_amd", "build.py"))
+        b = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(b)
         b.build_library()
     return ctypes.CDLL(LIB)
 
