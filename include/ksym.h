@@ -34,10 +34,13 @@
  *
  * Errors.  Calls return ksym_status and never abort or throw.  n == 0 returns
  * KSYM_OK with nothing enqueued.  n < 0, a NULL required input, a pointer not
- * aligned to its element size or an unknown dtype/path are rejected before any
- * HIP call.  Asynchronous kernel faults surface as KSYM_E_HIP from a later call
- * or from the caller's stream synchronisation.  Non-finite input entries are not
- * an error: that matrix's outputs are NaN and its flag has KSYM_FLAG_NONFINITE.
+ * aligned to its element size, an output plane (or workspace) whose bytes
+ * overlap those of an input or of another output, or an unknown dtype/path
+ * are rejected before any HIP call (KSYM_E_ARG / KSYM_E_DTYPE).  Inputs may
+ * share memory with each other.  Asynchronous kernel faults surface as
+ * KSYM_E_HIP from a later call or from the caller's stream synchronisation.
+ * Non-finite input entries are not an error: that matrix's outputs are NaN and
+ * its flag has KSYM_FLAG_NONFINITE.
  * ksym_last_error() returns text for the last non-OK status of the calling
  * thread.
  *
@@ -45,8 +48,12 @@
  * stream) without host synchronisation.  Calls are re-entrant; the library
  * keeps no mutable global state except a per-device cache of the CU count.
  *
- * Range.  Inputs are assumed finite with |A_ij| below 1e18 (float) or 1e150
- * (double); larger magnitudes may overflow intermediate squares.
+ * Range.  Any finite input is accepted: each matrix is scaled by a power of
+ * two (exactly) so that its largest entry lies in [1/2, 1) before any product
+ * is formed, and the eigenvalues are scaled back.  Only an output beyond the
+ * element type's range overflows (a 3x3 eigenvalue can reach 3 max|A_ij|,
+ * a 2x2 one 2 max|A_ij|); outputs below the smallest normal number are
+ * subnormal and lose precision gradually.
  */
 #ifndef KSYM_H
 #define KSYM_H
@@ -64,7 +71,7 @@ typedef enum { KSYM_F32 = 0, KSYM_F64 = 1 } ksym_dtype;
 
 typedef enum {
     KSYM_OK = 0,
-    KSYM_E_ARG = 1,          /* bad size, NULL required pointer, misalignment */
+    KSYM_E_ARG = 1,          /* bad size, NULL required pointer, misalignment, aliasing */
     KSYM_E_DTYPE = 2,        /* unknown dtype, or dtype/path combination not offered */
     KSYM_E_WORKSPACE = 3,    /* workspace pointer NULL or smaller than required */
     KSYM_E_HIP = 4,          /* a HIP runtime call failed; see ksym_last_error() */
@@ -311,7 +318,10 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
                              const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes);
 
 /* Enqueue the whole batch (counter reset kernel + one persistent kernel) on
-   `stream`.  No allocation, no synchronisation: safe under stream capture. */
+   `stream`.  ws: NULL, or a 4-byte aligned workspace of the *ws_bytes that
+   ksym_plan_create reported (its two counter words are zeroed, then
+   accumulated as for ksym_eig3).  No allocation, no synchronisation: safe
+   under stream capture. */
 ksym_status ksym_plan_run(ksym_plan *plan, void *ws, void *stream);
 
 /* Capture ksym_plan_run(plan, ws, stream) into a HIP graph held by the plan

@@ -32,7 +32,10 @@
  *             v and w of (5.1)-(5.2) are clamped to [0, 1].
  *   R-double: the equality case q^2 = 4 p^3 of §5 is taken when the computed
  *             eigenvalues coincide exactly or their smaller split, relative to
- *             sqrt(p), is below tau_dbl.
+ *             sqrt(p), is below tau_dbl.  That branch builds D from (5.20)-(5.25)
+ *             with the mean of the two close roots as the repeated value; the
+ *             returned eigenvalues are the roots (4.10)-(4.12) themselves,
+ *             equal where q^2 = 4 p^3 holds exactly.
  *   R-angle : angle(0) = 0, and -0 is turned into +0 before atan2.
  *   R-select: "smallest absolute difference" between phi1(1) and phi1(2) is
  *             measured on the circle (remainder modulo 2 pi); ties keep the
@@ -325,19 +328,23 @@ int ko_eig3_dbg(const double A[6], double tau_dbl, double lam[3], double Dout[9]
     }
     dbg->chosen = chosen;
     euler_to_D(p1, p2, 0.0, D);                                      /* (5.23) */
-    /* R-slots: columns (lm, lm, ls) -> slots (max, min, mid) */
+    /* R-slots: columns (lm, lm, ls) -> slots (max, min, mid).  R-double: the
+     * eigenvalues stay the roots (4.10)-(4.12); they coincide where q^2 = 4p^3
+     * holds exactly, and otherwise keep the split the cubic resolves (the
+     * mean lm serves (5.21) only).  In slot order the roots are (l1, l2, l3)
+     * in both cases: (ls, lm, lm) = (l1, l2, l3) with l3 ~ l2 and
+     * (lm, ls, lm) = (l1, l2, l3) with l1 ~ l3. */
     double E[3][3];
     if (ls > lm) {               /* (ls, lm, lm): cyclic permutation, det kept */
         for (int i = 0; i < 3; ++i) {
             E[i][0] = D[i][2]; E[i][1] = D[i][0]; E[i][2] = D[i][1];
         }
-        lam[0] = ls; lam[1] = lm; lam[2] = lm;
     } else {                     /* (lm, ls, lm): a swap, negate one column */
         for (int i = 0; i < 3; ++i) {
             E[i][0] = D[i][0]; E[i][1] = D[i][2]; E[i][2] = -D[i][1];
         }
-        lam[0] = lm; lam[1] = ls; lam[2] = lm;
     }
+    lam[0] = l1; lam[1] = l2; lam[2] = l3;
     D_to_euler(E, phi);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Dout[3 * i + j] = E[i][j];

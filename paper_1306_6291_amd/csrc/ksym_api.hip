@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <new>
 #include <string>
@@ -279,6 +280,49 @@ ksym_status check_outputs3(ksym_dtype dt, void *const lam[3], void *const D[9], 
     return KSYM_OK;
 }
 
+// Byte ranges of the planes of one call, for the aliasing test: an output
+// may not overlap an input or another output (inputs may share memory; the
+// kernels only read them).  Absent planes and empty ranges are skipped.
+struct Ranges {
+    struct R {
+        uintptr_t lo, hi;
+        bool out;
+        const char *what;
+        int idx;
+    };
+    std::vector<R> v;
+    void add(const void *p, size_t bytes, bool out, const char *what, int idx) {
+        if (p && bytes) v.push_back({(uintptr_t)p, (uintptr_t)p + bytes, out, what, idx});
+    }
+    void ins(const void *const *p, int k, size_t bytes, const char *what) {
+        if (p)
+            for (int c = 0; c < k; ++c) add(p[c], bytes, false, what, c);
+    }
+    void outs(void *const *p, int k, size_t bytes, const char *what) {
+        if (p)
+            for (int c = 0; c < k; ++c) add(p[c], bytes, true, what, c);
+    }
+    // Sweep in order of start address: a range overlaps an earlier-starting
+    // one exactly when it starts below the largest end seen so far; the
+    // largest end over outputs and over all ranges are tracked apart, so an
+    // input is tested against outputs only.
+    ksym_status check() {
+        std::sort(v.begin(), v.end(), [](const R &a, const R &b) { return a.lo < b.lo; });
+        uintptr_t end_all = 0, end_out = 0;
+        const R *arg_all = nullptr, *arg_out = nullptr;
+        for (const R &r : v) {
+            const R *hit = r.out ? (r.lo < end_all ? arg_all : nullptr) : (r.lo < end_out ? arg_out : nullptr);
+            if (hit)
+                return fail(KSYM_E_ARG, "%s[%d] overlaps %s[%d] (an output may not alias an input or another output)",
+                            r.out ? r.what : hit->what, r.out ? r.idx : hit->idx,
+                            r.out ? hit->what : r.what, r.out ? hit->idx : r.idx);
+            if (r.hi > end_all) { end_all = r.hi; arg_all = &r; }
+            if (r.out && r.hi > end_out) { end_out = r.hi; arg_out = &r; }
+        }
+        return KSYM_OK;
+    }
+};
+
 ksym_status check_ws(void *ws, size_t ws_bytes) {
     if (ws && ws_bytes < 8) return fail(KSYM_E_WORKSPACE, "workspace of %zu bytes is too small (need 8)", ws_bytes);
     if (ws && !aligned(ws, 4)) return fail(KSYM_E_WORKSPACE, "workspace must be 4-byte aligned");
@@ -344,6 +388,17 @@ ksym_status ksym_eig2(ksym_dtype dtype, int64_t n, const void *const in[3], void
     for (int c = 0; c < 4; ++c)
         if (D && !aligned(D[c], es)) return fail(KSYM_E_ARG, "D[%d] misaligned", c);
     if (!aligned(phi, es)) return fail(KSYM_E_ARG, "phi misaligned");
+    {
+        Ranges rg;
+        const size_t pb = (size_t)n * es;
+        rg.ins(in, 3, pb, "in");
+        rg.outs(lam, 2, pb, "lam");
+        rg.outs(D, 4, pb, "D");
+        rg.add(phi, pb, true, "phi", 0);
+        rg.add(flags, (size_t)n, true, "flags", 0);
+        s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     auto go = [&](auto tag) -> ksym_status {
         using T = decltype(tag);
         Eig2K<T> k = pick_eig2<T>(o.block, o.mats_per_lane);
@@ -414,6 +469,20 @@ static ksym_status eig3_common(bool aos_mode, ksym_dtype dtype, int64_t n, const
     if (s != KSYM_OK) return s;
     s = check_ws(ws, ws_bytes);
     if (s != KSYM_OK) return s;
+    {
+        Ranges rg;
+        const size_t pb = (size_t)n * es;
+        if (aos_mode) rg.add(a_aos, pb * 6, false, "a_aos", 0);
+        else rg.ins(in, 6, pb, "in");
+        rg.outs(lam, 3, pb, "lam");
+        rg.outs(D, 9, pb, "D");
+        rg.outs(phi, 3, pb, "phi");
+        rg.outs(gap, 3, pb, "gap");
+        rg.add(flags, (size_t)n, true, "flags", 0);
+        rg.add(ws, ws_bytes, true, "ws", 0);
+        s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     hipStream_t st = (hipStream_t)stream;
     if (dtype == KSYM_F32)
         return aos_mode ? eig3_impl<float, true>(n, in, a_aos, lam, D, phi, gap, flags, ws, ws_bytes, o, st)
@@ -449,6 +518,15 @@ static ksym_status compose_impl(int k, ksym_dtype dtype, int64_t n, const void *
         if (!phi[c] || !aligned(phi[c], es)) return fail(KSYM_E_ARG, "phi[%d] NULL or misaligned", c);
     for (int c = 0; c < na; ++c)
         if (!A[c] || !aligned(A[c], es)) return fail(KSYM_E_ARG, "A[%d] NULL or misaligned", c);
+    {
+        Ranges rg;
+        const size_t pb = (size_t)n * es;
+        rg.ins(lam, nl, pb, "lam");
+        rg.ins(phi, nf, pb, "phi");
+        rg.outs(A, na, pb, "A");
+        ksym_status s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     constexpr int BS = 256;
     auto go = [&](auto tag) -> ksym_status {
         using T = decltype(tag);
@@ -506,6 +584,18 @@ ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const la
         for (int c = 0; c < 4; ++c)
             if (gD[c] && !aligned(gD[c], es)) return fail(KSYM_E_ARG, "gD[%d] misaligned", c);
     if (gphi && !aligned(gphi, es)) return fail(KSYM_E_ARG, "gphi misaligned");
+    {
+        Ranges rg;
+        const size_t pb = (size_t)n * es;
+        rg.ins(lam, 2, pb, "lam");
+        rg.ins(D, 4, pb, "D");
+        rg.ins(glam, 2, pb, "glam");
+        rg.ins(gD, 4, pb, "gD");
+        rg.add(gphi, pb, false, "gphi", 0);
+        rg.outs(gA, 3, pb, "gA");
+        ksym_status s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     constexpr int BS = 256;
     auto go = [&](auto tag) -> ksym_status {
         using T = decltype(tag);
@@ -564,6 +654,20 @@ static ksym_status eig3_backward_impl(ksym_dtype dtype, int64_t n, const void *c
     if (gphi)
         for (int c = 0; c < 3; ++c)
             if (!gphi[c] || !aligned(gphi[c], es)) return fail(KSYM_E_ARG, "gphi[%d] NULL or misaligned", c);
+    {
+        Ranges rg;
+        const size_t pb = (size_t)n * es;
+        rg.ins(lam, 3, pb, "lam");
+        rg.ins(D, 9, pb, "D");
+        rg.ins(gap, 3, pb, "gap");
+        rg.ins(glam, 3, pb, "glam");
+        rg.ins(gD, 9, pb, "gD");
+        rg.ins(phi, 3, pb, "phi");
+        rg.ins(gphi, 3, pb, "gphi");
+        rg.outs(gA, 6, pb, "gA");
+        ksym_status s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     ksym_opts o;
     ksym_opts_default(dtype, &o);
     o.mats_per_lane = 1;
@@ -649,6 +753,22 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
         for (int c = 0; c < 9; ++c)
             if (!aligned(G.D[c], es)) return fail(KSYM_E_ARG, "group %d: D[%d] misaligned", g, c);
     }
+    {
+        // across all groups: no output may overlap any input or other output
+        Ranges rg;
+        for (int g = 0; g < ngroups; ++g) {
+            const ksym_group &G = groups[g];
+            const size_t pb = (size_t)G.n * es;
+            const bool k3 = G.kind == 3;
+            rg.ins(G.in, k3 ? 6 : 3, pb, "group in");
+            rg.outs(G.lam, k3 ? 3 : 2, pb, "group lam");
+            rg.outs(G.D, k3 ? 9 : 4, pb, "group D");
+            rg.outs(G.phi, k3 ? 3 : 1, pb, "group phi");
+            rg.add(G.flags, (size_t)G.n, true, "group flags", g);
+        }
+        s = rg.check();
+        if (s != KSYM_OK) return s;
+    }
     // one descriptor per KSYM_CHUNK matrices of a group (offsets stay 32-bit)
     std::vector<int64_t> tb(1, 0);
     std::vector<unsigned char> desc;
@@ -728,6 +848,7 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
 ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
     g_err.clear();
     if (!p) return fail(KSYM_E_ARG, "plan is NULL");
+    if (ws && !aligned(ws, 4)) return fail(KSYM_E_WORKSPACE, "workspace must be 4-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     if (ws) {
         hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), st, (unsigned *)ws, 2);

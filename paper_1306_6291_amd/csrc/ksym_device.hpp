@@ -639,6 +639,37 @@ __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a2
     return bad;
 }
 
+// The float64 check with Rayleigh-quotient eigenvalues: as check_fails, and
+// rq[k] receives d_k^T r_k = d_k^T B d_k - mu_k, the correction that turns
+// mu_k into the Rayleigh quotient of column k.  For a unit vector d_k at an
+// angle theta from its eigenvector the quotient is off by O(theta^2 ||A||)
+// (at most ||r_k||^2 / gap), while the cubic's root can carry an error of
+// order eps ||A||^2 / gap near a double root (arccos's slope in (4.9)).
+__device__ __forceinline__ bool check_rq64(double d1, double d2, double d3, double a12, double a13, double a23,
+                                           const double d[9], double mu1, double mu2, double mu3, double g12,
+                                           double g13, double g32, double lim2, double tau_vec, double rq[3]) {
+    const double mu[3] = {mu1, mu2, mu3};
+    double r[9];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double x = d[k], y = d[3 + k], z = d[6 + k];
+        r[k] = (d1 - mu[k]) * x + a12 * y + a13 * z;
+        r[3 + k] = a12 * x + (d2 - mu[k]) * y + a23 * z;
+        r[6 + k] = a13 * x + a23 * y + (d3 - mu[k]) * z;
+        const double n2 = r[k] * r[k] + r[3 + k] * r[3 + k] + r[6 + k] * r[6 + k];
+        bad |= !(n2 <= lim2);
+        rq[k] = x * r[k] + y * r[3 + k] + z * r[6 + k];
+    }
+    if (tau_vec > 0.0) {
+        asm volatile("");   // (a branch on the uniform threshold; see check_fails)
+        auto dot = [&](int j, int k) { return d[j] * r[k] + d[3 + j] * r[3 + k] + d[6 + j] * r[6 + k]; };
+        bad |= !(__builtin_fabs(dot(0, 1)) <= tau_vec * g12 && __builtin_fabs(dot(0, 2)) <= tau_vec * g13 &&
+                 __builtin_fabs(dot(1, 2)) <= tau_vec * g32);
+    }
+    return bad;
+}
+
 // ------------------------------------------------- float64 refinement ------
 // For matrices routed off the closed form (not in the paper): take the
 // eigenvalue lc farther from the middle one (it is separated from the other

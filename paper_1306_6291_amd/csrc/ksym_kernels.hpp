@@ -120,7 +120,10 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
         const T A12 = (T)a12, A13 = (T)a13, A22 = (T)a22, A33 = (T)a33, A23 = (T)a23;
         if (dbl) {
             // double root: labels (lam, lam, lam_s), s = cos^2 phi2 (5.21), phi3 = 0;
-            // deviations from the centre m keep s accurate when the spread is tiny
+            // deviations from the centre m keep s accurate when the spread is tiny.
+            // The mean lm of the close pair serves (5.21) only: the outputs keep
+            // the roots (4.10)-(4.12) and their gaps, which in slot order are
+            // (mu1, mu2, mu3) in both cases below
             double lm, ls;
             if (cu.g13 < cu.g32) { lm = 0.5 * (cu.mu1 + cu.mu3); ls = cu.mu2; }
             else { lm = 0.5 * (cu.mu3 + cu.mu2); ls = cu.mu1; }
@@ -130,23 +133,22 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
                                               T(1) - s, T(1), T(0), true);
             T Di[9];
             build_D(R, Di);
-            double L[3];
             if (ls > lm) {   // (ls, lm, lm): columns (3, 1, 2), even permutation
                 for (int r = 0; r < 3; ++r) {
                     o.v[O_D + 3 * r] = Di[3 * r + 2]; o.v[O_D + 3 * r + 1] = Di[3 * r]; o.v[O_D + 3 * r + 2] = Di[3 * r + 1];
                 }
-                L[0] = ls; L[1] = lm; L[2] = lm;
             } else {         // (lm, ls, lm): columns (1, 3, -2), odd permutation + sign
                 for (int r = 0; r < 3; ++r) {
                     o.v[O_D + 3 * r] = Di[3 * r]; o.v[O_D + 3 * r + 1] = Di[3 * r + 2]; o.v[O_D + 3 * r + 2] = -Di[3 * r + 1];
                 }
-                L[0] = lm; L[1] = ls; L[2] = lm;
             }
             extract_angles<T>(o.v + O_D, o.v + O_PHI);
-            for (int k = 0; k < 3; ++k) o.v[O_LAM + k] = (T)sc2(cu.m + L[k], ex);
-            o.v[O_GAP] = (T)sc2(L[0] - L[1], ex);
-            o.v[O_GAP + 1] = (T)sc2(L[0] - L[2], ex);
-            o.v[O_GAP + 2] = (T)sc2(L[2] - L[1], ex);
+            o.v[O_LAM] = (T)sc2(cu.m + cu.mu1, ex);
+            o.v[O_LAM + 1] = (T)sc2(cu.m + cu.mu2, ex);
+            o.v[O_LAM + 2] = (T)sc2(cu.m + cu.mu3, ex);
+            o.v[O_GAP] = (T)sc2(cu.g12, ex);
+            o.v[O_GAP + 1] = (T)sc2(cu.g13, ex);
+            o.v[O_GAP + 2] = (T)sc2(cu.g32, ex);
             o.flag = FLAG_DOUBLE;
         } else {
             // general branch (5.1)-(5.15), with the eigenvalue differences
@@ -280,12 +282,6 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
     const bool dbl = (cu.g13 * cu.g32 == 0.0) || split < prm.tau_dbl * cu.sp;
     const int flag = !fin ? FLAG_NONFINITE : (cu.triple ? FLAG_TRIPLE : (dbl ? FLAG_DOUBLE : FLAG_GENERAL));
     sink.flag(flag);
-    {
-        const double lam[3] = {sc2(cu.m + cu.mu1, ex), sc2(cu.m + cu.mu2, ex), sc2(cu.m + cu.mu3, ex)};
-        const double gap[3] = {sc2(cu.g12, ex), sc2(cu.g13, ex), sc2(cu.g32, ex)};
-        sink.template put_n<3>(O_LAM, lam);
-        sink.template put_n<3>(O_GAP, gap);
-    }
     bool bad = !fin || (!cu.triple && dbl);
     if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
         asm volatile("");      // (keeps the branch; see check_fails)
@@ -305,9 +301,24 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
     sink.template put_n<9>(O_D, D);
     // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
     const double fro2 = __builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
-    bad = bad || (!cu.triple && check_fails<double>(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], D, cu.mu1,
-                                                    cu.mu2, cu.mu3, cu.g12, cu.g13, cu.g32,
-                                                    prm.tau_res * prm.tau_res * fro2, prm.tau_vec));
+    double rq[3];
+    const bool cbad = check_rq64(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], D, cu.mu1, cu.mu2, cu.mu3, cu.g12,
+                                 cu.g13, cu.g32, prm.tau_res * prm.tau_res * fro2, prm.tau_vec, rq);
+    // eigenvalues as Rayleigh quotients of the checked columns (their gaps
+    // corrected alike); p = 0 keeps the exact lam = m.  A correction that
+    // would break the slot order (two eigenvalues within the residual of each
+    // other) sends the matrix to the refinement instead.
+    const double m1 = cu.triple ? cu.mu1 : cu.mu1 + rq[0], m2 = cu.triple ? cu.mu2 : cu.mu2 + rq[1],
+                 m3 = cu.triple ? cu.mu3 : cu.mu3 + rq[2];
+    const double g12 = cu.g12 + (m1 - cu.mu1) - (m2 - cu.mu2), g13 = cu.g13 + (m1 - cu.mu1) - (m3 - cu.mu3),
+                 g32 = cu.g32 + (m3 - cu.mu3) - (m2 - cu.mu2);
+    {
+        const double lam[3] = {sc2(cu.m + m1, ex), sc2(cu.m + m2, ex), sc2(cu.m + m3, ex)};
+        const double gap[3] = {sc2(fmax(g12, 0.0), ex), sc2(fmax(g13, 0.0), ex), sc2(fmax(g32, 0.0), ex)};
+        sink.template put_n<3>(O_LAM, lam);
+        sink.template put_n<3>(O_GAP, gap);
+    }
+    bad = bad || (!cu.triple && (cbad || !(g13 >= 0.0 && g32 >= 0.0)));
     refine = bad;
     return flag;
 }

@@ -261,3 +261,139 @@ def test_product_path_does_not_reference_the_oracle():
             if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt and "ksym_oracle" not in txt, fn
+
+
+def _fake(base, k, stride=1 << 16):
+    # fake device addresses, never dereferenced: each call below is rejected
+    # (or, for the control calls, would launch only after every check passes;
+    # those controls use n = 0 or an invalid dtype/option to stop first)
+    return (ctypes.c_void_p * k)(*[base + i * stride for i in range(k)])
+
+
+def test_outputs_aliasing_inputs_are_rejected(lib):
+    """An output plane whose bytes overlap an input plane or another output
+    plane is rejected with KSYM_E_ARG before any HIP call; the message names
+    both planes."""
+    P = ctypes.c_void_p
+    f = lib.ksym_eig3
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]
+    f.restype = ctypes.c_int
+    n = 1000                                   # 4000 bytes per float32 plane
+    ins = _fake(0x100000, 6)
+    lam = _fake(0x900000, 3)
+    # lam[1] starts inside in[4] (0x140000 .. 0x140fa0)
+    bad = (ctypes.c_void_p * 3)(0x900000, 0x140f00, 0x920000)
+    assert f(0, n, ins, bad, None, None, None, None, None, 0, None, None) == 1
+    msg = _err(lib)
+    assert "lam[1]" in msg and "in[4]" in msg
+    # an output overlapping another output (D[5] over lam[2])
+    D = _fake(0xa00000, 9)
+    D[5] = 0x920010
+    assert f(0, n, ins, lam, D, None, None, None, None, 0, None, None) == 1
+    assert "overlaps" in _err(lib)
+    # the flags plane (n bytes) over an input, and the workspace over an output
+    assert f(0, n, ins, lam, None, None, None, ctypes.c_void_p(0x100100), None, 0, None, None) == 1
+    assert "flags" in _err(lib)
+    assert f(0, n, ins, lam, None, None, None, None, ctypes.c_void_p(0x910000), 256, None, None) == 1
+    assert "ws" in _err(lib)
+    # control calls: block 1024 passes the option checks, but no 3x3 kernel is
+    # compiled for it, so a call that clears every argument check stops with
+    # KSYM_E_UNSUPPORTED just before its first HIP call
+    o = Opts()
+    lib.ksym_opts_default(0, ctypes.byref(o))
+    o.block = 1024
+    assert f(0, n, ins, lam, None, None, None, None, None, 0, ctypes.byref(o), None) == 5
+    # float64 planes are twice as long: lam[0] starts 4096 bytes into in[5],
+    # past a float32 plane of n elements (4000 bytes) but inside a float64 one
+    near = (ctypes.c_void_p * 3)(0x100000 + 5 * (1 << 16) + 4096, 0x980000, 0x990000)
+    assert f(0, n, ins, near, None, None, None, None, None, 0, ctypes.byref(o), None) == 5
+    lib.ksym_opts_default(1, ctypes.byref(o))
+    o.block = 1024
+    assert f(1, n, ins, near, None, None, None, None, None, 0, ctypes.byref(o), None) == 1
+    assert "lam[0]" in _err(lib) and "in[5]" in _err(lib)
+    # inputs may share memory with each other (the same plane six times)
+    same = (ctypes.c_void_p * 6)(*([0x100000] * 6))
+    lib.ksym_opts_default(0, ctypes.byref(o))
+    o.block = 1024
+    assert f(0, n, same, lam, None, None, None, None, None, 0, ctypes.byref(o), None) == 5
+
+
+def test_aliasing_rejected_in_every_entry_point(lib):
+    P = ctypes.c_void_p
+    n = 64
+    # AoS records: the n x 6 block covers 0x100000 .. +1536 bytes
+    f = lib.ksym_eig3_aos
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]
+    f.restype = ctypes.c_int
+    lam = (ctypes.c_void_p * 3)(0x900000, 0x100400, 0x920000)
+    assert f(0, n, ctypes.c_void_p(0x100000), lam, None, None, None, None, None, 0, None, None) == 1
+    assert "a_aos" in _err(lib)
+    # 2x2 forward: phi over A12
+    g = lib.ksym_eig2
+    g.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P]
+    g.restype = ctypes.c_int
+    ins = _fake(0x100000, 3)
+    assert g(0, n, ins, None, None, ctypes.c_void_p(0x120000 + 8), None, None, None) == 1
+    assert "phi" in _err(lib) and "in[2]" in _err(lib)
+    # 3x3 adjoint: gA[3] over gD[8]
+    b = lib.ksym_eig3_backward
+    b.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, P]
+    b.restype = ctypes.c_int
+    L, D, gl, gD = _fake(0x100000, 3), _fake(0x200000, 9), _fake(0x300000, 3), _fake(0x400000, 9)
+    gA = _fake(0x500000, 6)
+    gA[3] = 0x400000 + 8 * (1 << 16)
+    assert b(0, n, L, D, None, gl, gD, gA, 1e-6, None) == 1
+    assert "gA[3]" in _err(lib) and "gD[8]" in _err(lib)
+    # angle adjoint: gA over phi
+    ba = lib.ksym_eig3_backward_angles
+    ba.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_double, P]
+    ba.restype = ctypes.c_int
+    F, GP = _fake(0x600000, 3), _fake(0x700000, 3)
+    gA2 = _fake(0x600000 + 2 * (1 << 16), 6)
+    assert ba(0, n, L, D, F, None, gl, gD, GP, gA2, 1e-6, None) == 1
+    assert "phi" in _err(lib)
+    # 2x2 adjoint: gA[0] over gphi
+    b2 = lib.ksym_eig2_backward
+    b2.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, P]
+    b2.restype = ctypes.c_int
+    gA3 = (ctypes.c_void_p * 3)(0x800000, 0x810000, 0x820000)
+    assert b2(0, n, _fake(0x100000, 2), _fake(0x200000, 4), None, None, ctypes.c_void_p(0x800000), gA3,
+              1e-6, None) == 1
+    assert "gphi" in _err(lib)
+    # inverse maps: A[5] over lam[0]
+    c3 = lib.ksym_compose3
+    c3.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P]
+    c3.restype = ctypes.c_int
+    A6 = _fake(0x900000, 6)
+    A6[5] = 0x100000
+    assert c3(0, n, _fake(0x100000, 3), _fake(0x200000, 3), A6, None) == 1
+    assert "A[5]" in _err(lib) and "lam[0]" in _err(lib)
+    c2 = lib.ksym_compose2
+    c2.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, P]
+    c2.restype = ctypes.c_int
+    assert c2(0, n, _fake(0x100000, 2), ctypes.c_void_p(0x300000), _fake(0x300000, 3), None) == 1
+    assert "A[0]" in _err(lib)
+
+
+def test_plan_rejects_aliasing_across_groups(lib):
+    """A plan whose group 1 writes over group 0's input is rejected before
+    anything is allocated."""
+    import paper_1306_6291_amd as ksym
+    P = ctypes.c_void_p
+    f = lib.ksym_plan_create
+    f.argtypes = [ctypes.c_int, ctypes.c_int32, P, P, P, P]
+    f.restype = ctypes.c_int
+    arr = (ksym.Group * 2)()
+    for g, base in enumerate((0x1000000, 0x2000000)):
+        arr[g].kind = 3
+        arr[g].n = 100
+        for c in range(6):
+            arr[g].in_[c] = base + c * 0x10000
+        for c in range(3):
+            arr[g].lam[c] = base + 0x100000 + c * 0x10000
+    arr[1].lam[2] = 0x1000000 + 3 * 0x10000 + 64      # inside group 0's in[3]
+    h = ctypes.c_void_p()
+    assert f(0, 2, ctypes.cast(arr, ctypes.c_void_p), None, ctypes.byref(h), None) == 1
+    assert "overlaps" in _err(lib)
+    assert not h.value
+    lib.ksym_plan_run.argtypes = [P, P, P]

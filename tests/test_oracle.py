@@ -247,6 +247,40 @@ def test_eig3_double_root_cases():
     assert H.sorted_lam_err(P, o["lam"], np.sort(lam, axis=1).T).max() < 1e-7
 
 
+def test_eig3_near_double_keeps_the_roots():
+    """R-double: spectra whose two close eigenvalues differ by 2e-7 .. 8e-7
+    of their spread take the double branch (split below tau_dbl = 1e-6 of
+    sqrt(p)), which builds D from (5.20)-(5.25) but returns the roots
+    (4.10)-(4.12) as computed.  Against the long-double Jacobi solver they stay
+    within the trigonometric solution's error bound, eps (1 + ||A||^2/p)
+    (1 + p / (||A|| gap)) relative to ||A||_F: the literal q's cancellation
+    times arccos's slope near a double root.  The spectra are centred (p of
+    the order of ||A||_F^2), where that bound is tight, and replacing the
+    close pair by its mean -- off by half the split -- would miss it by far."""
+    rng = np.random.default_rng(29)
+    n = 4000
+    a = rng.uniform(0.5, 1, n) * rng.choice([-1, 1], n)
+    c = -a * rng.uniform(0.5, 1, n)
+    split = np.exp(rng.uniform(np.log(2e-7), np.log(8e-7), n)) * np.abs(a - c)
+    lam = np.stack([a, a + split, c], 1)
+    P = synth._sandwich(synth.haar_rotations(rng, n), lam)
+    o = oracle.eig3(P)
+    j = oracle.jacobi3(P)
+    assert np.all(o["branch"] == oracle.DOUBLE)
+    f = H.fro3(P)
+    p = H.p_invariant(P)
+    L = np.sort(j["lam"], axis=0)
+    g = np.minimum(L[1] - L[0], L[2] - L[1])
+    eps = np.finfo(np.float64).eps
+    tol = 2 * eps * (1 + f ** 2 / p) * (1 + p / (f * g))
+    err = H.sorted_lam_err(P, o["lam"], j["lam"])
+    assert np.all(err <= tol), (err / tol).max()
+    # the mean of the close pair would miss by half the split
+    assert np.all(0.5 * split / f > 10 * tol)
+    L = o["lam"]
+    assert np.all(L[0] >= L[2]) and np.all(L[2] >= L[1])
+
+
 def test_eig3_f1_or_f2_zero():
     """§5 conjecture (2) structures: |f1| = 0 (A12 = A13 = 0) or |f2| = 0
     (A22 = A33, A23 = 0) still give a correct decomposition."""

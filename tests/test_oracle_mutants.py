@@ -44,6 +44,9 @@ MUTANTS = [
     ("Euler product order", "matmul3(R1, R2, D);\n    matmul3(D, R3, D);", "matmul3(R3, R2, D);\n    matmul3(D, R1, D);"),
     ("double s wrong eigenvalue", "clamp01((a11 - ls) / (lm - ls))", "clamp01((a11 - lm) / (lm - ls))"),
     ("double slot det", "E[i][2] = -D[i][1];", "E[i][2] = D[i][1];"),
+    ("double returns the pair's mean", "    lam[0] = l1; lam[1] = l2; lam[2] = l3;\n    D_to_euler(E, phi);",
+     "    if (ls > lm) { lam[0] = ls; lam[1] = lm; lam[2] = lm; }\n"
+     "    else { lam[0] = lm; lam[1] = ls; lam[2] = lm; }\n    D_to_euler(E, phi);"),
     ("eig2 phi factor", "f = 0.5 * atan(2.0 * a12 / d);", "f = 0.5 * atan(a12 / d);"),
     ("eig2 lam2 sign", "lam[1] = 0.5 * (a11 + a22 - sg * root);", "lam[1] = 0.5 * (a11 + a22 + sg * root);"),
     ("eig2 sign(0)", "double sg = (d >= 0.0) ? 1.0 : -1.0;", "double sg = (d > 0.0) ? 1.0 : -1.0;"),
@@ -106,6 +109,19 @@ def _pins():
     od = oracle.eig3(Pd)
     if not H.residual3(Pd, od["lam"], od["D"]).max() < 1e-6 or not np.abs(H.det3(od["D"]) - 1).max() < 1e-12:
         fails.append("double")
+    # near doubles (split 2e-7 .. 8e-7 of the spread, centred spectra): the
+    # double branch keeps the roots, within the trigonometric error bound
+    a = rng.uniform(0.5, 1, 500) * rng.choice([-1, 1], 500)
+    cc = -a * rng.uniform(0.5, 1, 500)
+    sp = np.exp(rng.uniform(np.log(2e-7), np.log(8e-7), 500)) * np.abs(a - cc)
+    Pn = synth._sandwich(synth.haar_rotations(rng, 500), np.stack([a, a + sp, cc], 1))
+    on = oracle.eig3(Pn)
+    Ln = np.sort(np.linalg.eigvalsh(H.full3(Pn)).T, axis=0)
+    fn, pn = H.fro3(Pn), H.p_invariant(Pn)
+    gn = np.minimum(Ln[1] - Ln[0], Ln[2] - Ln[1])
+    tol = 2 * 2.220446049250313e-16 * (1 + fn ** 2 / pn) * (1 + pn / (fn * gn))
+    if not np.all(H.sorted_lam_err(Pn, on["lam"], Ln) <= tol):
+        fails.append("near double")
     # 2x2 golden and residual
     g2 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "eig2_exact.json")))["cases"]
     P2 = np.array([c["a"] for c in g2], dtype=np.float64).T
