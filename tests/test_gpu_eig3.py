@@ -85,7 +85,13 @@ def test_plain_f64_ragged_sizes_and_launch_shapes(ksym):
 
 def test_f64_double_and_triple_branches(ksym):
     """Exact double and triple spectra: the plain path takes the paper's
-    special cases (5.20)-(5.25) and p = 0; slots, det and residual hold."""
+    special cases (5.20)-(5.25) and p = 0; slots, det and residual hold.
+    Eigenvalues: the plain path returns the roots (4.10)-(4.12) in the double
+    branch (reading R-double), which at an exact double root carry the
+    arccos step's sqrt(eps) error (q^2 = 4 p^3 holds only up to rounding), as
+    the oracle's do with their own rounding; the pair still sums exactly to
+    the trace.  The checked path's Rayleigh-quotient eigenvalues meet the exact
+    spectrum to 1e-14."""
     rng = np.random.default_rng(91)
     n = 2000
     a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
@@ -99,10 +105,16 @@ def test_f64_double_and_triple_branches(ksym):
     Pt[0:3] = np.linspace(-2, 2, 64)
     for Q in (P, P2):
         ref = oracle.eig3(Q)
+        exact = Q[0:3]
         for path in (ksym.PATH_FP64_PLAIN, ksym.PATH_FP64_FIXUP):
             g = _run(ksym, Q, torch.float64, path=path)
             assert np.all(g["flags"] & 1), path
-            assert H.sorted_lam_err(Q, g["lam"], ref["lam"]).max() < 1e-14
+            if path == ksym.PATH_FP64_PLAIN:
+                assert H.sorted_lam_err(Q, g["lam"], exact).max() < 1e-7
+                assert H.sorted_lam_err(Q, g["lam"], ref["lam"]).max() < 1e-7
+                assert np.abs(g["lam"].sum(0) - exact.sum(0)).max() < 1e-14
+            else:
+                assert H.sorted_lam_err(Q, g["lam"], exact).max() < 1e-14
             assert H.residual3(Q, g["lam"], g["D"]).max() < (1e-7 if path == ksym.PATH_FP64_PLAIN else 1e-14)
             assert np.abs(H.det3(g["D"]) - 1).max() < 1e-14
             L = g["lam"]
