@@ -318,15 +318,16 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
                              const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes);
 
 /* Enqueue the whole batch (counter reset kernel + one persistent kernel) on
-   `stream`.  ws: NULL, or a 4-byte aligned workspace of the *ws_bytes that
-   ksym_plan_create reported (its two counter words are zeroed, then
-   accumulated as for ksym_eig3).  No allocation, no synchronisation: safe
-   under stream capture. */
-ksym_status ksym_plan_run(ksym_plan *plan, void *ws, void *stream);
+   `stream`.  ws: NULL, or a 4-byte aligned workspace of ws_bytes >= the
+   *ws_bytes that ksym_plan_create reported (its two counter words are
+   zeroed, then accumulated as for ksym_eig3); a smaller or misaligned
+   workspace gives KSYM_E_WORKSPACE.  No allocation, no synchronisation:
+   safe under stream capture. */
+ksym_status ksym_plan_run(ksym_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
-/* Capture ksym_plan_run(plan, ws, stream) into a HIP graph held by the plan
-   (replacing any previous one).  Not itself capturable. */
-ksym_status ksym_plan_capture(ksym_plan *plan, void *ws, void *stream);
+/* Capture ksym_plan_run(plan, ws, ws_bytes, stream) into a HIP graph held by
+   the plan (replacing any previous one).  Not itself capturable. */
+ksym_status ksym_plan_capture(ksym_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /* Launch the captured graph on `stream`. */
 ksym_status ksym_plan_replay(ksym_plan *plan, void *stream);

@@ -95,8 +95,8 @@ _lib.ksym_compose2.argtypes = [ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P]
 _lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
                                   ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_size_t)]
-_lib.ksym_plan_run.argtypes = [_P, _P, _P]
-_lib.ksym_plan_capture.argtypes = [_P, _P, _P]
+_lib.ksym_plan_run.argtypes = [_P, _P, ctypes.c_size_t, _P]
+_lib.ksym_plan_capture.argtypes = [_P, _P, ctypes.c_size_t, _P]
 _lib.ksym_plan_replay.argtypes = [_P, _P]
 _lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
 _lib.ksym_plan_destroy.argtypes = [_P]
@@ -417,6 +417,36 @@ def eig2_autograd(planes, eps_rel=None, opts=None):
 
 
 # ------------------------------------------------------- mixed plans --------
+def _group_array(groups):
+    """ctypes array of ksym_group for [(kind, planes, out), ...] (see Plan)."""
+    arr = (Group * len(groups))()
+    for g, (kind, planes, out) in enumerate(groups):
+        k = 3 if kind == 3 else 2
+        ptrs, n, t = _rows(planes, 6 if k == 3 else 3)
+        G = arr[g]
+        G.kind = k
+        G.n = n
+        for c, p in enumerate(ptrs):
+            G.in_[c] = p
+        nl, nd = (3, 9) if k == 3 else (2, 4)
+        if out.get("lam") is not None:
+            for c, p in enumerate(_rows(out["lam"], nl)[0]):
+                G.lam[c] = p
+        if out.get("D") is not None:
+            for c, p in enumerate(_rows(out["D"], nd)[0]):
+                G.D[c] = p
+        if out.get("phi") is not None:
+            ph = out["phi"]
+            if k == 3:
+                for c, p in enumerate(_rows(ph, 3)[0]):
+                    G.phi[c] = p
+            else:
+                G.phi[0] = ph.data_ptr()
+        if out.get("flags") is not None:
+            G.flags = out["flags"].data_ptr()
+    return arr
+
+
 class Plan:
     """Mixed persistent batch of 2x2 and 3x3 groups (one kernel launch).
     groups: list of (kind, planes, out) with planes a (3|6, n) tensor and out a
@@ -427,33 +457,8 @@ class Plan:
         dt = _dt(ref)
         self.dtype = dt
         self.device = ref.device
-        self._keep = []
-        arr = (Group * len(groups))()
-        for g, (kind, planes, out) in enumerate(groups):
-            k = 3 if kind == 3 else 2
-            ptrs, n, t = _rows(planes, 6 if k == 3 else 3)
-            G = arr[g]
-            G.kind = k
-            G.n = n
-            for c, p in enumerate(ptrs):
-                G.in_[c] = p
-            nl, nd, nph = (3, 9, 3) if k == 3 else (2, 4, 1)
-            if out.get("lam") is not None:
-                for c, p in enumerate(_rows(out["lam"], nl)[0]):
-                    G.lam[c] = p
-            if out.get("D") is not None:
-                for c, p in enumerate(_rows(out["D"], nd)[0]):
-                    G.D[c] = p
-            if out.get("phi") is not None:
-                ph = out["phi"]
-                if k == 3:
-                    for c, p in enumerate(_rows(ph, 3)[0]):
-                        G.phi[c] = p
-                else:
-                    G.phi[0] = ph.data_ptr()
-            if out.get("flags") is not None:
-                G.flags = out["flags"].data_ptr()
-            self._keep.append((planes, out))
+        self._keep = [(planes, out) for _, planes, out in groups]
+        arr = _group_array(groups)
         o = _opts(dt, opts, _kind="mixed")
         self.opts = o
         h = ctypes.c_void_p()
@@ -469,16 +474,19 @@ class Plan:
         _check(_lib.ksym_plan_info(self._h, ctypes.byref(t), ctypes.byref(g)))
         return {"tiles": t.value, "grid": g.value}
 
+    def _ws_bytes(self):
+        return self.ws.numel() * self.ws.element_size()
+
     def _st(self, stream):
         if stream is None:
             return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
         return ctypes.c_void_p(stream.cuda_stream)
 
     def run(self, stream=None):
-        _check(_lib.ksym_plan_run(self._h, self.ws.data_ptr(), self._st(stream)))
+        _check(_lib.ksym_plan_run(self._h, self.ws.data_ptr(), self._ws_bytes(), self._st(stream)))
 
     def capture(self, stream):
-        _check(_lib.ksym_plan_capture(self._h, self.ws.data_ptr(), self._st(stream)))
+        _check(_lib.ksym_plan_capture(self._h, self.ws.data_ptr(), self._ws_bytes(), self._st(stream)))
 
     def replay(self, stream=None):
         _check(_lib.ksym_plan_replay(self._h, self._st(stream)))
@@ -493,3 +501,4 @@ class Plan:
             self.close()
         except Exception:
             pass
+

@@ -283,16 +283,45 @@ ksym_status check_outputs3(ksym_dtype dt, void *const lam[3], void *const D[9], 
 // Byte ranges of the planes of one call, for the aliasing test: an output
 // may not overlap an input or another output (inputs may share memory; the
 // kernels only read them).  Absent planes and empty ranges are skipped.
-struct Ranges {
-    struct R {
-        uintptr_t lo, hi;
-        bool out;
-        const char *what;
-        int idx;
-    };
-    std::vector<R> v;
+struct Range {
+    uintptr_t lo, hi;
+    bool out;
+    const char *what;
+    int idx;
+};
+
+// Sweep in order of start address (sorted in place): a range overlaps an
+// earlier-starting one exactly when it starts below the largest end seen so
+// far; the largest end over outputs and over all ranges are tracked apart,
+// so an input is tested against outputs only.
+ksym_status check_ranges(Range *v, size_t n) {
+    std::sort(v, v + n, [](const Range &a, const Range &b) { return a.lo < b.lo; });
+    uintptr_t end_all = 0, end_out = 0;
+    const Range *arg_all = nullptr, *arg_out = nullptr;
+    for (size_t i = 0; i < n; ++i) {
+        const Range &r = v[i];
+        const Range *hit = r.out ? (r.lo < end_all ? arg_all : nullptr) : (r.lo < end_out ? arg_out : nullptr);
+        if (hit)
+            return fail(KSYM_E_ARG, "%s[%d] overlaps %s[%d] (an output may not alias an input or another output)",
+                        r.out ? r.what : hit->what, r.out ? r.idx : hit->idx,
+                        r.out ? hit->what : r.what, r.out ? hit->idx : r.idx);
+        if (r.hi > end_all) { end_all = r.hi; arg_all = &r; }
+        if (r.out && r.hi > end_out) { end_out = r.hi; arg_out = &r; }
+    }
+    return KSYM_OK;
+}
+
+// The ranges of one call, in a heap vector.
+struct VecStore {
+    std::vector<Range> v;
+    void push(const Range &r) { v.push_back(r); }
+    Range *data() { return v.data(); }
+    size_t size() const { return v.size(); }
+};
+template <typename Store> struct RangeSet {
+    Store st;
     void add(const void *p, size_t bytes, bool out, const char *what, int idx) {
-        if (p && bytes) v.push_back({(uintptr_t)p, (uintptr_t)p + bytes, out, what, idx});
+        if (p && bytes) st.push({(uintptr_t)p, (uintptr_t)p + bytes, out, what, idx});
     }
     void ins(const void *const *p, int k, size_t bytes, const char *what) {
         if (p)
@@ -302,26 +331,9 @@ struct Ranges {
         if (p)
             for (int c = 0; c < k; ++c) add(p[c], bytes, true, what, c);
     }
-    // Sweep in order of start address: a range overlaps an earlier-starting
-    // one exactly when it starts below the largest end seen so far; the
-    // largest end over outputs and over all ranges are tracked apart, so an
-    // input is tested against outputs only.
-    ksym_status check() {
-        std::sort(v.begin(), v.end(), [](const R &a, const R &b) { return a.lo < b.lo; });
-        uintptr_t end_all = 0, end_out = 0;
-        const R *arg_all = nullptr, *arg_out = nullptr;
-        for (const R &r : v) {
-            const R *hit = r.out ? (r.lo < end_all ? arg_all : nullptr) : (r.lo < end_out ? arg_out : nullptr);
-            if (hit)
-                return fail(KSYM_E_ARG, "%s[%d] overlaps %s[%d] (an output may not alias an input or another output)",
-                            r.out ? r.what : hit->what, r.out ? r.idx : hit->idx,
-                            r.out ? hit->what : r.what, r.out ? hit->idx : r.idx);
-            if (r.hi > end_all) { end_all = r.hi; arg_all = &r; }
-            if (r.out && r.hi > end_out) { end_out = r.hi; arg_out = &r; }
-        }
-        return KSYM_OK;
-    }
+    ksym_status check() { return check_ranges(st.data(), st.size()); }
 };
+using Ranges = RangeSet<VecStore>;
 
 ksym_status check_ws(void *ws, size_t ws_bytes) {
     if (ws && ws_bytes < 8) return fail(KSYM_E_WORKSPACE, "workspace of %zu bytes is too small (need 8)", ws_bytes);
@@ -722,28 +734,21 @@ ksym_status ksym_eig3_backward_angles(ksym_dtype dtype, int64_t n, const void *c
 }
 
 // ------------------------------------------------------------- plans ------
-ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
-                             const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes) {
-    g_err.clear();
-    if (!plan) return fail(KSYM_E_ARG, "plan is NULL");
-    *plan = nullptr;
-    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
-    if (ngroups <= 0 || !groups) return fail(KSYM_E_ARG, "need ngroups > 0 and a group array");
-    ksym_opts o;
-    ksym_status s = resolve_opts(dtype, opts, &o);
-    if (s != KSYM_OK) return s;
-    if (dtype == KSYM_F32) o.path = KSYM_PATH_FP32_FIXUP;
-    else o.path = KSYM_PATH_FP64_FIXUP;
+}  // extern "C"
+
+namespace {
+
+// Group checks shared by ksym_plan_create and ksym_mixed_run_noalloc: kinds,
+// sizes, alignment, and no output overlapping any input or other output
+// across all groups (rg collects the ranges).
+template <typename Store>
+ksym_status check_groups(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups, RangeSet<Store> &rg) {
     const size_t es = esize(dtype);
-    const int tile = 64 * o.mats_per_lane;   // one wave tile
-    const bool f32 = dtype == KSYM_F32;
-    if (f32 ? !pick_mixed<float>(o.block, o.mats_per_lane) : !pick_mixed<double>(o.block, o.mats_per_lane))
-        return fail(KSYM_E_UNSUPPORTED, "no compiled mixed kernel for block %d, mats_per_lane %d",
-                    o.block, o.mats_per_lane);
     for (int g = 0; g < ngroups; ++g) {
         const ksym_group &G = groups[g];
         if (G.kind != 2 && G.kind != 3) return fail(KSYM_E_ARG, "group %d: kind must be 2 or 3", g);
         if (G.n < 0) return fail(KSYM_E_ARG, "group %d: n < 0", g);
+        if (G.n >= ((int64_t)1 << 40)) return fail(KSYM_E_ARG, "group %d: n too large", g);
         const int nin = G.kind == 3 ? 6 : 3;
         if (G.n > 0)
             for (int c = 0; c < nin; ++c)
@@ -753,68 +758,164 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
         for (int c = 0; c < 9; ++c)
             if (!aligned(G.D[c], es)) return fail(KSYM_E_ARG, "group %d: D[%d] misaligned", g, c);
     }
-    {
-        // across all groups: no output may overlap any input or other output
-        Ranges rg;
-        for (int g = 0; g < ngroups; ++g) {
-            const ksym_group &G = groups[g];
-            const size_t pb = (size_t)G.n * es;
-            const bool k3 = G.kind == 3;
-            rg.ins(G.in, k3 ? 6 : 3, pb, "group in");
-            rg.outs(G.lam, k3 ? 3 : 2, pb, "group lam");
-            rg.outs(G.D, k3 ? 9 : 4, pb, "group D");
-            rg.outs(G.phi, k3 ? 3 : 1, pb, "group phi");
-            rg.add(G.flags, (size_t)G.n, true, "group flags", g);
-        }
-        s = rg.check();
-        if (s != KSYM_OK) return s;
+    for (int g = 0; g < ngroups; ++g) {
+        const ksym_group &G = groups[g];
+        const size_t pb = (size_t)G.n * es;
+        const bool k3 = G.kind == 3;
+        rg.ins(G.in, k3 ? 6 : 3, pb, "group in");
+        rg.outs(G.lam, k3 ? 3 : 2, pb, "group lam");
+        rg.outs(G.D, k3 ? 9 : 4, pb, "group D");
+        rg.outs(G.phi, k3 ? 3 : 1, pb, "group phi");
+        rg.add(G.flags, (size_t)G.n, true, "group flags", g);
     }
-    // one descriptor per KSYM_CHUNK matrices of a group (offsets stay 32-bit)
-    std::vector<int64_t> tb(1, 0);
-    std::vector<unsigned char> desc;
-    const size_t dsz = f32 ? sizeof(GroupDesc<float>) : sizeof(GroupDesc<double>);
+    return rg.check();
+}
+
+// Planes a group of kind 2 or 3 uses, for the range count of the checks.
+constexpr int kGroupRanges = 6 + 3 + 9 + 3 + 1;
+
+// The descriptor of matrices [start, start + len) of group G (every plane
+// pointer advanced by start; a descriptor covers at most KSYM_CHUNK).
+template <typename T> GroupDesc<T> make_desc(const ksym_group &G, int64_t start, int64_t len) {
+    GroupDesc<T> d;
+    memset(&d, 0, sizeof d);
+    d.n = len;
+    d.kind = G.kind;
+    const int nin = G.kind == 3 ? 6 : 3;
+    const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
+    auto adv = [&](const void *q) { return q ? (T *)q + start : nullptr; };
+    for (int c = 0; c < nin; ++c) d.p3.in[c] = adv(G.in[c]);
+    for (int c = 0; c < nl; ++c) d.p3.out[O_LAM + c] = adv(G.lam[c]);
+    for (int c = 0; c < nd; ++c) d.p3.out[O_D + c] = adv(G.D[c]);
+    for (int c = 0; c < np; ++c) d.p3.out[O_PHI + c] = adv(G.phi[c]);
+    d.p3.flags = G.flags ? G.flags + start : nullptr;
+    return d;
+}
+
+// Calls emit(group, start, len, first_tile) for every descriptor of the
+// batch in order (one per KSYM_CHUNK matrices of a group, one for an empty
+// group) and returns the total number of wave tiles of `tile` matrices.
+template <typename F> int64_t for_each_desc(int32_t ngroups, const ksym_group *groups, int tile, F emit) {
+    int64_t tiles = 0;
     for (int g = 0; g < ngroups; ++g) {
         const ksym_group &G = groups[g];
         for (int64_t start = 0; start == 0 || start < G.n; start += KSYM_CHUNK) {
             const int64_t len = G.n - start < KSYM_CHUNK ? G.n - start : KSYM_CHUNK;
-            auto fill = [&](auto tag) {
-                using T = decltype(tag);
-                GroupDesc<T> d;
-                memset(&d, 0, sizeof d);
-                d.n = len;
-                d.kind = G.kind;
-                const int nin = G.kind == 3 ? 6 : 3;
-                const int nl = G.kind == 3 ? 3 : 2, nd = G.kind == 3 ? 9 : 4, np = G.kind == 3 ? 3 : 1;
-                auto adv = [&](const void *q) { return q ? (T *)q + start : nullptr; };
-                for (int c = 0; c < nin; ++c) d.p3.in[c] = adv(G.in[c]);
-                for (int c = 0; c < nl; ++c) d.p3.out[O_LAM + c] = adv(G.lam[c]);
-                for (int c = 0; c < nd; ++c) d.p3.out[O_D + c] = adv(G.D[c]);
-                for (int c = 0; c < np; ++c) d.p3.out[O_PHI + c] = adv(G.phi[c]);
-                d.p3.flags = G.flags ? G.flags + start : nullptr;
-                const size_t at = desc.size();
-                desc.resize(at + sizeof d);
-                memcpy(desc.data() + at, &d, sizeof d);
-            };
-            if (f32) fill(float()); else fill(double());
-            tb.push_back(tb.back() + (len + tile - 1) / tile);
+            emit(g, start, len, tiles);
+            tiles += (len + tile - 1) / tile;
         }
     }
-    const int64_t ndesc = (int64_t)(desc.size() / dsz);
+    return tiles;
+}
+
+// Mixed-batch options: the checked path of the dtype and a compiled shape.
+ksym_status mixed_opts(ksym_dtype dtype, const ksym_opts *opts, ksym_opts *o) {
+    ksym_status s = resolve_opts(dtype, opts, o);
+    if (s != KSYM_OK) return s;
+    o->path = dtype == KSYM_F32 ? KSYM_PATH_FP32_FIXUP : KSYM_PATH_FP64_FIXUP;
+    const bool ok = dtype == KSYM_F32 ? pick_mixed<float>(o->block, o->mats_per_lane) != nullptr
+                                      : pick_mixed<double>(o->block, o->mats_per_lane) != nullptr;
+    if (!ok)
+        return fail(KSYM_E_UNSUPPORTED, "no compiled mixed kernel for block %d, mats_per_lane %d", o->block,
+                    o->mats_per_lane);
+    return KSYM_OK;
+}
+
+// Workgroups of the mixed launch: grid_mult per CU, at most one per
+// block/64 tiles.
+ksym_status mixed_grid(const ksym_opts &o, int64_t ntiles, int *grid) {
+    int cus = 0;
+    ksym_status s = cu_count(&cus);
+    if (s != KSYM_OK) return s;
+    int64_t g = (int64_t)o.grid_mult * cus;
+    const int64_t need = (ntiles + o.block / 64 - 1) / (o.block / 64);
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    *grid = (int)g;
+    return KSYM_OK;
+}
+
+// Counter reset and the persistent mixed kernel over descriptor and tile
+// tables already in device memory.
+ksym_status launch_mixed(ksym_dtype dtype, const ksym_opts &o, const void *d_groups, const TileInfo *d_tiles,
+                         int32_t ndesc, int64_t ntiles, int grid, void *ws, hipStream_t st) {
+    if (ws) {
+        hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), st, (unsigned *)ws, 2);
+        if (e != hipSuccess) return hip_fail(e, "launch k_zero_u32");
+    }
+    if (ntiles == 0) return KSYM_OK;
+    auto go = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        MixedArgs<T> a;
+        memset(&a, 0, sizeof a);
+        a.groups = (const GroupDesc<T> *)d_groups;
+        a.tiles = d_tiles;
+        a.ngroups = ndesc;
+        a.ntiles = ntiles;
+        a.prm.n = 0;
+        a.prm.tau_gap = o.tau_gap;
+        a.prm.tau_res = o.tau_res;
+        a.prm.tau_vec = o.tau_vec;
+        a.prm.tau_dbl = o.tau_dbl;
+        a.prm.drain_tiles = o.drain_tiles;
+        a.prm.counters = (unsigned *)ws;
+        finish_params(a.prm);
+        MixK<T> k = pick_mixed<T>(o.block, o.mats_per_lane);
+        hipError_t e = launch(k, dim3(grid), dim3(o.block), st, a);
+        if (e != hipSuccess) return hip_fail(e, "launch k_mixed");
+        return KSYM_OK;
+    };
+    return dtype == KSYM_F32 ? go(float()) : go(double());
+}
+
+}  // namespace
+
+extern "C" {
+
+ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
+                             const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes) {
+    g_err.clear();
+    if (!plan) return fail(KSYM_E_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (ngroups <= 0 || !groups) return fail(KSYM_E_ARG, "need ngroups > 0 and a group array");
+    ksym_opts o;
+    ksym_status s = mixed_opts(dtype, opts, &o);
+    if (s != KSYM_OK) return s;
+    {
+        Ranges rg;
+        s = check_groups(dtype, ngroups, groups, rg);
+        if (s != KSYM_OK) return s;
+    }
+    const int tile = 64 * o.mats_per_lane;   // one wave tile
+    const bool f32 = dtype == KSYM_F32;
+    // one descriptor per KSYM_CHUNK matrices of a group (offsets stay 32-bit)
+    std::vector<int64_t> tb;
+    std::vector<unsigned char> desc;
+    const int64_t ntiles = for_each_desc(ngroups, groups, tile, [&](int g, int64_t start, int64_t len, int64_t first) {
+        const size_t at = desc.size();
+        if (f32) {
+            const GroupDesc<float> d = make_desc<float>(groups[g], start, len);
+            desc.resize(at + sizeof d);
+            memcpy(desc.data() + at, &d, sizeof d);
+        } else {
+            const GroupDesc<double> d = make_desc<double>(groups[g], start, len);
+            desc.resize(at + sizeof d);
+            memcpy(desc.data() + at, &d, sizeof d);
+        }
+        tb.push_back(first);
+    });
+    tb.push_back(ntiles);
+    const int64_t ndesc = (int64_t)tb.size() - 1;
     if (ndesc >= (1 << 24)) return fail(KSYM_E_ARG, "too many groups (%lld descriptors)", (long long)ndesc);
     ksym_plan *p = new (std::nothrow) ksym_plan();
     if (!p) return fail(KSYM_E_ARG, "out of host memory");
     p->dtype = dtype;
     p->opts = o;
     p->ngroups = (int32_t)ndesc;
-    p->ntiles = tb.back();
-    int cus = 0;
-    s = cu_count(&cus);
+    p->ntiles = ntiles;
+    s = mixed_grid(o, ntiles, &p->grid);
     if (s != KSYM_OK) { delete p; return s; }
-    int64_t grid = (int64_t)o.grid_mult * cus;
-    const int64_t need = (p->ntiles + o.block / 64 - 1) / (o.block / 64);   // workgroups of block/64 waves
-    if (grid > need) grid = need;
-    if (grid < 1) grid = 1;
-    p->grid = (int)grid;
     // one (descriptor, first-matrix offset) entry per wave tile
     std::vector<TileInfo> ti;
     try {
@@ -845,50 +946,27 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
     return KSYM_OK;
 }
 
-ksym_status ksym_plan_run(ksym_plan *p, void *ws, void *stream) {
+ksym_status ksym_plan_run(ksym_plan *p, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     if (!p) return fail(KSYM_E_ARG, "plan is NULL");
-    if (ws && !aligned(ws, 4)) return fail(KSYM_E_WORKSPACE, "workspace must be 4-byte aligned");
-    hipStream_t st = (hipStream_t)stream;
-    if (ws) {
-        hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), st, (unsigned *)ws, 2);
-        if (e != hipSuccess) return hip_fail(e, "launch k_zero_u32");
-    }
-    if (p->ntiles == 0) return KSYM_OK;
-    auto go = [&](auto tag) -> ksym_status {
-        using T = decltype(tag);
-        MixedArgs<T> a;
-        memset(&a, 0, sizeof a);
-        a.groups = (const GroupDesc<T> *)p->d_groups;
-        a.tiles = p->d_tiles;
-        a.ngroups = p->ngroups;
-        a.ntiles = p->ntiles;
-        a.prm.n = 0;
-        a.prm.tau_gap = p->opts.tau_gap;
-        a.prm.tau_res = p->opts.tau_res;
-        a.prm.tau_vec = p->opts.tau_vec;
-        a.prm.tau_dbl = p->opts.tau_dbl;
-        a.prm.drain_tiles = p->opts.drain_tiles;
-        a.prm.counters = (unsigned *)ws;
-        finish_params(a.prm);
-        MixK<T> k = pick_mixed<T>(p->opts.block, p->opts.mats_per_lane);
-        hipError_t e = launch(k, dim3(p->grid), dim3(p->opts.block), st, a);
-        if (e != hipSuccess) return hip_fail(e, "launch k_mixed");
-        return KSYM_OK;
-    };
-    return p->dtype == KSYM_F32 ? go(float()) : go(double());
+    ksym_status s = check_ws(ws, ws_bytes);
+    if (s != KSYM_OK) return s;
+    return launch_mixed(p->dtype, p->opts, p->d_groups, p->d_tiles, p->ngroups, p->ntiles, p->grid, ws,
+                        (hipStream_t)stream);
 }
 
-ksym_status ksym_plan_capture(ksym_plan *p, void *ws, void *stream) {
+ksym_status ksym_plan_capture(ksym_plan *p, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     if (!p) return fail(KSYM_E_ARG, "plan is NULL");
     hipStream_t st = (hipStream_t)stream;
     if (!st) return fail(KSYM_E_ARG, "capture needs a non-default stream");
+    ksym_status s = check_ws(ws, ws_bytes);
+    if (s != KSYM_OK) return s;
     if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    ksym_status s = ksym_plan_run(p, ws, stream);
+    s = ksym_plan_run(p, ws, ws_bytes, stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(st, &g);
     if (s != KSYM_OK) { if (g) (void)hipGraphDestroy(g); return s; }
@@ -925,5 +1003,6 @@ void ksym_plan_destroy(ksym_plan *p) {
     if (p->d_groups) (void)hipFree(p->d_groups);
     delete p;
 }
+
 
 }  // extern "C"

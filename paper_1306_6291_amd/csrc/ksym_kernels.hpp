@@ -1280,4 +1280,5 @@ __global__ void k_zero_u32(unsigned *p, int n) {
     if (i < n) p[i] = 0u;
 }
 
+
 }  // namespace ksym

@@ -242,8 +242,10 @@ def test_plan_argument_errors(lib):
     assert f(0, 2, ctypes.cast(arr, ctypes.c_void_p), None, ctypes.byref(h), None) == 1
     lib.ksym_plan_destroy.argtypes = [P]
     lib.ksym_plan_destroy(None)   # no-op
-    lib.ksym_plan_run.argtypes = [P, P, P]
-    assert lib.ksym_plan_run(None, None, None) == 1
+    lib.ksym_plan_run.argtypes = [P, P, ctypes.c_size_t, P]
+    assert lib.ksym_plan_run(None, None, 0, None) == 1
+    lib.ksym_plan_capture.argtypes = [P, P, ctypes.c_size_t, P]
+    assert lib.ksym_plan_capture(None, None, 0, None) == 1
     lib.ksym_plan_replay.argtypes = [P, P]
     assert lib.ksym_plan_replay(None, None) == 1
 
@@ -396,4 +398,4 @@ def test_plan_rejects_aliasing_across_groups(lib):
     assert f(0, 2, ctypes.cast(arr, ctypes.c_void_p), None, ctypes.byref(h), None) == 1
     assert "overlaps" in _err(lib)
     assert not h.value
-    lib.ksym_plan_run.argtypes = [P, P, P]
+
