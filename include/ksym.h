@@ -12,8 +12,9 @@
  * ---------------------------------------------------------------- conventions
  * Memory.  Every array argument is a DEVICE pointer owned by the caller.  The
  * library never allocates inside ksym_eig2, ksym_eig3, ksym_eig3_aos,
- * ksym_eig3_backward or ksym_plan_run / ksym_plan_replay.  ksym_plan_create
- * allocates one small descriptor buffer, freed by ksym_plan_destroy.
+ * ksym_eig3_backward, ksym_plan_run / ksym_plan_replay or
+ * ksym_mixed_run_noalloc.  ksym_plan_create allocates one small descriptor
+ * buffer, freed by ksym_plan_destroy.
  *
  * Layout.  Structure of arrays: one contiguous plane of n elements per
  * quantity, element type float (KSYM_F32) or double (KSYM_F64), each plane
@@ -337,6 +338,33 @@ ksym_status ksym_plan_info(const ksym_plan *plan, int64_t *tiles, int32_t *grid)
 
 /* Free the plan, its descriptor table and its graph.  NULL is a no-op. */
 void ksym_plan_destroy(ksym_plan *plan);
+
+/*
+ * Mixed batch without a plan, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Runs the same kernels, and gives bitwise the same outputs and
+ * counters, as ksym_plan_create + ksym_plan_run on the same groups and
+ * options, but allocates nothing: the descriptor and tile tables go into a
+ * fixed device array of the library (about 17.8 MiB, one per GPU the library
+ * runs on, held until the process ends), written on `stream` by small
+ * kernels before the batch kernel.  Limits: at most KSYM_NOALLOC_MAX_GROUPS
+ * groups, KSYM_NOALLOC_MAX_DESCRIPTORS chunks of at most 2^28 matrices (a
+ * group counts one chunk per started 2^28 matrices, an empty group one), and
+ * KSYM_NOALLOC_MAX_TILES wave tiles of 64 * mats_per_lane matrices (a group
+ * rounds up to whole tiles; 2^21 tiles hold 2^27 matrices at one matrix per
+ * lane).  Beyond them the call returns KSYM_E_ARG before any HIP call.
+ * Arguments, checks and ws as for ksym_plan_create and ksym_plan_run.  Every
+ * call on one GPU uses that GPU's one array and keeps the last call's tables
+ * there: calls that overlap on one GPU (on different streams, or from
+ * several threads) race and must be ordered by the caller; calls on one
+ * stream are ordered by it.  The first call on a device looks up the array's
+ * address there (hipGetSymbolAddress).
+ */
+#define KSYM_NOALLOC_MAX_GROUPS 4096
+#define KSYM_NOALLOC_MAX_DESCRIPTORS 8192
+#define KSYM_NOALLOC_MAX_TILES 2097152
+ksym_status ksym_mixed_run_noalloc(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
+                                   const ksym_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -97,6 +97,8 @@ _lib.ksym_plan_create.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(G
                                   ctypes.POINTER(ctypes.c_size_t)]
 _lib.ksym_plan_run.argtypes = [_P, _P, ctypes.c_size_t, _P]
 _lib.ksym_plan_capture.argtypes = [_P, _P, ctypes.c_size_t, _P]
+_lib.ksym_mixed_run_noalloc.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Group),
+                                        ctypes.POINTER(Opts), _P, ctypes.c_size_t, _P]
 _lib.ksym_plan_replay.argtypes = [_P, _P]
 _lib.ksym_plan_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
 _lib.ksym_plan_destroy.argtypes = [_P]
@@ -104,7 +106,7 @@ _lib.ksym_plan_destroy.restype = None
 for _f in ("ksym_eig2", "ksym_zero_counters", "ksym_eig3", "ksym_eig3_aos", "ksym_eig3_backward",
            "ksym_eig2_backward", "ksym_compose3", "ksym_compose2", "ksym_eig3_backward_angles",
            "ksym_plan_create", "ksym_plan_run", "ksym_plan_capture", "ksym_plan_replay",
-           "ksym_plan_info"):
+           "ksym_plan_info", "ksym_mixed_run_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -502,3 +504,16 @@ class Plan:
         except Exception:
             pass
 
+
+def mixed_run_noalloc(groups, opts=None, ws=None, stream=None):
+    """The mixed batch of Plan(groups, opts).run(), in one call that allocates
+    no device memory (the library's fixed tables; see include/ksym.h for the
+    limits).  groups as for Plan; ws: None or a workspace() tensor, whose
+    counters are zeroed and accumulated.  Calls that overlap on one GPU race."""
+    ref = groups[0][1]
+    dt = _dt(ref)
+    arr = _group_array(groups)
+    o = _opts(dt, opts, _kind="mixed")
+    st = _stream(ref) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    wp, wb = (ws.data_ptr(), ws.numel() * ws.element_size()) if ws is not None else (None, 0)
+    _check(_lib.ksym_mixed_run_noalloc(dt, len(groups), arr, ctypes.byref(o), wp, wb, st))

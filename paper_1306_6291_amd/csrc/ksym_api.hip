@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -311,12 +312,22 @@ ksym_status check_ranges(Range *v, size_t n) {
     return KSYM_OK;
 }
 
-// The ranges of one call, in a heap vector.
+// The ranges of one call, in a heap vector (VecStore) or in a caller-owned
+// fixed array (FixedStore, for the entry point that allocates nothing).
 struct VecStore {
     std::vector<Range> v;
     void push(const Range &r) { v.push_back(r); }
     Range *data() { return v.data(); }
     size_t size() const { return v.size(); }
+};
+struct FixedStore {
+    Range *v;
+    size_t n, cap;
+    void push(const Range &r) {
+        if (n < cap) v[n++] = r;
+    }
+    Range *data() { return v; }
+    size_t size() const { return n; }
 };
 template <typename Store> struct RangeSet {
     Store st;
@@ -1004,5 +1015,134 @@ void ksym_plan_destroy(ksym_plan *p) {
     delete p;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ mixed batch, no allocation ---
+// ksym_mixed_run_noalloc keeps the descriptor table, its first-tile prefix and
+// the wave-tile table of one mixed batch in `scratch`, a fixed device array
+// (one copy per GPU, held until the process ends).  In host code the array's
+// name is only a handle for hipGetSymbolAddress: its device address, which
+// differs per GPU, is looked up once per device and kept in g_scratch_addr.
+namespace {
+constexpr size_t kNaDescBytes = (size_t)KSYM_NOALLOC_MAX_DESCRIPTORS * sizeof(GroupDesc<double>);
+constexpr size_t kNaFirstBytes = (((size_t)KSYM_NOALLOC_MAX_DESCRIPTORS + 1) * sizeof(int64_t) + 255) / 256 * 256;
+constexpr size_t kNaTileBytes = (size_t)KSYM_NOALLOC_MAX_TILES * sizeof(TileInfo);
+constexpr size_t kNaScratchBytes = kNaDescBytes + kNaFirstBytes + kNaTileBytes;
+static_assert(sizeof(GroupDesc<float>) == sizeof(GroupDesc<double>), "descriptor layouts differ by dtype");
+static_assert(kNaDescBytes % 256 == 0, "descriptor region must keep the next region 256-byte aligned");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+namespace {
+std::atomic<void *> g_scratch_addr[64];
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call).
+ksym_status scratch_addr(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(KSYM_E_HIP, "device index %d out of range", dev);
+    void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch_addr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            if (!p) return fail(KSYM_E_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+            g_scratch_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return KSYM_OK;
+}
+
+// Fixed storage for the aliasing check of ksym_mixed_run_noalloc (plus one
+// range for the workspace), guarded by g_na_mu.
+Range g_na_ranges[(size_t)KSYM_NOALLOC_MAX_GROUPS * kGroupRanges + 1];
+std::mutex g_na_mu;
+}  // namespace
+
+extern "C" {
+
+ksym_status ksym_mixed_run_noalloc(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
+                                   const ksym_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (dtype != KSYM_F32 && dtype != KSYM_F64) return fail(KSYM_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (ngroups <= 0 || !groups) return fail(KSYM_E_ARG, "need ngroups > 0 and a group array");
+    if (ngroups > KSYM_NOALLOC_MAX_GROUPS)
+        return fail(KSYM_E_ARG, "%d groups; ksym_mixed_run_noalloc takes at most %d", (int)ngroups,
+                    KSYM_NOALLOC_MAX_GROUPS);
+    ksym_opts o;
+    ksym_status s = mixed_opts(dtype, opts, &o);
+    if (s != KSYM_OK) return s;
+    s = check_ws(ws, ws_bytes);
+    if (s != KSYM_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_na_mu);
+        RangeSet<FixedStore> rg{FixedStore{g_na_ranges, 0, sizeof g_na_ranges / sizeof g_na_ranges[0]}};
+        rg.add(ws, ws_bytes, true, "ws", 0);
+        s = check_groups(dtype, ngroups, groups, rg);
+        if (s != KSYM_OK) return s;
+    }
+    const int tile = 64 * o.mats_per_lane;
+    int64_t ndesc = 0;
+    const int64_t ntiles = for_each_desc(ngroups, groups, tile, [&](int, int64_t, int64_t, int64_t) { ++ndesc; });
+    if (ndesc > KSYM_NOALLOC_MAX_DESCRIPTORS)
+        return fail(KSYM_E_ARG, "%lld group chunks of at most 2^28 matrices; at most %d", (long long)ndesc,
+                    KSYM_NOALLOC_MAX_DESCRIPTORS);
+    if (ntiles > KSYM_NOALLOC_MAX_TILES)
+        return fail(KSYM_E_ARG, "%lld wave tiles of %d matrices; at most %d", (long long)ntiles, tile,
+                    KSYM_NOALLOC_MAX_TILES);
+    int grid = 0;
+    s = mixed_grid(o, ntiles, &grid);
+    if (s != KSYM_OK) return s;
+    void *base = nullptr;
+    s = scratch_addr(&base);
+    if (s != KSYM_OK) return s;
+    char *const b = (char *)base;
+    void *const d_desc = b;
+    int64_t *const d_first = (int64_t *)(b + kNaDescBytes);
+    TileInfo *const d_tiles = (TileInfo *)(b + kNaDescBytes + kNaFirstBytes);
+    const hipStream_t st = (hipStream_t)stream;
+    // descriptors and their first tiles through kernel arguments, DESC_BATCH
+    // per launch; then the tile table from the prefix
+    auto tables = [&](auto tag) -> ksym_status {
+        using T = decltype(tag);
+        DescBatch<T> batch;
+        memset(&batch, 0, sizeof batch);
+        int64_t done = 0;
+        hipError_t err = hipSuccess;
+        auto flush = [&](bool last) {
+            batch.last = last ? 1 : 0;
+            batch.total_tiles = ntiles;
+            if (err == hipSuccess)
+                err = launch(&k_put_desc<T>, dim3(1), dim3(64), st, batch, (GroupDesc<T> *)d_desc, d_first);
+            batch.start += batch.count;
+            batch.count = 0;
+        };
+        for_each_desc(ngroups, groups, tile, [&](int g, int64_t start, int64_t len, int64_t first) {
+            batch.d[batch.count] = make_desc<T>(groups[g], start, len);
+            batch.first_tile[batch.count] = first;
+            ++batch.count;
+            ++done;
+            if (batch.count == DESC_BATCH && done < ndesc) flush(false);
+        });
+        flush(true);
+        if (err != hipSuccess) return hip_fail(err, "launch k_put_desc");
+        if (ntiles > 0) {
+            err = launch(&k_fill_tiles, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), st,
+                         (const int64_t *)d_first, (int32_t)ndesc, d_tiles, ntiles, (int32_t)tile);
+            if (err != hipSuccess) return hip_fail(err, "launch k_fill_tiles");
+        }
+        return KSYM_OK;
+    };
+    s = dtype == KSYM_F32 ? tables(float()) : tables(double());
+    if (s != KSYM_OK) return s;
+    return launch_mixed(dtype, o, d_desc, d_tiles, (int32_t)ndesc, ntiles, grid, ws, st);
+}
 
 }  // extern "C"

@@ -1280,5 +1280,47 @@ __global__ void k_zero_u32(unsigned *p, int n) {
     if (i < n) p[i] = 0u;
 }
 
+// ------------------------------------------- mixed batch without a plan ----
+// The descriptor table and the tile table of a mixed batch written on the
+// device from kernel arguments, for the entry point that allocates nothing
+// (its tables live in a fixed device array).  DESC_BATCH descriptors travel
+// per launch in the argument block (at most 4 KB), with the index of each
+// one's first tile; the last batch also carries the total, which closes the
+// prefix array.
+constexpr int DESC_BATCH = 16;
+template <typename T> struct DescBatch {
+    GroupDesc<T> d[DESC_BATCH];
+    int64_t first_tile[DESC_BATCH];
+    int64_t total_tiles;   // written after the last descriptor when last != 0
+    int32_t start, count, last, pad;
+};
+static_assert(sizeof(DescBatch<double>) <= 4096, "descriptor batch exceeds the kernel argument limit");
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_put_desc(DescBatch<T> b, GroupDesc<T> *dst, int64_t *first) {
+    const int i = threadIdx.x;
+    if (i < b.count) {
+        dst[b.start + i] = b.d[i];
+        first[b.start + i] = b.first_tile[i];
+    }
+    if (i == 0 && b.last) first[b.start + b.count] = b.total_tiles;
+}
+
+// tiles[t] = (descriptor d, offset of the tile's first matrix in d) for the
+// descriptor with first[d] <= t < first[d + 1]; empty descriptors (first[d] =
+// first[d + 1]) own no tile.  first has ndesc + 1 entries, ndesc >= 1.
+__global__ __launch_bounds__(256) void k_fill_tiles(const int64_t *first, int32_t ndesc, TileInfo *tiles,
+                                                    int64_t ntiles, int32_t tile) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int32_t lo = 0, hi = ndesc - 1;   // the last d with first[d] <= t
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (first[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    tiles[t].group = lo;
+    tiles[t].base = (uint32_t)((t - first[lo]) * tile);
+}
 
 }  // namespace ksym

@@ -399,3 +399,66 @@ def test_plan_rejects_aliasing_across_groups(lib):
     assert "overlaps" in _err(lib)
     assert not h.value
 
+
+def _noalloc(lib):
+    f = lib.ksym_mixed_run_noalloc
+    P = ctypes.c_void_p
+    f.argtypes = [ctypes.c_int, ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    f.restype = ctypes.c_int
+    return f
+
+
+def _disjoint_groups(ksym, ng, n, kind=3, stride=0x100000):
+    """ng groups of n matrices at made-up, non-overlapping addresses (never
+    dereferenced: every case below is rejected before any HIP call)."""
+    arr = (ksym.Group * ng)()
+    base = 0x10000000
+    for g in range(ng):
+        arr[g].kind = kind
+        arr[g].n = n
+        for c in range(6 if kind == 3 else 3):
+            arr[g].in_[c] = base
+            base += stride
+        for c in range(3 if kind == 3 else 2):
+            arr[g].lam[c] = base
+            base += stride
+    return arr
+
+
+def test_noalloc_rejects_bad_batches_before_any_hip_call(lib):
+    """ksym_mixed_run_noalloc: group count, chunk count and tile count beyond
+    the fixed tables, bad groups, aliasing across groups and a short
+    workspace are KSYM_E_ARG / KSYM_E_WORKSPACE, reported before any HIP call
+    (this host has no GPU)."""
+    import paper_1306_6291_amd as ksym
+    f = _noalloc(lib)
+    arr = _disjoint_groups(ksym, 2, 1000)
+    g = ctypes.cast(arr, ctypes.c_void_p)
+    assert f(0, 0, g, None, None, 0, None) == 1
+    assert f(0, 2, None, None, None, 0, None) == 1
+    assert f(7, 2, g, None, None, 0, None) == 2
+    big = _disjoint_groups(ksym, 4097, 1, stride=0x1000)
+    assert f(0, 4097, ctypes.cast(big, ctypes.c_void_p), None, None, 0, None) == 1
+    assert "at most 4096" in _err(lib)
+    # 2^21 tiles of 64 matrices: one group of 2^27 + 1 matrices needs one more
+    one = _disjoint_groups(ksym, 1, (1 << 27) + 1, stride=1 << 30)
+    assert f(0, 1, ctypes.cast(one, ctypes.c_void_p), None, None, 0, None) == 1
+    assert "wave tiles" in _err(lib)
+    # 8192 chunks of 2^28: 33 groups of 2^33 matrices give 33 * 32 = 1056 chunks
+    # (allowed), 257 such groups 8224 (too many)
+    many = _disjoint_groups(ksym, 257, 1 << 33, stride=1 << 36)
+    assert f(1, 257, ctypes.cast(many, ctypes.c_void_p), None, None, 0, None) == 1
+    assert "chunks" in _err(lib)
+    arr[1].kind = 5
+    assert f(0, 2, g, None, None, 0, None) == 1
+    arr[1].kind = 3
+    arr[1].lam[2] = arr[0].in_[4] + 64          # an output inside another group's input
+    assert f(0, 2, g, None, None, 0, None) == 1
+    assert "overlaps" in _err(lib)
+    arr = _disjoint_groups(ksym, 2, 1000)
+    g = ctypes.cast(arr, ctypes.c_void_p)
+    ws = 0x7000000000
+    assert f(0, 2, g, None, ctypes.c_void_p(ws), 4, None) == 3     # too small
+    assert f(0, 2, g, None, ctypes.c_void_p(ws + 2), 256, None) == 3  # misaligned
+    assert f(0, 2, g, None, ctypes.c_void_p(arr[0].lam[1]), 256, None) == 1  # ws inside an output
+    assert "overlaps" in _err(lib)
