@@ -123,9 +123,16 @@ typedef enum {
  *                  below which a matrix always takes the refinement (0 = off).
  *   tau_res        refinement if some residual ||A d_k - lam_k d_k|| exceeds
  *                  tau_res * ||A||_F.
- *   tau_vec        refinement if some |d_j^T A d_k| / |lam_k - lam_j| exceeds
- *                  tau_vec (first-order angle error of the eigenvectors;
- *                  0 = off).
+ *   tau_vec        differentiated calls (0 = off): the first-order rotation
+ *                  T_jk of each pair of columns of D against the true
+ *                  eigenvectors, T_jk (lam_j - lam_k) = d_j^T A d_k -
+ *                  (lam_j + lam_k)/2 d_j^T d_k, is evaluated in float64 and
+ *                  removed from D (D (I - T)) and from the angles (which keep
+ *                  D = R1 R2 R3 (phi) to first order); a matrix whose |T_jk|
+ *                  or angle correction exceeds tau_vec is refined instead.
+ *                  The adjoint multiplies eigenvector errors by
+ *                  1/(lam_j - lam_k), so a small gap needs D accurate to far
+ *                  below the float32 closed form's rounding level.
  *   drain_tiles    refinement queue age limit: each wavefront refines its
  *                  queued matrices once 64 are waiting or once the oldest has
  *                  waited this many of the wave's tiles, whichever comes
@@ -313,7 +320,8 @@ typedef struct ksym_plan ksym_plan;
  * Build a plan for `ngroups` groups (copied; the group array may be freed
  * afterwards, the device planes it points to may not).  Allocates the device
  * descriptor table (the only allocating call).  *ws_bytes receives the
- * workspace size ksym_plan_run needs.
+ * workspace size ksym_plan_run needs.  Options with tau_vec > 0 give
+ * KSYM_E_UNSUPPORTED (mixed batches are not differentiated).
  */
 ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group *groups,
                              const ksym_opts *opts, ksym_plan **plan, size_t *ws_bytes);

@@ -345,13 +345,22 @@ def zero_counters(ws):
 
 
 # ------------------------------------------------------------ autograd ------
+def _grad_opts(planes, opts):
+    """Forward options for a differentiated call: the caller's, else the tuned
+    gradient setting, whose tau_vec > 0 has the forward remove each
+    eigenvector pair's first-order rotation in float64 (the adjoint's
+    1/(lam_i - lam_j) terms would magnify it)."""
+    return opts if opts is not None else tuned_opts("eig3_grad", _dt(planes))
+
+
 class Eig3Function(torch.autograd.Function):
-    """lam, D = Eig3Function.apply(planes, eps_rel): differentiable in lam and D
-    through the hand-written adjoint kernel.  planes is a (6, n) tensor."""
+    """lam, D = Eig3Function.apply(planes, eps_rel, opts): differentiable in lam
+    and D through the hand-written adjoint kernel.  planes is a (6, n) tensor;
+    opts None takes the tuned gradient setting (tau_vec > 0)."""
 
     @staticmethod
     def forward(ctx, planes, eps_rel=None, opts=None):
-        out = eig3(planes.contiguous(), opts=opts, outputs=("lam", "D", "gap"))
+        out = eig3(planes.contiguous(), opts=_grad_opts(planes, opts), outputs=("lam", "D", "gap"))
         ctx.save_for_backward(out["lam"], out["D"], out["gap"])
         ctx.eps_rel = eps_rel
         return out["lam"], out["D"]
@@ -370,13 +379,14 @@ def eig3_autograd(planes, eps_rel=None, opts=None):
 
 
 class Eig3AnglesFunction(torch.autograd.Function):
-    """lam, D, phi = Eig3AnglesFunction.apply(planes, eps_rel): differentiable
-    in lam, D and the Euler angles (regularised at gimbal lock; the angles are
-    not differentiable where they wrap)."""
+    """lam, D, phi = Eig3AnglesFunction.apply(planes, eps_rel, opts):
+    differentiable in lam, D and the Euler angles (regularised at gimbal lock;
+    the angles are not differentiable where they wrap); opts as for
+    Eig3Function."""
 
     @staticmethod
     def forward(ctx, planes, eps_rel=None, opts=None):
-        out = eig3(planes.contiguous(), opts=opts, outputs=("lam", "D", "phi", "gap"))
+        out = eig3(planes.contiguous(), opts=_grad_opts(planes, opts), outputs=("lam", "D", "phi", "gap"))
         ctx.save_for_backward(out["lam"], out["D"], out["phi"], out["gap"])
         ctx.eps_rel = eps_rel
         return out["lam"], out["D"], out["phi"]

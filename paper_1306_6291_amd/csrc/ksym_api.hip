@@ -109,9 +109,13 @@ ksym_status grid_for(int64_t n, int tile, int grid_mult, int *grid) {
 template <typename T, int PATH, bool AOS> using Eig3K = void (*)(Eig3Args<T>);
 
 #define KSYM_E3(T, P, A, B, M) \
-    if (bs == B && mpl == M) return &k_eig3<T, P, B, M, A>;
+    if (bs == B && mpl == M) return grad ? &k_eig3<T, P, B, M, A, true> : &k_eig3<T, P, B, M, A, false>;
+#define KSYM_E3N(T, P, A, B, M) \
+    if (bs == B && mpl == M) return grad ? nullptr : &k_eig3<T, P, B, M, A, false>;
 
-template <typename T, int PATH, bool AOS> Eig3K<T, PATH, AOS> pick_eig3(int bs, int mpl);
+// grad: the variant for differentiated calls (tau_vec > 0), compiled for a
+// subset of the shapes (KSYM_E3N: plain variant only)
+template <typename T, int PATH, bool AOS> Eig3K<T, PATH, AOS> pick_eig3(int bs, int mpl, bool grad);
 
 // eigenvalues-only kernel (float32 SoA), the same launch shapes as k_eig3<float>
 using LamK = void (*)(Eig3Args<float>);
@@ -132,48 +136,49 @@ bool none_requested(void *const *planes, int k) {
     return true;
 }
 
-template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXUP, false>(int bs, int mpl) {
+template <> Eig3K<float, PATH_FP32_FIXUP, false> pick_eig3<float, PATH_FP32_FIXUP, false>(int bs, int mpl, bool grad) {
     KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 1)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 64, 2)
+    KSYM_E3N(float, PATH_FP32_FIXUP, false, 64, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 1)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 128, 2)
+    KSYM_E3N(float, PATH_FP32_FIXUP, false, 128, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 256, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 1)
-    KSYM_E3(float, PATH_FP32_FIXUP, false, 512, 2)
+    KSYM_E3N(float, PATH_FP32_FIXUP, false, 512, 2)
     return nullptr;
 }
-template <> Eig3K<float, PATH_FP32_FIXUP, true> pick_eig3<float, PATH_FP32_FIXUP, true>(int bs, int mpl) {
-    KSYM_E3(float, PATH_FP32_FIXUP, true, 64, 1)
+template <> Eig3K<float, PATH_FP32_FIXUP, true> pick_eig3<float, PATH_FP32_FIXUP, true>(int bs, int mpl, bool grad) {
+    KSYM_E3N(float, PATH_FP32_FIXUP, true, 64, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 128, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 1)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 256, 2)
     KSYM_E3(float, PATH_FP32_FIXUP, true, 512, 1)
     return nullptr;
 }
-template <> Eig3K<double, PATH_FP64_PLAIN, false> pick_eig3<double, PATH_FP64_PLAIN, false>(int bs, int mpl) {
-    KSYM_E3(double, PATH_FP64_PLAIN, false, 64, 1)
-    KSYM_E3(double, PATH_FP64_PLAIN, false, 128, 1)
-    KSYM_E3(double, PATH_FP64_PLAIN, false, 256, 1)
-    KSYM_E3(double, PATH_FP64_PLAIN, false, 256, 2)
+template <> Eig3K<double, PATH_FP64_PLAIN, false> pick_eig3<double, PATH_FP64_PLAIN, false>(int bs, int mpl, bool grad) {
+    KSYM_E3N(double, PATH_FP64_PLAIN, false, 64, 1)
+    KSYM_E3N(double, PATH_FP64_PLAIN, false, 128, 1)
+    KSYM_E3N(double, PATH_FP64_PLAIN, false, 256, 1)
+    KSYM_E3N(double, PATH_FP64_PLAIN, false, 256, 2)
     return nullptr;
 }
-template <> Eig3K<double, PATH_FP64_PLAIN, true> pick_eig3<double, PATH_FP64_PLAIN, true>(int bs, int mpl) {
-    KSYM_E3(double, PATH_FP64_PLAIN, true, 256, 1)
+template <> Eig3K<double, PATH_FP64_PLAIN, true> pick_eig3<double, PATH_FP64_PLAIN, true>(int bs, int mpl, bool grad) {
+    KSYM_E3N(double, PATH_FP64_PLAIN, true, 256, 1)
     return nullptr;
 }
-template <> Eig3K<double, PATH_FP64_FIXUP, false> pick_eig3<double, PATH_FP64_FIXUP, false>(int bs, int mpl) {
-    KSYM_E3(double, PATH_FP64_FIXUP, false, 64, 1)
-    KSYM_E3(double, PATH_FP64_FIXUP, false, 128, 1)
+template <> Eig3K<double, PATH_FP64_FIXUP, false> pick_eig3<double, PATH_FP64_FIXUP, false>(int bs, int mpl, bool grad) {
+    KSYM_E3N(double, PATH_FP64_FIXUP, false, 64, 1)
+    KSYM_E3N(double, PATH_FP64_FIXUP, false, 128, 1)
     KSYM_E3(double, PATH_FP64_FIXUP, false, 256, 1)
-    KSYM_E3(double, PATH_FP64_FIXUP, false, 256, 2)
+    KSYM_E3N(double, PATH_FP64_FIXUP, false, 256, 2)
     return nullptr;
 }
-template <> Eig3K<double, PATH_FP64_FIXUP, true> pick_eig3<double, PATH_FP64_FIXUP, true>(int bs, int mpl) {
+template <> Eig3K<double, PATH_FP64_FIXUP, true> pick_eig3<double, PATH_FP64_FIXUP, true>(int bs, int mpl, bool grad) {
     KSYM_E3(double, PATH_FP64_FIXUP, true, 256, 1)
     return nullptr;
 }
 #undef KSYM_E3
+#undef KSYM_E3N
 
 template <typename T> using Eig2K = void (*)(Eig2Ptrs<T>, uint32_t);
 template <typename T> Eig2K<T> pick_eig2(int bs, int mpl) {
@@ -227,17 +232,19 @@ ksym_status eig3_impl(int64_t n, const void *const in[6], const void *aos, void 
     finish_params(a.prm);
     (void)ws_bytes;
     void (*k)(Eig3Args<T>) = nullptr;
+    const bool grad = o.tau_vec > 0.0;
     if constexpr (sizeof(T) == 4) {
         // no D and no angles: the eigenvalues-only kernel (reduced-output mode)
         if (!AOS && none_requested(D, 9) && none_requested(phi, 3)) k = pick_eig3_lam(o.block, o.mats_per_lane);
-        else k = pick_eig3<float, PATH_FP32_FIXUP, AOS>(o.block, o.mats_per_lane);
+        else k = pick_eig3<float, PATH_FP32_FIXUP, AOS>(o.block, o.mats_per_lane, grad);
     } else {
-        if (o.path == KSYM_PATH_FP64_PLAIN) k = pick_eig3<double, PATH_FP64_PLAIN, AOS>(o.block, o.mats_per_lane);
-        else k = pick_eig3<double, PATH_FP64_FIXUP, AOS>(o.block, o.mats_per_lane);
+        // (the plain path has no check, so tau_vec does not apply to it)
+        if (o.path == KSYM_PATH_FP64_PLAIN) k = pick_eig3<double, PATH_FP64_PLAIN, AOS>(o.block, o.mats_per_lane, false);
+        else k = pick_eig3<double, PATH_FP64_FIXUP, AOS>(o.block, o.mats_per_lane, grad);
     }
     if (!k)
-        return fail(KSYM_E_UNSUPPORTED, "no compiled 3x3 kernel for block %d, mats_per_lane %d%s",
-                    o.block, o.mats_per_lane, AOS ? " (AoS)" : "");
+        return fail(KSYM_E_UNSUPPORTED, "no compiled 3x3 kernel for block %d, mats_per_lane %d%s%s",
+                    o.block, o.mats_per_lane, AOS ? " (AoS)" : "", grad ? " with tau_vec > 0" : "");
     // one launch per chunk of matrices, every pointer advanced by the chunk start
     const int64_t chunk = !AOS ? KSYM_CHUNK : (sizeof(T) == 4 ? KSYM_CHUNK_AOS_F32 : KSYM_CHUNK_AOS_F64);
     for (int64_t start = 0; start < n; start += chunk) {
@@ -824,6 +831,9 @@ ksym_status mixed_opts(ksym_dtype dtype, const ksym_opts *opts, ksym_opts *o) {
     ksym_status s = resolve_opts(dtype, opts, o);
     if (s != KSYM_OK) return s;
     o->path = dtype == KSYM_F32 ? KSYM_PATH_FP32_FIXUP : KSYM_PATH_FP64_FIXUP;
+    if (o->tau_vec > 0.0)
+        return fail(KSYM_E_UNSUPPORTED, "tau_vec (differentiated calls) applies to ksym_eig3 and ksym_eig3_aos, "
+                                        "not to mixed batches");
     const bool ok = dtype == KSYM_F32 ? pick_mixed<float>(o->block, o->mats_per_lane) != nullptr
                                       : pick_mixed<double>(o->block, o->mats_per_lane) != nullptr;
     if (!ok)

@@ -606,37 +606,94 @@ template <typename T> __device__ __forceinline__ void extract_angles(T D[9], T p
 // r_k = B d_k - mu_k d_k = A d_k - lam_k d_k.  Fails when some ||r_k||^2
 // exceeds lim2 = (tau_res ||A||_F)^2; for orthonormal D, ||r_k|| is the norm
 // of column k of D^T B D - diag(mu), so this covers both a wrong eigenvector
-// (off-diagonal entries) and a wrong pairing with mu_k (diagonal entry).  With
-// tau_vec > 0 it also fails when |d_j^T A d_k| / |lam_j - lam_k|, the
-// first-order angle by which d_k leans towards d_j, exceeds tau_vec.  C is the
-// arithmetic type; in float32 its rounding noise is about 1e-7 ||A||_F.
+// (off-diagonal entries) and a wrong pairing with mu_k (diagonal entry).  C is
+// the arithmetic type; in float32 its rounding noise is about 1e-7 ||A||_F.
 template <typename C>
 __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a23, const C d[9],
-                                            C mu1, C mu2, C mu3, C g12, C g13, C g32, C lim2,
-                                            C tau_vec) {
+                                            C mu1, C mu2, C mu3, C lim2) {
     const C mu[3] = {mu1, mu2, mu3};
-    C r[9];
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const C x = d[k], y = d[3 + k], z = d[6 + k];
-        r[k] = (d1 - mu[k]) * x + a12 * y + a13 * z;
-        r[3 + k] = a12 * x + (d2 - mu[k]) * y + a23 * z;
-        r[6 + k] = a13 * x + a23 * y + (d3 - mu[k]) * z;
-        const C n2 = r[k] * r[k] + r[3 + k] * r[3 + k] + r[6 + k] * r[6 + k];
-        bad |= !(n2 <= lim2);
-    }
-    if (tau_vec > C(0)) {
-        // (the empty asm keeps this a branch on the uniform threshold; the
-        // compiler would otherwise evaluate the test for every matrix)
-        asm volatile("");
-        using M = Mth<C>;
-        // d_j^T B d_k = d_j^T r_k for j != k (the columns are orthogonal)
-        auto dot = [&](int j, int k) { return d[j] * r[k] + d[3 + j] * r[3 + k] + d[6 + j] * r[6 + k]; };
-        bad |= !(M::fabs(dot(0, 1)) <= tau_vec * g12 && M::fabs(dot(0, 2)) <= tau_vec * g13 &&
-                 M::fabs(dot(1, 2)) <= tau_vec * g32);
+        const C r0 = (d1 - mu[k]) * x + a12 * y + a13 * z;
+        const C r1 = a12 * x + (d2 - mu[k]) * y + a23 * z;
+        const C r2 = a13 * x + a23 * y + (d3 - mu[k]) * z;
+        bad |= !(r0 * r0 + r1 * r1 + r2 * r2 <= lim2);
     }
     return bad;
+}
+
+// First-order pair correction for differentiated calls (tau_vec > 0), in
+// float64 on D as computed (its float type C).  Writing D = V (I + T + S)
+// with V the true eigenvectors, T antisymmetric (a rotation) and S symmetric
+// (D's departure from orthonormality), the off-diagonal entries of D^T B D
+// are, to first order, T_jk (mu_j - mu_k) + (mu_j + mu_k) S_jk, and
+// d_j^T d_k = 2 S_jk; so
+//   X_jk = d_j^T B d_k - (mu_j + mu_k) / 2 * d_j^T d_k = T_jk (mu_j - mu_k)
+// gives the rotation T_jk of each pair (j, k), which the adjoint would
+// magnify by 1/(lam_j - lam_k).  D is replaced by D (I - T), which leaves a
+// remainder of second order in T, and the angles by phi + dphi, where dphi
+// solves M(phi) dphi = w for the body rates w of D^T dD = -T ([w]x = -T;
+// M as in angle_body_cotangent), so that D = R1 R2 R3 (phi) still holds to
+// first order.  Returns true (refine instead) when a rotation or an angle
+// correction exceeds tau (a large one would leave a remainder that matters,
+// as near gimbal lock, where dphi1 divides by cos phi2), or when a pair with
+// a zero gap is not already exact.  In float32 the X_jk of a small gap would
+// drown in rounding noise (about 1e-7 ||A||_F).  Slots 0 = max, 1 = min,
+// 2 = mid; gaps g12 = mu1 - mu2 (pair 0, 1), g13 = mu1 - mu3 (0, 2),
+// g32 = mu3 - mu2 (1, 2).
+template <typename C>
+__device__ __forceinline__ bool rotate_pairs64(double d1, double d2, double d3, double a12, double a13,
+                                               double a23, double mu1, double mu2, double mu3, double g12,
+                                               double g13, double g32, const Rot<C> &R, double tau, C D[9],
+                                               C phi[3]) {
+    double c[3][3];   // c[k] = column k
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c[k][0] = (double)D[k];
+        c[k][1] = (double)D[3 + k];
+        c[k][2] = (double)D[6 + k];
+    }
+    auto Bcol = [&](int k, double out[3]) {
+        out[0] = d1 * c[k][0] + a12 * c[k][1] + a13 * c[k][2];
+        out[1] = a12 * c[k][0] + d2 * c[k][1] + a23 * c[k][2];
+        out[2] = a13 * c[k][0] + a23 * c[k][1] + d3 * c[k][2];
+    };
+    auto dot = [&](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+    double b1[3], b2[3];
+    Bcol(1, b1);
+    Bcol(2, b2);
+    const double x01 = dot(c[0], b1) - 0.5 * (mu1 + mu2) * dot(c[0], c[1]);
+    const double x02 = dot(c[0], b2) - 0.5 * (mu1 + mu3) * dot(c[0], c[2]);
+    const double x12 = dot(c[1], b2) - 0.5 * (mu2 + mu3) * dot(c[1], c[2]);
+    // T_jk = X_jk / (lam_j - lam_k): lam0 - lam1 = g12, lam0 - lam2 = g13,
+    // lam1 - lam2 = -g32 (a reciprocal good to 2^-44 is ample here)
+    const double t01 = g12 > 0.0 ? x01 * rcp64<1>(g12) : 0.0;
+    const double t02 = g13 > 0.0 ? x02 * rcp64<1>(g13) : 0.0;
+    const double t12 = g32 > 0.0 ? -x12 * rcp64<1>(g32) : 0.0;
+    bool big = (g12 == 0.0 && x01 != 0.0) || (g13 == 0.0 && x02 != 0.0) || (g32 == 0.0 && x12 != 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double n0 = c[0][i] + c[1][i] * t01 + c[2][i] * t02;
+        const double n1 = c[1][i] - c[0][i] * t01 + c[2][i] * t12;
+        const double n2 = c[2][i] - c[0][i] * t02 - c[1][i] * t12;
+        D[3 * i] = (C)n0;
+        D[3 * i + 1] = (C)n1;
+        D[3 * i + 2] = (C)n2;
+    }
+    // [w]x = -T: w = (t12, -t02, t01)
+    const C w0 = (C)t12, w1 = (C)-t02, w2 = (C)t01;
+    const C dp2 = R.s3 * w0 + R.c3 * w1;
+    const C dp1 = Mth<C>::div(R.c3 * w0 - R.s3 * w1, R.c2);
+    const C dp3 = w2 - R.s2 * dp1;
+    const C tc = (C)tau;
+    big = big || !(__builtin_fabs(t01) <= tau && __builtin_fabs(t02) <= tau && __builtin_fabs(t12) <= tau &&
+                   Mth<C>::fabs(dp1) <= tc && Mth<C>::fabs(dp3) <= tc);
+    phi[0] += dp1;
+    phi[1] += dp2;
+    phi[2] += dp3;
+    return big;
 }
 
 // The float64 check with Rayleigh-quotient eigenvalues: as check_fails, and
@@ -646,8 +703,8 @@ __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a2
 // (at most ||r_k||^2 / gap), while the cubic's root can carry an error of
 // order eps ||A||^2 / gap near a double root (arccos's slope in (4.9)).
 __device__ __forceinline__ bool check_rq64(double d1, double d2, double d3, double a12, double a13, double a23,
-                                           const double d[9], double mu1, double mu2, double mu3, double g12,
-                                           double g13, double g32, double lim2, double tau_vec, double rq[3]) {
+                                           const double d[9], double mu1, double mu2, double mu3, double lim2,
+                                           double rq[3]) {
     const double mu[3] = {mu1, mu2, mu3};
     double r[9];
     bool bad = false;
@@ -660,12 +717,6 @@ __device__ __forceinline__ bool check_rq64(double d1, double d2, double d3, doub
         const double n2 = r[k] * r[k] + r[3 + k] * r[3 + k] + r[6 + k] * r[6 + k];
         bad |= !(n2 <= lim2);
         rq[k] = x * r[k] + y * r[3 + k] + z * r[6 + k];
-    }
-    if (tau_vec > 0.0) {
-        asm volatile("");   // (a branch on the uniform threshold; see check_fails)
-        auto dot = [&](int j, int k) { return d[j] * r[k] + d[3 + j] * r[3 + k] + d[6 + j] * r[6 + k]; };
-        bad |= !(__builtin_fabs(dot(0, 1)) <= tau_vec * g12 && __builtin_fabs(dot(0, 2)) <= tau_vec * g13 &&
-                 __builtin_fabs(dot(1, 2)) <= tau_vec * g32);
     }
     return bad;
 }

@@ -55,16 +55,16 @@ struct Eig3Params {
     unsigned *counters;   // [0] refined, [1] non-finite; may be null
     int32_t zero;         // always 0; see put3
     int32_t drain_tiles;  // queue age limit in wave tiles (0 = full waves only)
-    // the float32 check's thresholds, rounded once on the host so that they
-    // stay scalar operands: (float)tau_res squared in float, (float)tau_vec
-    float tau_res2_f, tau_vec_f;
+    // the float32 check's threshold, rounded once on the host so that it
+    // stays a scalar operand: (float)tau_res squared in float
+    float tau_res2_f, pad_f;
 };
 
-// Fills the float32 thresholds of a parameter block whose double fields are set.
+// Fills the float32 threshold of a parameter block whose double fields are set.
 __host__ inline void finish_params(Eig3Params &prm) {
     const float tr = (float)prm.tau_res;
     prm.tau_res2_f = tr * tr;
-    prm.tau_vec_f = (float)prm.tau_vec;
+    prm.pad_f = 0.0f;
 }
 
 template <typename T> struct Eig3Args {
@@ -187,7 +187,7 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
 // exist (plane k of lam, D, phi, gap), which keeps few of them in registers.
 // Sets refine (and the isolated eigenvalue lc for the refinement, a float64
 // deviation in scaled units) and returns the flag.
-template <typename Sink>
+template <bool GRAD, typename Sink>
 __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &prm, const Sink &sink,
                                         bool &refine, double &lc) {
     // max|A_ij| ignores a NaN entry and is infinite for an infinite one (then
@@ -244,15 +244,29 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
     float phi[3];
     angles_of(R, v, s2sq, w, cw, phi);
-    sink.template put_n<3>(O_PHI, phi);
     float D[9];
-    build_D(R, D);
+    if constexpr (GRAD) {
+        // differentiated calls (tau_vec > 0): the pairs' first-order rotation
+        // removed from D and the angles before they are stored
+        build_D(R, D);
+        const bool big = rotate_pairs64<float>(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], cu.mu1, cu.mu2, cu.mu3,
+                                               cu.g12, cu.g13, cu.g32, R, prm.tau_vec, D, phi);
+        // the adjoint's F_jk = g/(g^2 + eps^2) needs each gap to a few digits;
+        // the cubic stage's gaps carry absolute errors of a few 1e-10 sqrt(p)
+        // (its float32 tails), so a gap below 1e-5 sqrt(p) takes the
+        // refinement, whose Rayleigh quotients give it to float64 rounding
+        const bool close = split < 1e-5 * cu.sp;
+        bad = bad || big || close;
+        sink.template put_n<3>(O_PHI, phi);
+    } else {
+        sink.template put_n<3>(O_PHI, phi);
+        build_D(R, D);
+    }
     sink.template put_n<9>(O_D, D);
     // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
     const float fro2 = (float)__builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
     bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
-                                    (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, G12, G13, G32,
-                                    prm.tau_res2_f * fro2, prm.tau_vec_f);
+                                    (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, prm.tau_res2_f * fro2);
     refine = bad;
     return flag;
 }
@@ -265,7 +279,7 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
 // angles 0, lam = m) and a non-finite input is queued for its NaN outputs.
 // Sets refine and lc (the isolated eigenvalue handed to the refinement, a
 // deviation in scaled units) and returns the flag.
-template <typename Sink>
+template <bool GRAD, typename Sink>
 __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &prm, const Sink &sink,
                                          bool &refine, double &lc) {
     // as in eig3_f32, a non-finite entry shows as a non-finite p (cu.fin)
@@ -295,15 +309,24 @@ __device__ __forceinline__ int eig3_f64s(const double ain[6], const Eig3Params &
                                                 u.s2sq, u.w, u.cw, plus);
     double phi[3];
     angles_of(R, phi);
-    sink.template put_n<3>(O_PHI, phi);
     double D[9];
-    build_D(R, D);
+    bool big = false;
+    if constexpr (GRAD) {   // differentiated calls: as in eig3_f32
+        build_D(R, D);
+        big = rotate_pairs64<double>(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], cu.mu1, cu.mu2, cu.mu3, cu.g12, cu.g13,
+                                     cu.g32, R, prm.tau_vec, D, phi);
+        sink.template put_n<3>(O_PHI, phi);
+    } else {
+        sink.template put_n<3>(O_PHI, phi);
+        build_D(R, D);
+    }
     sink.template put_n<9>(O_D, D);
     // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
     const double fro2 = __builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
     double rq[3];
-    const bool cbad = check_rq64(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], D, cu.mu1, cu.mu2, cu.mu3, cu.g12,
-                                 cu.g13, cu.g32, prm.tau_res * prm.tau_res * fro2, prm.tau_vec, rq);
+    const bool rbad = check_rq64(cu.d1, cu.d2, cu.d3, a[3], a[4], a[5], D, cu.mu1, cu.mu2, cu.mu3,
+                                 prm.tau_res * prm.tau_res * fro2, rq);
+    const bool cbad = big || rbad;
     // eigenvalues as Rayleigh quotients of the checked columns (their gaps
     // corrected alike); p = 0 keeps the exact lam = m.  A correction that
     // would break the slot order (two eigenvalues within the residual of each
@@ -644,7 +667,7 @@ __device__ __forceinline__ unsigned drain_wave(WaveQueue<T, CAP> *q, int cnt, co
 // Process one wave tile of 64*MPL 3x3 matrices starting at `base` from inputs
 // already in registers: compute, store, queue the matrices that need the
 // refinement, and drain the queue.  Wave-uniform control flow.
-template <typename T, int PATH, int MPL, bool AOS, int SP, typename Planes, typename PlanesOf>
+template <typename T, int PATH, int MPL, bool AOS, int SP, bool GRAD, typename Planes, typename PlanesOf>
 __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &planes_of, int grp,
                                            const Eig3Params &prm, const WIn<T, MPL, AOS> &in,
                                            uint32_t n, uint32_t base,
@@ -682,9 +705,9 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
         bool refine;
         double lc;
         if constexpr (PATH == PATH_FP32_FIXUP) {
-            flag = eig3_f32(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
+            flag = eig3_f32<GRAD>(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
         } else if constexpr (PATH == PATH_FP64_FIXUP) {
-            flag = eig3_f64s(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
+            flag = eig3_f64s<GRAD>(A, prm, LaneSink<T, SP, Planes>{pl, salt, off}, refine, lc);
         } else {
             Out3<T> o;
             eig3_one<T>(A, prm, o);
@@ -796,23 +819,25 @@ __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refine
 
 // float32: an occupancy target makes the compiler fit the kernel into the
 // registers of 6 waves per SIMD (80 VGPRs) with one matrix per lane and of
-// 5 waves (96) with two; two matrices per lane at 6 waves would spill, and
+// 5 waves (96) with two (one wave less for the differentiated variant); two matrices per lane at 6 waves would spill, and
 // their queue's LDS allows 5 waves per SIMD anyway.  The plain float64 path
 // runs faster at 4 waves (128 VGPRs, a few spills) than at 3; the checked
 // one does not, and neither does the mixed-batch kernel at a higher target.
 // The target never exceeds what the workgroup's LDS allows (160 KB per CU).
-template <typename T, int PATH, int BS, int MPL, bool AOS>
+template <typename T, int PATH, int BS, int MPL, bool AOS, bool GRAD>
 constexpr int eig3_waves_target() {
     constexpr int NW = BS / WAVE;
-    constexpr int want = sizeof(T) == 4 ? (MPL == 1 ? 6 : MPL == 2 ? 5 : 1)
+    // (the differentiated float32 variant, with its float64 pair correction,
+    // gets one wave less: at the plain variant's budget it would spill)
+    constexpr int want = sizeof(T) == 4 ? (MPL == 1 ? 6 - GRAD : MPL == 2 ? 5 - GRAD : 1)
                                         : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1);
     constexpr size_t lds = NW * (sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>) + sizeof(int));
     constexpr int by_lds = (int)(163840 / lds) * NW / 4;
     return want < by_lds ? want : (by_lds > 1 ? by_lds : 1);
 }
-template <typename T, int PATH, int BS, int MPL, bool AOS>
+template <typename T, int PATH, int BS, int MPL, bool AOS, bool GRAD = false>
 __global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu(eig3_waves_target<T, PATH, BS, MPL, AOS>())))
+__attribute__((amdgpu_waves_per_eu(eig3_waves_target<T, PATH, BS, MPL, AOS, GRAD>())))
 void k_eig3(Eig3Args<T> args) {
     constexpr int NW = BS / WAVE;
     constexpr int WT = WAVE * MPL;
@@ -847,7 +872,7 @@ void k_eig3(Eig3Args<T> args) {
     auto step = [&]() {
         const uint32_t tn = t + stride;
         if (tn < ntiles) load_wtile3<T, MPL, AOS, LP>(nxt, inputs(tn), n, tn * WT);
-        wtile_eig3<T, PATH, MPL, AOS, SP>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
+        wtile_eig3<T, PATH, MPL, AOS, SP, GRAD>(pl, planes_of, 0, args.prm, cur, n, t * WT, my, qn, qage, refined,
                                           nonfinite);
         cur = nxt;
     };
@@ -1026,32 +1051,44 @@ __device__ __forceinline__ void bwd_lane(bool has_gap, bool has_ang, uint32_t i,
     for (int c = 0; c < 3; ++c) gl[c] = ld_plane<T, kStream>(pco.p[c], n, i);
 #pragma unroll
     for (int c = 0; c < 9; ++c) gD[c] = ld_plane<T, kStream>(pco.p[3 + c], n, i);
-    T g12, g13, g32;
+    // the arithmetic is float64 for either storage type: the symmetric part
+    // F_jk (E_jk - E_kj) can cancel, and a small gap then magnifies float32
+    // rounding of E into the gradient
+    double g12, g13, g32;
     if (has_gap) {
         const PtrN<const T, 3> pg = karg_ptrs<const T, 3>(P + offsetof(BwdPtrs<T>, gap) + 8 * salt);
-        g12 = ld_plane<T, kStream>(pg.p[0], n, i);
-        g13 = ld_plane<T, kStream>(pg.p[1], n, i);
-        g32 = ld_plane<T, kStream>(pg.p[2], n, i);
+        g12 = (double)ld_plane<T, kStream>(pg.p[0], n, i);
+        g13 = (double)ld_plane<T, kStream>(pg.p[1], n, i);
+        g32 = (double)ld_plane<T, kStream>(pg.p[2], n, i);
     } else {
-        // differences of the stored eigenvalues, exact in float64
-        g12 = (T)((double)L[0] - (double)L[1]);
-        g13 = (T)((double)L[0] - (double)L[2]);
-        g32 = (T)((double)L[2] - (double)L[1]);
+        // differences of the stored eigenvalues (exact in float64 for float32)
+        g12 = (double)L[0] - (double)L[1];
+        g13 = (double)L[0] - (double)L[2];
+        g32 = (double)L[2] - (double)L[1];
     }
-    const T eps = (T)eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
-    T wb[3] = {T(0), T(0), T(0)};
+    double Dd[9], gld[3], gDd[9], gAd[6];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Dd[c] = (double)D[c];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gDd[c] = (double)gD[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gld[c] = (double)gl[c];
+    const double l0 = L[0], l1 = L[1], l2 = L[2];
+    const double eps = eps_rel * sqrt_any64(l0 * l0 + l1 * l1 + l2 * l2);
+    double wb[3] = {0.0, 0.0, 0.0};
     if (has_ang) {   // uniform
         const PtrN<const T, 6> pa = karg_ptrs<const T, 6>(P + offsetof(BwdPtrs<T>, phi) + 8 * salt);
-        const T f2 = ld_plane<T, kStream>(pa.p[1], n, i), f3 = ld_plane<T, kStream>(pa.p[2], n, i);
-        const T gphi[3] = {ld_plane<T, kStream>(pa.p[3], n, i), ld_plane<T, kStream>(pa.p[4], n, i),
-                           ld_plane<T, kStream>(pa.p[5], n, i)};
-        T s2, c2, s3, c3;
+        const double f2 = ld_plane<T, kStream>(pa.p[1], n, i), f3 = ld_plane<T, kStream>(pa.p[2], n, i);
+        const double gphi[3] = {ld_plane<T, kStream>(pa.p[3], n, i), ld_plane<T, kStream>(pa.p[4], n, i),
+                                ld_plane<T, kStream>(pa.p[5], n, i)};
+        double s2, c2, s3, c3;
         sincos_t(f2, s2, c2);
         sincos_t(f3, s3, c3);
-        const T d = (T)eps_rel;
-        angle_body_cotangent<T>(c2, s2, c3, s3, gphi, d * d, wb);
+        angle_body_cotangent<double>(c2, s2, c3, s3, gphi, eps_rel * eps_rel, wb);
     }
-    adjoint3<T>(D, gl, gD, g12, g13, g32, eps * eps, wb, gA);
+    adjoint3<double>(Dd, gld, gDd, g12, g13, g32, eps * eps, wb, gAd);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gA[c] = (T)gAd[c];
     const PtrN<T, 6> po = karg_ptrs<T, 6>(P + offsetof(BwdPtrs<T>, gA) + 8 * salt);
 #pragma unroll
     for (int c = 0; c < 6; ++c) st_plane<T, kStream>(po.p[c], n, i, gA[c]);
@@ -1090,7 +1127,7 @@ template <typename T> struct Bwd2Args {
 };
 
 // One matrix per lane, grid-stride; the planes are streams.  eps = eps_rel *
-// ||lam||; the gap lam2 - lam1 is taken in float64 (exact for float32).
+// ||lam||; the arithmetic is float64 (the gap lam2 - lam1 exact for float32).
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_eig2_bwd(Bwd2Args<T> a) {
     const uint32_t n = a.n;
@@ -1104,10 +1141,21 @@ __global__ __launch_bounds__(BS) void k_eig2_bwd(Bwd2Args<T> a) {
         for (int c = 0; c < 2; ++c) gl[c] = ld_plane<T, kStream>(a.p.glam[c], n, i);
 #pragma unroll
         for (int c = 0; c < 4; ++c) gD[c] = ld_plane<T, kStream>(a.p.gD[c], n, i);
-        const T gphi = ld_plane<T, kStream>(a.p.gphi, n, i);
-        const T d = (T)((double)L[1] - (double)L[0]);
-        const T eps = (T)a.eps_rel * Mth<T>::sqrt(L[0] * L[0] + L[1] * L[1]);
-        adjoint2<T>(D, gl, gD, gphi, d, eps * eps, gA);
+        const double gphi = ld_plane<T, kStream>(a.p.gphi, n, i);
+        // float64 arithmetic for either storage type (as in the 3x3 adjoint)
+        const double l0 = L[0], l1 = L[1];
+        const double d = l1 - l0;
+        const double eps = a.eps_rel * sqrt_any64(l0 * l0 + l1 * l1);
+        double Dd[4], gld[2], gDd[4], gAd[3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Dd[c] = (double)D[c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gDd[c] = (double)gD[c];
+        gld[0] = gl[0];
+        gld[1] = gl[1];
+        adjoint2<double>(Dd, gld, gDd, gphi, d, eps * eps, gAd);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gA[c] = (T)gAd[c];
 #pragma unroll
         for (int c = 0; c < 3; ++c) st_plane<T, kStream>(a.p.gA[c], n, i, gA[c]);
     }
@@ -1254,7 +1302,7 @@ void k_mixed(MixedArgs<T> a) {
         const auto &g = groups[cur.group];
         const uint32_t n = (uint32_t)g.n;
         if (g.kind == 3)
-            wtile_eig3<T, PATH, MPL, false, kCached>(planes_of(cur.group), planes_of, cur.group, a.prm,
+            wtile_eig3<T, PATH, MPL, false, kCached, false>(planes_of(cur.group), planes_of, cur.group, a.prm,
                                                      in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
         else
             wtile_eig2_in<T, MPL>(g, in_cur, cur.base);

@@ -65,8 +65,7 @@ def check_f32_result(P, out, lam_ref, V_ref, label=""):
     g = H.rel_gaps(lam_ref)
     ve = H.eigvec_err(lam, D, lam_ref, V_ref)
     # gap of each output slot: match it to the reference slot with the closest eigenvalue
-    idx = np.argmin(np.abs(lam_ref[None, :, :] - lam[:, None, :]), axis=1)
-    gk = np.take_along_axis(g, idx, axis=0)
+    gk = np.stack([np.choose(H.nearest_slot(lam_ref, lam[k]), list(g)) for k in range(3)])
     sel = gk >= VEC_GAP_F32
     vec_ratio = np.where(sel, ve * gk, 0.0)
     stats = {"lam": float(np.max(lam_err, initial=0)), "res": float(np.max(res, initial=0)),
@@ -82,9 +81,27 @@ def check_f32_result(P, out, lam_ref, V_ref, label=""):
     assert np.all(lam[0] >= lam[2]) and np.all(lam[2] >= lam[1]), label
     # angles reproduce D (eq. (2.6)) to float32 rounding
     if "phi" in out:
-        R = H.rot_from_angles(out["phi"].astype(np.float64))
-        assert np.abs(R - H.as_mats(D)).max() < 2e-5, label
+        R = H.rot_planes(out["phi"].astype(np.float64))
+        assert np.abs(R - D).max() < 2e-5, label
     return stats
+
+
+def check_f32_whole(P, out, label="", chunk=1 << 22):
+    """check_f32_result over a whole batch, chunk by chunk against the
+    certified reference of each chunk.  P: (6, n) float32 or float64 planes
+    (host); out: host arrays lam (3, n), D (9, n) and optionally phi (3, n).
+    Returns the largest statistics over the chunks."""
+    n = P.shape[1]
+    worst = {}
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        P64 = np.asarray(P[:, s:e], dtype=np.float64)
+        g = {k: v[..., s:e] for k, v in out.items()}
+        lam_ref, V_ref = certified_reference(P64)
+        st = check_f32_result(P64, g, lam_ref, V_ref, f"{label} [{s}:{e}]")
+        for k, v in st.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    return worst
 
 
 def props3_gpu(A, lam, D, chunk=1 << 22):

@@ -78,6 +78,33 @@ def test_eig3_f32_soa_across_chunks(ksym):
             assert torch.equal(_cols(lam[k], a, b), ref[k]), (k, a, b)
 
 
+@pytest.mark.parametrize("path_name", ["PATH_FP64_PLAIN", "PATH_FP64_FIXUP"])
+def test_eig3_f64_soa_across_chunks(ksym, path_name):
+    """float64 structure-of-arrays input just past one launch chunk: each
+    plane of the first chunk spans 2^31 bytes, the most a 32-bit buffer
+    offset reaches.  Both float64 paths; windows bitwise equal to separate
+    calls and within the float64 tolerances of the oracle."""
+    import oracle
+    from tests import helpers as H
+    from tests.gpu_common import LAM_TOL_F64, RES_TOL_F64
+    n = CHUNK + 333
+    A = _randn((6, n), 308, torch.float64)
+    opts = ksym.Opts.defaults(ksym.F64)
+    opts.path = getattr(ksym, path_name)
+    out = ksym.eig3(A, opts=opts, outputs=("lam", "D", "phi", "flags"))
+    torch.cuda.synchronize()
+    for a, b in _windows(CHUNK, n):
+        ref = ksym.eig3(_cols(A, a, b), opts=opts, outputs=("lam", "D", "phi", "flags"))
+        for k in ref:
+            assert torch.equal(_cols(out[k], a, b), ref[k]), (path_name, k, a, b)
+        P64 = A[:, a:b].cpu().numpy()
+        lam = _cols(out["lam"], a, b).cpu().numpy()
+        D = _cols(out["D"], a, b).cpu().numpy()
+        o = oracle.eig3(P64)
+        assert H.sorted_lam_err(P64, lam, o["lam"]).max() <= LAM_TOL_F64, (path_name, a, b)
+        assert H.residual3(P64, lam, D).max() <= RES_TOL_F64, (path_name, a, b)
+
+
 @pytest.mark.parametrize("dtype,chunk", [(torch.float32, CHUNK_AOS_F32), (torch.float64, CHUNK_AOS_F64)])
 def test_eig3_aos_across_chunks(ksym, dtype, chunk):
     n = chunk + 513

@@ -10,7 +10,7 @@ import pytest
 import oracle
 import synth
 from tests import helpers as H
-from tests.gpu_common import (DET_TOL_F32, ORTH_TOL_F32, RES_TOL_F32, certified_reference,
+from tests.gpu_common import (DET_TOL_F32, ORTH_TOL_F32, RES_TOL_F32, certified_reference, check_f32_whole,
                               check_f32_result, props2_gpu, props3_gpu, to_dev, to_np)
 
 pytestmark = pytest.mark.gpu
@@ -225,21 +225,92 @@ def test_backward_f64_matches_oracle_adjoint(ksym):
 
 
 def _aligned_reference(P64, lam_g, D_g):
-    """Reference eigenpairs of the stored matrices in the GPU result's slots,
-    each reference eigenvector signed like the GPU's column."""
+    """Reference eigenpairs of the stored matrices (certified_reference) in the
+    GPU result's slots -- both are in the slot order (max, min, mid), so slot k
+    of one is slot k of the other -- with each reference eigenvector signed
+    like the GPU's column."""
     lam_ref, V_ref = certified_reference(P64)
-    Dg = H.as_mats(D_g)
-    Vr = H.as_mats(V_ref)
-    n = P64.shape[1]
-    L = np.empty((3, n))
-    V = np.empty((n, 3, 3))
+    L = np.asarray(lam_ref, dtype=np.float64)
+    assert np.all(L[0] >= L[2]) and np.all(L[2] >= L[1])
+    V = np.array(V_ref, dtype=np.float64)
+    D = np.asarray(D_g, dtype=np.float64)
     for k in range(3):
-        j = np.argmin(np.abs(lam_ref - lam_g[k][None, :]), axis=0)
-        L[k] = lam_ref[j, np.arange(n)]
-        v = Vr[np.arange(n), :, j]
-        s = np.sign(np.einsum("ni,ni->n", v, Dg[:, :, k]))
-        V[:, :, k] = v * np.where(s == 0, 1, s)[:, None]
-    return L, V.reshape(n, 9).T
+        s = np.sign(V[k] * D[k] + V[3 + k] * D[3 + k] + V[6 + k] * D[6 + k])
+        s = np.where(s == 0, 1.0, s)
+        for i in range(3):
+            V[3 * i + k] *= s
+    return L, V
+
+
+def _oracle_adjoint_rel_eps(L, V, w, G, lam_g, eps_rel=1e-6):
+    """The oracle adjoint with the GPU adjoint's regulariser eps = eps_rel
+    sqrt(sum lam_gpu^2), which differs per matrix, while the oracle takes one
+    absolute eps: F_ij = d/(d^2 + eps^2) with d = lam_j - lam_i satisfies
+    F(lam, eps) = F(lam / f, eps / f) / f, and E = D^T Dbar is linear in Dbar,
+    so the oracle is called with lam / f, Dbar / f and eps_rel, f = the
+    matrix's sqrt(sum lam_gpu^2) (1 for a zero matrix)."""
+    lg = np.asarray(lam_g, dtype=np.float64)
+    f = np.sqrt((lg * lg).sum(0))
+    f = np.where(f > 0, f, 1.0)
+    return oracle.eig3_bwd(L / f, V, np.asarray(w, dtype=np.float64), np.asarray(G, dtype=np.float64) / f,
+                           eps=eps_rel)
+
+
+def _f32_floor(L, V, w, G, lam_g, ref):
+    """Per matrix, the relative gradient error that rounding the exact
+    eigenvectors to float32 alone produces, to first order: the sensitivity
+    of the oracle adjoint to a perturbation of V in each of the nine
+    directions V (I + delta P) -- a rotation, a symmetric shear or a column
+    scaling (P = E_jk - E_kj, E_jk + E_kj, E_kk) -- times the float32 unit
+    roundoff 2^-24 of D's entries, combined in quadrature.  Where the
+    gradient is this ill-conditioned (a small gap whose term F_jk (E_jk -
+    E_kj) nearly cancels), no float32 D can give it to 1e-4."""
+    u = 2.0 ** -24
+    delta = 1e-7
+    nr = np.linalg.norm(ref, axis=0)
+    nr = np.where(nr > 0, nr, 1.0)
+    Vm = [[V[3 * i + k] for k in range(3)] for i in range(3)]
+    acc = np.zeros(nr.shape)
+    gens = [(j, k, s) for j, k in ((0, 1), (0, 2), (1, 2)) for s in (-1.0, 1.0)] + [(k, k, 1.0) for k in range(3)]
+    for j, k, sg in gens:
+        P = np.zeros((3, 3))
+        P[j, k] += 1.0
+        P[k, j] += sg if j != k else 0.0
+        Vp = np.empty_like(V)
+        for i in range(3):
+            for c in range(3):
+                Vp[3 * i + c] = Vm[i][c] + delta * sum(Vm[i][r] * P[r, c] for r in range(3))
+        rp = _oracle_adjoint_rel_eps(L, Vp, w, G, lam_g)
+        acc += (np.linalg.norm(rp - ref, axis=0) / nr / delta) ** 2
+    return u * np.sqrt(acc)
+
+
+def _gradient_vs_oracle(P, lam_g, D_g, gA, w, G, label, chunk=1 << 22, tol=1e-4, floor=False):
+    """Per matrix ||gA - gA_ref||_F <= tol ||gA_ref||_F over a whole batch,
+    gA_ref the oracle adjoint on the certified eigenpairs aligned to the GPU's
+    slots and signs, with the GPU's regulariser.  With floor, the bound per
+    matrix is tol + 2 x the float32 floor of _f32_floor.  Host arrays; returns
+    (largest relative error, matrices whose floor term exceeds tol)."""
+    n = P.shape[1]
+    worst = 0.0
+    floored = 0
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        P64 = np.asarray(P[:, s:e], dtype=np.float64)
+        L, V = _aligned_reference(P64, lam_g[:, s:e], D_g[:, s:e])
+        ref = _oracle_adjoint_rel_eps(L, V, w[:, s:e], G[:, s:e], lam_g[:, s:e])
+        got = np.asarray(gA[:, s:e], dtype=np.float64)
+        nr = np.linalg.norm(ref, axis=0)
+        rel = np.linalg.norm(got - ref, axis=0) / np.where(nr > 0, nr, 1.0)
+        worst = max(worst, float(rel.max()))
+        bound = np.full(rel.shape, tol)
+        if floor:
+            fl = _f32_floor(L, V, w[:, s:e], G[:, s:e], lam_g[:, s:e], ref)
+            bound = bound + 2.0 * fl
+            floored += int(np.sum(2.0 * fl > tol))
+        bad = rel > bound
+        assert not bad.any(), (label, s, int(bad.sum()), float(rel.max()), int(np.argmax(rel)) + s)
+    return worst, floored
 
 
 def test_gradient_workload_f32(ksym):
@@ -247,15 +318,15 @@ def test_gradient_workload_f32(ksym):
     loss sum w*lam + sum G*D) at 2^16 matrices: float32 forward + adjoint on
     the GPU against the oracle adjoint evaluated on the exact eigenpairs (signs
     aligned to the GPU's), per matrix ||dA - dA_ref||_F <= 1e-4 ||dA_ref||_F.
-    The float32 closed form leaves eigenvector angle errors of up to about
-    1e-6 ||A||_F / gap, and the gradient's 1/(lam_i - lam_j) terms magnify
-    them; the forward therefore certifies every pair to first order,
-    |d_j^T A d_k| <= tau_vec |lam_j - lam_k| with tau_vec = 5e-6, and routes
-    the rest (~2 %) to the float64 refinement."""
+    The float32 closed form leaves eigenvector rotations of about
+    1e-8 ||A||_F / gap, and the gradient's 1/(lam_i - lam_j) terms magnify
+    them; the differentiated forward (tau_vec > 0) therefore removes each
+    pair's first-order rotation in float64 and refines the matrices whose
+    rotation exceeds tau_vec = 1e-4."""
     n = 1 << 16
     d = synth.make_grad(n, seed=204)
     P32 = d["planes3"]
-    opts = ksym.Opts.defaults(ksym.F32, tau_vec=5e-6)
+    opts = ksym.Opts.defaults(ksym.F32, tau_vec=1e-4)
     A = to_dev(P32, torch.float32)
     out = ksym.eig3(A, opts=opts, outputs=("lam", "D", "gap", "flags"))
     gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
@@ -527,11 +598,12 @@ def test_field_workload_aos_forward_backward(ksym):
 
 
 # --------------------------------------- full-size precision workload -----
-def test_precision_workload_full_size_sampled(ksym):
+def test_precision_workload_full_size(ksym):
     """2^24 matrices of the precision recipe in the launch configuration the
     benchmark times: every matrix checked for residual, orthogonality, det and
-    slot order on the GPU in float64; 2^15 sampled matrices checked one by one
-    against the certified reference with the float32 tolerances."""
+    slot order on the GPU in float64, and every matrix against the certified
+    reference with the float32 tolerances (eigenvalues; eigenvectors up to sign
+    where the relative gap is at least 1e-2; the angles reproduce D)."""
     n = 1 << 24
     P32 = synth.make_precision(n)
     A = to_dev(P32, torch.float32)
@@ -541,36 +613,32 @@ def test_precision_workload_full_size_sampled(ksym):
     pr = props3_gpu(A, out["lam"], out["D"])
     assert pr["order"], pr
     assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
-    rng = np.random.default_rng(209)
-    idx = np.sort(rng.choice(n, size=1 << 15, replace=False))
-    P64 = P32[:, idx].astype(np.float64)
-    lam_ref, V_ref = certified_reference(P64)
-    ti = torch.from_numpy(idx).cuda()
-    g = {k: v[:, ti].cpu().numpy() if v.dim() == 2 else v[ti].cpu().numpy() for k, v in out.items()}
-    check_f32_result(P64, g, lam_ref, V_ref, "full-size sample")
+    del A
+    host = {k: out[k].cpu().numpy() for k in ("lam", "D", "phi")}
+    del out
+    st = check_f32_whole(P32, host, "precision full size")
+    print("precision full size:", st, flush=True)
 
 
 # ------------------------------ full-size mixed, gradient and field workloads -----
-def test_mixed_workload_full_size_sampled(ksym):
+def test_mixed_workload_full_size(ksym):
     """2^26 mixed matrices (30 % 2x2, 70 % 3x3, N(0,1) entries) in 1024 groups
     of log-uniform sizes, run as the benchmark runs them: one plan with the
     tuned options, captured in a HIP graph and replayed.  Every matrix of every
     group is checked on the GPU in float64 (residual, orthogonality, det and
-    slot order for 3x3; residual and D = R(phi) for 2x2); 8 sampled matrices
-    per group are checked one by one against the oracle with the float32
-    tolerances."""
+    slot order for 3x3; residual and D = R(phi) for 2x2), and every matrix
+    against the reference: 3x3 against the certified reference with the
+    float32 tolerances, 2x2 against the oracle (eigenvalues within 2e-6
+    ||A||_F, angles within 1e-6)."""
     total = 1 << 26
     sizes, kinds = synth.mixed_group_sizes(total)
     rng = np.random.default_rng(synth.BASE_SEED + 1002)
-    pick = np.random.default_rng(210)
-    groups, samples = [], []
+    groups, host = [], []
     for s, k in zip(sizes, kinds):
         s, k = int(s), int(k)
         P = rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)
-        idx = np.sort(pick.choice(s, size=min(8, s), replace=False))
-        samples.append((idx, P[:, idx].copy()))
+        host.append(P)
         t = to_dev(P, torch.float32)
-        del P
         if k == 3:
             out = {"lam": torch.empty((3, s), device="cuda"), "D": torch.empty((9, s), device="cuda"),
                    "phi": torch.empty((3, s), device="cuda")}
@@ -585,9 +653,10 @@ def test_mixed_workload_full_size_sampled(ksym):
     torch.cuda.synchronize()
     plan.replay(torch.cuda.current_stream())
     torch.cuda.synchronize()
-    s3 = {"P": [], "lam": [], "D": [], "phi": []}
-    s2 = {"P": [], "lam": [], "D": [], "phi": []}
-    for (k, t, out), (idx, Ps) in zip(groups, samples):
+    r3 = {"lam": [], "D": [], "phi": []}
+    r2 = {"lam": [], "D": [], "phi": []}
+    P3, P2 = [], []
+    for (k, t, out), P in zip(groups, host):
         if k == 3:
             pr = props3_gpu(t, out["lam"], out["D"])
             assert pr["order"], pr
@@ -595,80 +664,91 @@ def test_mixed_workload_full_size_sampled(ksym):
         else:
             pr = props2_gpu(t, out["lam"], out["D"], out["phi"])
             assert pr["res"] <= RES_TOL_F32 and pr["rot"] <= 3e-7 and pr["phi_abs"] <= math.pi / 4 + 1e-6, pr
-        ti = torch.from_numpy(idx).cuda()
-        acc = s3 if k == 3 else s2
-        acc["P"].append(Ps)
+        acc = r3 if k == 3 else r2
+        (P3 if k == 3 else P2).append(P)
         for key in ("lam", "D", "phi"):
-            v = out[key]
-            acc[key].append((v[:, ti] if v.dim() == 2 else v[ti]).cpu().numpy())
+            acc[key].append(out[key].cpu().numpy())
     plan.close()
-    g3 = {key: np.concatenate(v, axis=-1) for key, v in s3.items()}
-    P64 = g3.pop("P").astype(np.float64)
-    lam_ref, V_ref = certified_reference(P64)
-    check_f32_result(P64, g3, lam_ref, V_ref, "mixed full-size 3x3 sample")
-    g2 = {key: np.concatenate(v, axis=-1) for key, v in s2.items()}
-    P64 = g2.pop("P").astype(np.float64)
+    del groups
+    g3 = {key: np.concatenate(v, axis=-1) for key, v in r3.items()}
+    st = check_f32_whole(np.concatenate(P3, axis=1), g3, "mixed full size 3x3")
+    print("mixed full size 3x3:", st, flush=True)
+    del g3, P3
+    g2 = {key: np.concatenate(v, axis=-1) for key, v in r2.items()}
+    P64 = np.concatenate(P2, axis=1).astype(np.float64)
     ref = oracle.eig2(P64)
-    A2 = _mats2(P64)
-    f = np.linalg.norm(A2.reshape(-1, 4), axis=1)
-    lam_err = (np.abs(g2["lam"].astype(np.float64) - ref["lam"]).max(0) / f).max()
+    f = np.sqrt(P64[0] ** 2 + P64[1] ** 2 + 2 * P64[2] ** 2)
+    lam_err = (np.abs(g2["lam"].astype(np.float64) - ref["lam"]).max(0) / np.where(f > 0, f, 1)).max()
     phi_err = np.abs(g2["phi"].astype(np.float64) - ref["phi"]).max()
     assert lam_err < 2e-6 and phi_err < 1e-6, (lam_err, phi_err)
 
 
-def test_gradient_workload_full_size_sampled(ksym):
+def test_gradient_workload_full_size(ksym):
     """2^22 matrices of the gradient recipe in the benchmark's launch
-    configuration (tuned options with the pair certificate tau_vec, outputs
-    lam, D and the gaps, then the adjoint with the saved gaps).  Every
-    forward result is checked on the GPU in float64; 2^12 sampled matrices
-    are checked against the certified reference, and their gradients against
-    the oracle adjoint on the exact eigenpairs (signs aligned to the GPU's),
-    per matrix ||dA - dA_ref||_F <= 1e-4 ||dA_ref||_F."""
+    configuration (tuned options with the float64 pair correction, outputs
+    lam, D and the gaps, then the adjoint with the saved gaps), and the same
+    loss through eig3_autograd with its default options.  Every forward
+    result is checked on the GPU in float64 and against the certified
+    reference; every matrix's gradient against the oracle adjoint on the
+    certified eigenpairs (slots and signs aligned to the GPU's, the GPU's
+    regulariser), per matrix ||dA - dA_ref||_F <= 1e-4 ||dA_ref||_F.  The
+    autograd gradient equals the explicit one bitwise."""
     n = 1 << 22
     d = synth.make_grad(n)
     A = to_dev(d["planes3"], torch.float32)
+    w, G = to_dev(d["w"], torch.float32), to_dev(d["G"], torch.float32)
     opts = ksym.tuned_opts("eig3_grad", ksym.F32)
     out = {"lam": torch.empty((3, n), device="cuda"), "D": torch.empty((9, n), device="cuda"),
            "gap": torch.empty((3, n), device="cuda")}
     ksym.eig3(A, opts=opts, out=out)
-    gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
-                            to_dev(d["G"], torch.float32), gap=out["gap"])
+    gA = ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"])
     torch.cuda.synchronize()
     pr = props3_gpu(A, out["lam"], out["D"])
     assert pr["order"], pr
     assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
     assert bool(torch.isfinite(gA).all())
-    idx = np.sort(np.random.default_rng(211).choice(n, size=1 << 12, replace=False))
-    ti = torch.from_numpy(idx).cuda()
-    P64 = d["planes3"][:, idx].astype(np.float64)
-    g = {k: out[k][:, ti].cpu().numpy() for k in ("lam", "D")}
-    lam_ref, V_ref = certified_reference(P64)
-    check_f32_result(P64, g, lam_ref, V_ref, "gradient full-size sample")
-    L, V = _aligned_reference(P64, g["lam"].astype(np.float64), g["D"].astype(np.float64))
-    ref = oracle.eig3_bwd(L, V, d["w"][:, idx].astype(np.float64), d["G"][:, idx].astype(np.float64), eps=0.0)
-    got = gA[:, ti].cpu().numpy()
-    rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
-    assert rel.max() <= 1e-4, (rel.max(), np.percentile(rel, 99.9))
+    # the same loss through autograd with the default options
+    Ag = A.clone().requires_grad_(True)
+    lam_a, D_a = ksym.eig3_autograd(Ag)
+    ((w * lam_a).sum() + (G * D_a).sum()).backward()
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a.detach(), out["lam"]) and torch.equal(D_a.detach(), out["D"])
+    assert torch.equal(Ag.grad, gA)
+    host = {k: out[k].cpu().numpy() for k in ("lam", "D")}
+    check_f32_whole(d["planes3"], host, "gradient full size")
+    worst, _ = _gradient_vs_oracle(d["planes3"], host["lam"], host["D"], gA.cpu().numpy(), d["w"], d["G"],
+                                   "gradient full size")
+    print("gradient full size: max relative gradient error", worst, flush=True)
 
 
-def test_field_workload_full_size_sampled(ksym):
+def test_field_workload_full_size(ksym):
     """The 256^3 tensor field in the benchmark's launch configuration
-    (array-of-structures input, tuned options, outputs lam, D and the gaps,
-    then the adjoint with the saved gaps).  Every voxel is checked on the GPU
-    in float64; isotropic voxels come out exactly as lam I with D = I; 2^13
-    sampled voxels are checked against the certified reference, and 2^11 of
-    their gradients against the oracle adjoint on the same outputs."""
+    (array-of-structures input, tuned options with the float64 pair
+    correction (tau_vec), outputs lam, D and the gaps, then the adjoint with the saved
+    gaps).  Every voxel is checked on the GPU in float64 and against the
+    certified reference; isotropic voxels come out exactly as lam I with
+    D = I; every voxel's gradient against the oracle adjoint on the certified
+    eigenpairs (slots and signs aligned to the GPU's, the GPU's regulariser),
+    per voxel ||dA - dA_ref||_F <= (1e-4 + 2 f) ||dA_ref||_F, f the error
+    that rounding the exact eigenvectors to float32 alone gives that voxel's
+    gradient (_f32_floor; 2 f exceeds 1e-4 only where a small gap meets a
+    nearly cancelling cotangent, about 2e-5 of the voxels) -- the
+    isotropic voxels, where D is not differentiable, at the same regularised
+    formula."""
     nx = 256
     d = synth.make_field(nx, nx, nx)
     n = nx ** 3
     rec = to_dev(d["aos"], torch.float32)
     opts = ksym.tuned_opts("eig3_aos", ksym.F32)
+    assert opts.tau_vec > 0, "the field's forward corrects eigenvector pairs for its gradients"
     out = {"lam": torch.empty((3, n), device="cuda"), "D": torch.empty((9, n), device="cuda"),
            "gap": torch.empty((3, n), device="cuda")}
-    ksym.eig3_aos(rec, opts=opts, out=out)
+    ws = ksym.workspace()
+    ksym.eig3_aos(rec, opts=opts, out=out, ws=ws)
     gA = ksym.eig3_backward(out["lam"], out["D"], to_dev(d["w"], torch.float32),
                             to_dev(d["G"], torch.float32), gap=out["gap"])
     torch.cuda.synchronize()
+    print("field: refined fraction", int(ws[0].item()) / n, flush=True)
     pr = props3_gpu(rec.T, out["lam"], out["D"])
     assert pr["order"], pr
     assert pr["res"] <= RES_TOL_F32 and pr["orth"] <= ORTH_TOL_F32 and pr["det"] <= DET_TOL_F32, pr
@@ -677,18 +757,16 @@ def test_field_workload_full_size_sampled(ksym):
     eye = torch.tensor([1, 0, 0, 0, 1, 0, 0, 0, 1], dtype=torch.float32, device="cuda")[:, None]
     assert bool((out["D"][:, iso] == eye).all())
     assert bool((out["lam"][:, iso] == rec[iso, 0][None, :]).all())
-    pick = np.random.default_rng(212)
-    idx = np.sort(pick.choice(n, size=1 << 13, replace=False))
-    ti = torch.from_numpy(idx).cuda()
-    P64 = d["aos"][idx].T.astype(np.float64)
-    g = {k: out[k][:, ti].cpu().numpy() for k in ("lam", "D")}
-    lam_ref, V_ref = certified_reference(P64)
-    check_f32_result(P64, g, lam_ref, V_ref, "field full-size sample")
-    sub = idx[:: 4]
-    ref = _oracle_adjoint_at(out, d["w"], d["G"], sub)
-    got = gA[:, torch.from_numpy(sub).cuda()].cpu().numpy()
-    rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
-    assert rel.max() < 1e-4, rel.max()
+    del rec
+    host = {k: out[k].cpu().numpy() for k in ("lam", "D")}
+    del out
+    P32 = np.ascontiguousarray(d["aos"].T)
+    check_f32_whole(P32, host, "field full size")
+    worst, floored = _gradient_vs_oracle(P32, host["lam"], host["D"], gA.cpu().numpy(), d["w"], d["G"],
+                                         "field full size", floor=True)
+    print("field full size: max relative gradient error", worst, "voxels whose float32 floor exceeds 1e-4:",
+          floored, flush=True)
+    assert floored <= n // 10000, floored   # 345 of 2^24 voxels (2e-5) at the time of writing
 
 
 # ------------------------------------------------------- usage example -----
