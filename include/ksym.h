@@ -68,7 +68,11 @@ extern "C" {
 
 #define KSYM_VERSION 100   /* 1.0.0 */
 
-typedef enum { KSYM_F32 = 0, KSYM_F64 = 1 } ksym_dtype;
+/* Element type of the planes.  A plain integer type (not an enum), so that
+   any value a caller passes is a valid argument and an unknown one is
+   rejected (KSYM_E_DTYPE) rather than undefined. */
+typedef int32_t ksym_dtype;
+enum { KSYM_F32 = 0, KSYM_F64 = 1 };
 
 typedef enum {
     KSYM_OK = 0,
@@ -121,8 +125,12 @@ typedef enum {
  *                  per wave) below about 2^18 tiles, which measured fastest.
  *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
  *                  below which a matrix always takes the refinement (0 = off).
- *   tau_res        refinement if some residual ||A d_k - lam_k d_k|| exceeds
- *                  tau_res * ||A||_F.
+ *   tau_res        refinement if the residuals r_k = A d_k - lam_k d_k are too
+ *                  large: float32 path, ||r_0||^2 + ||r_1||^2 > (tau_res
+ *                  ||A||_F)^2 (the third residual then stays within sqrt(2)
+ *                  tau_res ||A||_F, as it follows from the first two for
+ *                  orthonormal D); float64 paths, some ||r_k|| > tau_res
+ *                  ||A||_F.
  *   tau_vec        differentiated calls (0 = off): the first-order rotation
  *                  T_jk of each pair of columns of D against the true
  *                  eigenvectors, T_jk (lam_j - lam_k) = d_j^T A d_k -

@@ -61,6 +61,11 @@ __device__ __forceinline__ int scale_exponent(double amax) {
     if (amax > 0.0 && __builtin_isfinite(amax)) (void)__builtin_frexp(amax, &e);
     return e;
 }
+__device__ __forceinline__ int scale_exponent_f(float amax) {
+    int e = 0;
+    if (amax > 0.0f && __builtin_isfinite(amax)) (void)__builtin_frexpf(amax, &e);
+    return e;
+}
 
 // ------------------------------------------------ polynomial kernels -----
 // Coefficients and their derivation: ksym_poly.hpp / gen_poly.py.
@@ -556,10 +561,16 @@ template <typename T> __device__ __forceinline__ void angles_of(const Rot<T>& R,
 // float32: phi2 and phi3 lie in [-pi/2, pi/2] (non-negative cosines c2 =
 // sqrt(v), c3 = sqrt(w)), so each is +-asin of the smaller of its sine and
 // cosine, from the squared values the angle solve already has; a sine of -0
-// gives +0 like the general atan2.
+// gives +0 like the general atan2.  phi1 is folded from the same arcsine of
+// its unit vector's smaller component.
 __device__ __forceinline__ void angles_of(const Rot<float>& R, float v, float s2sq, float w, float cw,
                                           float phi[3]) {
-    phi[0] = atan2_fast(R.s1, R.c1);
+    // phi1 in (-pi, pi] from the unit vector (c1, s1): the angle of
+    // (|c1|, |s1|) in [0, pi/2] from the squares, then folded into its
+    // quadrant (a sine of -0 counts as +0, as in atan2_fast)
+    const float t1 = angle_from_squares(__builtin_fabsf(R.s1), R.s1 * R.s1, __builtin_fabsf(R.c1), R.c1 * R.c1);
+    const float q1 = R.c1 < 0.0f ? 3.14159265358979324f - t1 : t1;
+    phi[0] = R.s1 < 0.0f ? -q1 : q1;
     const float t2 = angle_from_squares(__builtin_fabsf(R.s2), s2sq, R.c2, v);
     const float t3 = angle_from_squares(__builtin_fabsf(R.s3), cw, R.c3, w);
     phi[1] = R.s2 < 0.0f ? -t2 : t2;
@@ -622,6 +633,31 @@ __device__ __forceinline__ bool check_fails(C d1, C d2, C d3, C a12, C a13, C a2
         bad |= !(r0 * r0 + r1 * r1 + r2 * r2 <= lim2);
     }
     return bad;
+}
+
+// The float32 check on two columns.  For orthonormal columns d0, d1, d2 the
+// third residual follows from the first two: its components along d0 and d1
+// are r0 . d2 and r1 . d2 (B is symmetric), and along d2 it is
+// tr(B) - (mu0 + mu1 + mu2) - r0 . d0 - r1 . d1, where tr(B) and the sum of
+// the deviations both vanish (up to rounding).  Hence ||r2||^2 <= ||r0||^2 +
+// ||r1||^2 + (r0 . d0)^2 + (r1 . d1)^2 <= 2 (||r0||^2 + ||r1||^2), and the
+// test ||r0||^2 + ||r1||^2 <= lim2 bounds every residual: columns 0 and 1 by
+// sqrt(lim2), column 2 by sqrt(2 lim2) (float32 rounding of D and B adds
+// about 1e-7 ||A||_F).  A wrong eigenvector or a wrong pairing with mu_k in
+// any column shows in r0 or r1, since d2 is fixed by d0 and d1.
+__device__ __forceinline__ bool check2_fails(float d1, float d2, float d3, float a12, float a13, float a23,
+                                             const float d[9], float mu1, float mu2, float lim2) {
+    const float mu[2] = {mu1, mu2};
+    float n2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float x = d[k], y = d[3 + k], z = d[6 + k];
+        const float r0 = (d1 - mu[k]) * x + a12 * y + a13 * z;
+        const float r1 = a12 * x + (d2 - mu[k]) * y + a23 * z;
+        const float r2 = a13 * x + a23 * y + (d3 - mu[k]) * z;
+        n2 += r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    return !(n2 <= lim2);
 }
 
 // First-order pair correction for differentiated calls (tau_vec > 0), in

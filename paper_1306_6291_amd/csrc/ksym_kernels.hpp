@@ -198,7 +198,7 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     amax = __builtin_fmaxf(amax, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[3]),
                                                                  __builtin_fabsf(ain[4])),
                                                  __builtin_fabsf(ain[5])));
-    const int ex = scale_exponent((double)amax);
+    const int ex = scale_exponent_f(amax);
     double a[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) a[c] = sc2((double)ain[c], -ex);
@@ -265,8 +265,8 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     sink.template put_n<9>(O_D, D);
     // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
     const float fro2 = (float)__builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
-    bad = bad || check_fails<float>((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
-                                    (float)cu.mu1, (float)cu.mu2, (float)cu.mu3, prm.tau_res2_f * fro2);
+    bad = bad || check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D, (float)cu.mu1,
+                              (float)cu.mu2, prm.tau_res2_f * fro2);
     refine = bad;
     return flag;
 }
@@ -900,7 +900,7 @@ __device__ __forceinline__ int eig3_lam_f32(const float ain[6], const Eig3Params
     amax = __builtin_fmaxf(amax, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(ain[3]),
                                                                  __builtin_fabsf(ain[4])),
                                                  __builtin_fabsf(ain[5])));
-    const int ex = scale_exponent((double)amax);
+    const int ex = scale_exponent_f(amax);
     double a[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) a[c] = sc2((double)ain[c], -ex);

@@ -318,6 +318,28 @@ def test_all_matrices_refined_f32(ksym):
         check_f32_result(P64, g, lam_ref, V_ref, f"all-refined {block}x{mpl}")
 
 
+def test_eigenvalues_and_angles_mode_f32(ksym):
+    """Reduced-output mode lam + phi (no D planes, 48 B per matrix): the
+    angles alone determine D (eq. (2.6)), so a caller can drop D's 36 B.  The
+    kernel still forms D in registers for the check and the refinement, so
+    lam, phi, gap and flags are bitwise the full path's for every matrix
+    (refined ones included), and R1 R2 R3 (phi) meets the float32 tolerances
+    against the certified reference: eigenvalues, residual, orthogonality and
+    eigenvectors up to sign where the relative gap is at least 1e-2."""
+    n = (1 << 17) + 77
+    P32 = synth.make_precision(n, seed=1306632)
+    P64 = P32.astype(np.float64)
+    full = _run(ksym, P32, torch.float32)
+    lp = _run(ksym, P32, torch.float32, outputs=("lam", "phi", "gap", "flags"))
+    assert "D" not in lp
+    for k in ("lam", "phi", "gap", "flags"):
+        assert np.array_equal(lp[k], full[k]), k
+    assert int(lp["ws"][0]) == int(full["ws"][0]) > 0
+    lam_ref, V_ref = certified_reference(P64)
+    g = {"lam": lp["lam"], "D": H.rot_planes(lp["phi"].astype(np.float64)).astype(np.float32)}
+    check_f32_result(P64, g, lam_ref, V_ref, "lam + phi mode, D from the angles")
+
+
 def test_optional_outputs(ksym):
     P32 = synth.make_plain(3000, 16, seed=8, dtype=np.float32)["planes3"]
     full = _run(ksym, P32, torch.float32)
