@@ -6,19 +6,28 @@ Default workload (one step = one pass of the 3x3 forward path over the batch):
 near-degenerate with relative gaps log-uniform in [1e-7, 1e-3], 1 % exactly
 repeated, diagonal and zero matrices), structure-of-arrays planes resident in
 HBM; outputs lam, D and the angles.  The float32 path computes the cubic step
-in float64, the angle solve in float32, checks every D in float64 and refines
-the failing matrices in float64 inside the same kernel.
+in float64, the angle solve in float32, checks every D and refines the
+failing matrices in float64 inside the same kernel.
+
+Order: the inputs are generated and copied to the device; one forward with
+the flags and counters runs and its result is checked (residual and
+orthogonality of every matrix on the GPU, eigenvalues against LAPACK on a
+sample); then the warmup steps and the timed steps of the headline.
 
 Printed: one JSON line with matrices/s, the roofline of the kernel (HBM,
-algorithmic bytes 84 per matrix), the CPU oracle's throughput on the host cores,
-the float64 GPU path on the same matrices, accuracy on a sample, the median
-and minimum of single launches, and the throughput at two further seeds of the
-same recipe (timed step only; --seeds).
+algorithmic bytes 84 per matrix), the CPU oracle's throughput on the host
+cores, the float64 GPU paths on the same matrices, the accuracy, the median
+and minimum of single launches, a steady-state figure taken after at least
+0.2 s of further launches, the reduced-output modes (eigenvalues only;
+eigenvalues and angles), the throughput at two further seeds of the same
+recipe, and the other workloads of the library (below), each with its
+algorithmic bytes and fraction of the HBM roof.
 
-Other workloads for measurement (--workload): mixed (2^26 mixed 2x2/3x3 in
-1024 groups, one persistent launch replayed from a HIP graph), grad (2^22
-forward + backward), field (256^3 array-of-structures tensor field, forward +
-backward), copy (a device copy of known size, for counter calibration).
+Other workloads (--workload for a line of their own; in the default line
+under "workloads"): mixed (2^26 mixed 2x2/3x3 in 1024 groups, one persistent
+launch replayed from a HIP graph), grad (2^22 forward + backward), field
+(256^3 array-of-structures tensor field, forward + backward), copy (a device
+copy of known size, for counter calibration).
 """
 
 from __future__ import annotations
@@ -40,6 +49,7 @@ VALU_PEAK_TLANE = 256 * 64 * 2.4e9 / 1e12   # 39.3 T lane-instructions/s
 BYTES_3X3_F32 = 84      # 24 in + 60 out (lam 12, D 36, phi 12)
 BYTES_3X3_F64 = 168
 BYTES_3X3_LAM_F32 = 36  # eigenvalues-only mode: 24 in + 12 out (lam)
+BYTES_3X3_LAMPHI_F32 = 48   # eigenvalues and angles, no D: 24 in + 24 out
 BYTES_2X2_F32 = 40      # 12 in + 28 out (lam 8, D 16, phi 4)
 BYTES_BWD_F32 = 120     # lam 12 + D 36 + glam 12 + gD 36 in, gA 24 out
 
@@ -136,6 +146,28 @@ def _step_stats(fn, steps, torch):
     return {"median": float(np.median(t)), "min": float(t.min()), "steps": steps}
 
 
+def _warm(fn, torch, seconds):
+    """Untimed calls for at least `seconds` of wall time (the GPU's clocks
+    rise over about 0.1 s of work)."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def _timed_after_warm(fn, steps, torch, seconds=0.2):
+    """Mean ms of `steps` calls after at least `seconds` of untimed calls."""
+    _warm(fn, torch, seconds)
+    ms, _ = _time_steps(fn, steps, 0, torch)
+    return ms
+
+
+def _roof(bytes_per_launch, ms):
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -148,30 +180,12 @@ def _cpu_model():
 
 
 def _accuracy(P32, out, n_sample, torch, seed=0):
-    """Accuracy of a result, without the oracle: residual max_k ||A d_k -
-    lam_k d_k|| / ||A||_F and max |D^T D - I| over every matrix (float64 on the
-    GPU, plane by plane, in chunks), and |delta lam| / ||A||_F against LAPACK
-    (numpy eigvalsh) on a random sample."""
+    """Accuracy of a result, without the oracle: |delta lam| / ||A||_F against
+    LAPACK (numpy eigvalsh) on a random sample (host), then the residual
+    max_k ||A d_k - lam_k d_k|| / ||A||_F and max |D^T D - I| over every
+    matrix (float64 on the GPU, plane by plane, in chunks) -- the device
+    part last, so that a timed region following it finds the GPU busy."""
     n = P32.shape[1]
-    res_max = 0.0
-    orth_max = 0.0
-    chunk = 1 << 22
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        a11, a22, a33, a12, a13, a23 = torch.from_numpy(P32[:, s:e]).to("cuda", torch.float64)
-        A = ((a11, a12, a13), (a12, a22, a23), (a13, a23, a33))
-        D = out["D"][:, s:e].to(torch.float64)
-        L = out["lam"][:, s:e].to(torch.float64)
-        fro = torch.sqrt(a11 * a11 + a22 * a22 + a33 * a33 + 2 * (a12 * a12 + a13 * a13 + a23 * a23))
-        fro = torch.where(fro > 0, fro, torch.ones_like(fro))
-        for k in range(3):
-            col = (D[k], D[3 + k], D[6 + k])
-            r2 = sum((A[i][0] * col[0] + A[i][1] * col[1] + A[i][2] * col[2] - L[k] * col[i]) ** 2
-                     for i in range(3))
-            res_max = max(res_max, float((torch.sqrt(r2) / fro).max()))
-            for j in range(k, 3):
-                dot = D[j] * D[k] + D[3 + j] * D[3 + k] + D[6 + j] * D[6 + k]
-                orth_max = max(orth_max, float((dot - (1.0 if j == k else 0.0)).abs().max()))
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(n, size=min(n_sample, n), replace=False))
     P64 = P32[:, idx].astype(np.float64)
@@ -182,6 +196,25 @@ def _accuracy(P32, out, n_sample, torch, seed=0):
     lam = np.sort(out["lam"][:, idx].cpu().numpy().astype(np.float64).T, axis=1)
     fro = np.sqrt((A * A).sum((1, 2)))
     err = np.abs(lam - ref).max(1) / np.where(fro > 0, fro, 1)
+    res_max = 0.0
+    orth_max = 0.0
+    chunk = 1 << 22
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        a11, a22, a33, a12, a13, a23 = torch.from_numpy(P32[:, s:e]).to("cuda", torch.float64)
+        Am = ((a11, a12, a13), (a12, a22, a23), (a13, a23, a33))
+        D = out["D"][:, s:e].to(torch.float64)
+        L = out["lam"][:, s:e].to(torch.float64)
+        f = torch.sqrt(a11 * a11 + a22 * a22 + a33 * a33 + 2 * (a12 * a12 + a13 * a13 + a23 * a23))
+        f = torch.where(f > 0, f, torch.ones_like(f))
+        for k in range(3):
+            col = (D[k], D[3 + k], D[6 + k])
+            r2 = sum((Am[i][0] * col[0] + Am[i][1] * col[1] + Am[i][2] * col[2] - L[k] * col[i]) ** 2
+                     for i in range(3))
+            res_max = max(res_max, float((torch.sqrt(r2) / f).max()))
+            for j in range(k, 3):
+                dot = D[j] * D[k] + D[3 + j] * D[3 + k] + D[6 + j] * D[6 + k]
+                orth_max = max(orth_max, float((dot - (1.0 if j == k else 0.0)).abs().max()))
     return {"residual_max": res_max, "orth_max": orth_max, "lam_err_max_vs_lapack": float(err.max()),
             "lam_sample": int(idx.size)}
 
@@ -200,45 +233,57 @@ def bench_precision(args, torch, ksym, synth):
     def step():
         ksym.eig3(A, opts=opts, out=out)
 
-    ms, wall = _time_steps(step, args.steps, args.warmup, torch)
-    value = n / (ms * 1e-3)
-    achieved = BYTES_3X3_F32 * n / (ms * 1e-3) / 1e9
-    per_step = _step_stats(step, min(args.steps, 50), torch)
-    # refined fraction and flags, one extra untimed call with the counters
+    # the result is checked first: one call with the flags and counters, then
+    # the accuracy of every matrix (on the GPU) and of a sample (LAPACK)
     ws = ksym.workspace()
     flags = torch.empty((n,), dtype=torch.uint8, device=dev)
     ksym.eig3(A, opts=opts, out=dict(out, flags=flags), ws=ws)
     torch.cuda.synchronize()
     refined = int(ws[0].item())
-    res = {"ms": ms, "wall": wall, "value": value, "achieved": achieved, "refined": refined, "n": n,
-           "opts": opts.as_dict(), "per_step": per_step,
+    res = {"refined": refined, "n": n, "opts": opts.as_dict(),
            "input_sha256": hashlib.sha256(np.ascontiguousarray(P32).data).hexdigest()[:16]}
     if args.accuracy:
         res["accuracy"] = _accuracy(P32, out, args.accuracy, torch)
-    # reduced-output mode on the same matrices: eigenvalues only (no D, no
-    # angles), which runs the eigenvalues-only kernel; reported beside the
-    # metric, not in it
+    del flags
+    print("[bench] accuracy checked; timing", file=sys.stderr, flush=True)
+    # the headline: W warmup steps, then exactly K timed steps
+    ms, wall = _time_steps(step, args.steps, args.warmup, torch)
+    res.update({"ms": ms, "wall": wall, "value": n / (ms * 1e-3),
+                "achieved": BYTES_3X3_F32 * n / (ms * 1e-3) / 1e9})
+    res["per_step"] = _step_stats(step, min(args.steps, 50), torch)
+    # steady state: after at least 0.2 s of further untimed launches
+    ms_ss = _timed_after_warm(step, args.steps, torch)
+    res["steady"] = dict({"ms_per_step": ms_ss, "value": n / (ms_ss * 1e-3), "steps": args.steps,
+                          "after": "at least 0.2 s of untimed launches"}, **_roof(BYTES_3X3_F32 * n, ms_ss))
+    # reduced-output modes on the same matrices, reported beside the metric:
+    # eigenvalues only (no D, no angles: the eigenvalues-only kernel) and
+    # eigenvalues and angles (no D: the full kernel, D kept in registers)
     lam_only = {"lam": out["lam"]}
     opts_l = ksym.tuned_opts("eig3_lam", ksym.F32)
-    ms_l, _ = _time_steps(lambda: ksym.eig3(A, opts=opts_l, out=lam_only), max(3, args.steps // 2),
-                          max(2, args.warmup // 2), torch)
-    res["lam_only"] = {"value": n / (ms_l * 1e-3), "ms_per_step": ms_l, "bytes_per_matrix": BYTES_3X3_LAM_F32,
-                       "achieved_GBs": BYTES_3X3_LAM_F32 * n / (ms_l * 1e-3) / 1e9,
-                       "kernel": "k_eig3_lam (outputs lam only)", "block": opts_l.block,
-                       "mats_per_lane": opts_l.mats_per_lane, "grid_mult": opts_l.grid_mult}
+    ms_l = _timed_after_warm(lambda: ksym.eig3(A, opts=opts_l, out=lam_only), args.steps, torch)
+    res["lam_only"] = dict({"value": n / (ms_l * 1e-3), "ms_per_step": ms_l,
+                            "bytes_per_matrix": BYTES_3X3_LAM_F32, "kernel": "k_eig3_lam (outputs lam only)",
+                            "block": opts_l.block, "mats_per_lane": opts_l.mats_per_lane,
+                            "grid_mult": opts_l.grid_mult}, **_roof(BYTES_3X3_LAM_F32 * n, ms_l))
+    lam_phi = {"lam": out["lam"], "phi": out["phi"]}
+    ms_lp = _timed_after_warm(lambda: ksym.eig3(A, opts=opts, out=lam_phi), args.steps, torch)
+    res["lam_phi"] = dict({"value": n / (ms_lp * 1e-3), "ms_per_step": ms_lp,
+                           "bytes_per_matrix": BYTES_3X3_LAMPHI_F32,
+                           "kernel": "k_eig3<float> with no D planes (lam and angles stored)"},
+                          **_roof(BYTES_3X3_LAMPHI_F32 * n, ms_lp))
     # the same recipe at further seeds (timed step only), beside the headline
     if args.seeds > 1 and not args.n:
-        vals = [value]
+        vals = [n / (ms_ss * 1e-3)]
         for k in range(1, args.seeds):
             Pk = synth.make_precision(n, seed=synth.BASE_SEED + 1 + 1000 * k)
             A.copy_(torch.from_numpy(Pk))
             del Pk
-            ms_k, _ = _time_steps(step, args.steps, max(20, args.warmup // 4), torch)
-            vals.append(n / (ms_k * 1e-3))
+            vals.append(n / (_timed_after_warm(step, args.steps, torch) * 1e-3))
         A.copy_(torch.from_numpy(P32))
         res["seeds"] = {"values": vals, "min": min(vals), "max": max(vals),
-                        "seeds": [synth.BASE_SEED + 1 + 1000 * k for k in range(args.seeds)]}
-    # float64 GPU path on the same matrices
+                        "seeds": [synth.BASE_SEED + 1 + 1000 * k for k in range(args.seeds)],
+                        "timing": "steady state (after at least 0.2 s of untimed launches)"}
+    # float64 GPU paths on the same matrices, as many steps as the headline
     if not args.no_fp64:
         del out
         A64 = A.double()
@@ -249,12 +294,19 @@ def bench_precision(args, torch, ksym, synth):
         for name, path in (("fp64_fixup", ksym.PATH_FP64_FIXUP), ("fp64_plain", ksym.PATH_FP64_PLAIN)):
             o64 = ksym.tuned_opts("eig3", ksym.F64)
             o64.path = path
-            ms64, _ = _time_steps(lambda: ksym.eig3(A64, opts=o64, out=out64), max(3, args.steps // 4),
-                                  max(2, args.warmup // 4), torch)
-            rec = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64,
-                   "achieved_GBs": BYTES_3X3_F64 * n / (ms64 * 1e-3) / 1e9}
+
+            def step64():
+                ksym.eig3(A64, opts=o64, out=out64)
+
+            step64()
+            torch.cuda.synchronize()
+            rec = {}
             if args.accuracy:
                 rec["accuracy"] = _accuracy(P32, out64, args.accuracy, torch)
+            ms64, _ = _time_steps(step64, args.steps, args.warmup, torch)
+            rec.update({"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.steps,
+                        "warmup": args.warmup})
+            rec.update(_roof(BYTES_3X3_F64 * n, ms64))
             f64[name] = rec
         res["fp64"] = f64
         del A64, out64
@@ -281,6 +333,14 @@ def bench_copy(args, torch):
     y = torch.empty_like(x)
     ms, _ = _time_steps(lambda: y.copy_(x), args.steps, args.warmup, torch)
     return {"ms": ms, "bytes_read": 4 * n, "bytes_written": 4 * n, "GBs": 8 * n / (ms * 1e-3) / 1e9}
+
+
+def _timed(fn, args, torch):
+    """A secondary workload's timing: at least 0.2 s of untimed calls, the
+    warmup steps, then the timed steps (mean ms)."""
+    _warm(fn, torch, 0.2)
+    ms, _ = _time_steps(fn, args.steps, args.warmup, torch)
+    return ms
 
 
 def bench_mixed(args, torch, ksym, synth):
@@ -312,12 +372,45 @@ def bench_mixed(args, torch, ksym, synth):
     def step():
         plan.replay(cur)
 
-    ms, wall = _time_steps(step, args.steps, args.warmup, torch)
+    ms = _timed(step, args, torch)
     per_step = _step_stats(step, min(args.steps, 50), torch)
     frac2 = float(sizes[kinds == 2].sum()) / total
-    return {"ms": ms, "wall": wall, "value": total / (ms * 1e-3), "n": total, "ms_per_step_dist": per_step,
-            "achieved": bytes_alg / (ms * 1e-3) / 1e9, "bytes_alg": bytes_alg, "frac2x2": frac2,
-            "plan": plan.info(), "refined": int(plan.ws[0].item())}
+    r = {"workload": "mixed: 2^26 float32 2x2/3x3 (30 % 2x2), N(0,1) entries, 1024 groups of log-uniform sizes; "
+                     "one persistent launch replayed from a HIP graph; outputs lam, D, angles",
+         "kernel": "k_mixed", "value": total / (ms * 1e-3), "unit": "matrices/s", "ms_per_step": ms, "n": total,
+         "ms_per_step_dist": per_step, "bytes_per_launch": bytes_alg, "frac2x2": frac2, "plan": plan.info(),
+         "refined": int(plan.ws[0].item()), "opts": plan.opts.as_dict()}
+    r.update(_roof(bytes_alg, ms))
+    plan.close()
+    return r
+
+
+def _fwd_bwd(args, torch, ksym, fwd, out, w, G, n, label, kernels, opts):
+    """Forward, backward and both as one step of a differentiation workload."""
+    gA = torch.empty((6, n), device=out["lam"].device)
+
+    def bwd():
+        ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], out=gA)
+
+    def step():
+        fwd()
+        bwd()
+
+    ws = ksym.workspace()
+    fwd(ws)
+    torch.cuda.synchronize()
+    refined = int(ws[0].item())
+    ms_f = _timed(fwd, args, torch)
+    ms_b = _timed(bwd, args, torch)
+    ms_s = _timed(step, args, torch)
+    fb, bb = BYTES_3X3_F32, BYTES_BWD_F32 + 12   # forward: lam, D and the gaps; backward with the gaps
+    r = {"workload": label, "kernels": kernels, "value": n / (ms_s * 1e-3), "unit": "matrices/s (forward + backward)",
+         "ms_per_step": ms_s, "n": n, "refined_fraction": refined / n, "opts": opts.as_dict(),
+         "bytes_per_matrix": {"forward": fb, "backward": bb, "step": fb + bb},
+         "forward": dict({"ms": ms_f}, **_roof(fb * n, ms_f)),
+         "backward": dict({"ms": ms_b}, **_roof(bb * n, ms_b))}
+    r.update(_roof((fb + bb) * n, ms_s))
+    return r
 
 
 def bench_grad(args, torch, ksym, synth):
@@ -330,18 +423,14 @@ def bench_grad(args, torch, ksym, synth):
     opts = ksym.tuned_opts("eig3_grad", ksym.F32)
     out = {"lam": torch.empty((3, n), device=dev), "D": torch.empty((9, n), device=dev),
            "gap": torch.empty((3, n), device=dev)}
-    gA = torch.empty((6, n), device=dev)
-    ms_f, _ = _time_steps(lambda: ksym.eig3(A, opts=opts, out=out), args.steps, args.warmup, torch)
-    ms_b, _ = _time_steps(lambda: ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], out=gA),
-                          args.steps, args.warmup, torch)
 
-    def step():   # forward and backward together, one step
-        ksym.eig3(A, opts=opts, out=out)
-        ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], out=gA)
+    def fwd(ws=None):
+        ksym.eig3(A, opts=opts, out=out, ws=ws)
 
-    ms_s, _ = _time_steps(step, args.steps, args.warmup, torch)
-    return {"ms_fwd": ms_f, "ms_bwd": ms_b, "ms_step": ms_s, "n": n, "value": n / (ms_s * 1e-3),
-            "fwd_GBs": 96 * n / (ms_f * 1e-3) / 1e9, "bwd_GBs": (BYTES_BWD_F32 + 12) * n / (ms_b * 1e-3) / 1e9}
+    return _fwd_bwd(args, torch, ksym, fwd, out, w, G, n,
+                    "grad: 2^22 float32 3x3, N(0,1) entries, relative gap >= 1e-3; loss sum w lam + sum G D; "
+                    "forward (lam, D, gaps; float64 pair correction) then the adjoint",
+                    "k_eig3<float, GRAD> + k_eig3_bwd", opts)
 
 
 def bench_field(args, torch, ksym, synth):
@@ -355,18 +444,14 @@ def bench_field(args, torch, ksym, synth):
     opts = ksym.tuned_opts("eig3_aos", ksym.F32)
     out = {"lam": torch.empty((3, n), device=dev), "D": torch.empty((9, n), device=dev),
            "gap": torch.empty((3, n), device=dev)}
-    gA = torch.empty((6, n), device=dev)
-    ms_f, _ = _time_steps(lambda: ksym.eig3_aos(rec, opts=opts, out=out), args.steps, args.warmup, torch)
-    ms_b, _ = _time_steps(lambda: ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], out=gA),
-                          args.steps, args.warmup, torch)
 
-    def step():   # forward and backward together, one step
-        ksym.eig3_aos(rec, opts=opts, out=out)
-        ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"], out=gA)
+    def fwd(ws=None):
+        ksym.eig3_aos(rec, opts=opts, out=out, ws=ws)
 
-    ms_s, _ = _time_steps(step, args.steps, args.warmup, torch)
-    return {"ms_fwd": ms_f, "ms_bwd": ms_b, "ms_step": ms_s, "n": n, "value": n / (ms_s * 1e-3),
-            "fwd_GBs": 96 * n / (ms_f * 1e-3) / 1e9, "bwd_GBs": (BYTES_BWD_F32 + 12) * n / (ms_b * 1e-3) / 1e9}
+    return _fwd_bwd(args, torch, ksym, fwd, out, w, G, n,
+                    f"field: {nx}^3 SPD tensor field, array-of-structures float32 records, eigenvalues "
+                    "10^U[-4,-2], smooth rotations, 5 % isotropic; forward (float64 pair correction) then "
+                    "the adjoint", "k_eig3<float, AoS, GRAD> + k_eig3_bwd", opts)
 
 
 def main():
@@ -387,6 +472,9 @@ def main():
                          "(the first is the headline's), to show the spread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workloads", default="mixed,grad,field",
+                    help="precision workload: the other workloads timed into the same line "
+                         "(comma-separated from mixed, grad, field; empty for none)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -445,10 +533,27 @@ def main():
             line["fp64_path"] = r["fp64"]
         if "lam_only" in r:
             line["eigenvalues_only"] = r["lam_only"]
+        if "lam_phi" in r:
+            line["eigenvalues_and_angles"] = r["lam_phi"]
+        line["steady_state"] = r["steady"]
         if "seeds" in r:
             line["seed_spread"] = r["seeds"]
         if "accuracy" in r:
             line["accuracy"] = r["accuracy"]
+        line["timing"] = ("after the accuracy check of one forward (its device part last), "
+                          f"{args.warmup} warmup steps, then {args.steps} timed steps between HIP events "
+                          "on the launching stream")
+        # the library's other workloads, each timed on its own inputs
+        work = {}
+        for name in [w for w in args.workloads.split(",") if w]:
+            print(f"[bench] workload {name}", file=sys.stderr, flush=True)
+            fn = {"mixed": bench_mixed, "grad": bench_grad, "field": bench_field}[name]
+            wargs = argparse.Namespace(**vars(args))
+            wargs.n = 0
+            work[name] = fn(wargs, torch, ksym, synth)
+            torch.cuda.empty_cache()
+        if work:
+            line["workloads"] = work
         print(json.dumps(line), flush=True)
         return
 
