@@ -22,6 +22,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ksym_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
+# the checking build (AddressSanitizer and UndefinedBehaviorSanitizer, every
+# report fatal), loaded instead of the plain one when KSYM_ORACLE_SANITIZE=1;
+# the process then needs gcc's libasan and libubsan preloaded
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 GENERAL, DOUBLE, TRIPLE = 0, 1, 2
 TAU_DBL = 1e-6          # relative split below which the double-root case is taken
@@ -29,19 +34,23 @@ TAU_DBL = 1e-6          # relative split below which the double-root case is tak
 _lib = None
 
 
-def build(force=True):
-    """Compile the oracle with gcc into oracle/liboracle.so."""
-    cmd = ["gcc", *CFLAGS, "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+def build(force=True, sanitize=False):
+    """Compile the oracle with gcc into oracle/liboracle.so (sanitize: the
+    checking build oracle/liboracle_san.so)."""
+    lib = _LIB_SAN if sanitize else _LIB
+    cmd = ["gcc", *CFLAGS, *(SAN_FLAGS if sanitize else []), "-o", lib + ".tmp", _SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    os.replace(lib + ".tmp", lib)
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        _lib = ctypes.CDLL(_LIB)
+        san = os.environ.get("KSYM_ORACLE_SANITIZE") == "1"
+        lib = _LIB_SAN if san else _LIB
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            build(sanitize=san)
+        _lib = ctypes.CDLL(lib)
         P = ctypes.c_void_p
         i64, dbl, cint = ctypes.c_int64, ctypes.c_double, ctypes.c_int
         _lib.ko_eig3_batch.argtypes = [i64, P, P, P, P, P, dbl, cint]

@@ -40,10 +40,22 @@ def sources():
         os.path.join(os.path.dirname(HERE), "include", "ksym.h")]
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile csrc/ksym_api.hip into libksym.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+# The checking build of the host code (argument checks, plans, dispatch):
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host side only (each
+# -fsanitize= directly after -Xarch_host; the device code is built as usual).
+# Loaded by the ABI tests when KSYM_ABI_LIB names it, with clang's ASan runtime
+# preloaded.
+LIB_SAN = os.path.join(HERE, "libksym_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_library(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile csrc/ksym_api.hip into libksym.so (always recompiles);
+    sanitize: the host-checking build libksym_san.so instead."""
+    lib = LIB_SAN if sanitize else LIB
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *(SAN_FLAGS if sanitize else []), "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,8 +65,8 @@ def build_library(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{msg}")
     if msg.strip() and verbose:
         print(msg)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def is_stale() -> bool:

@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ksym.h")
-LIB = os.path.join(ROOT, "paper_1306_6291_amd", "libksym.so")
+# KSYM_ABI_LIB: another build of the library to check (the sanitizer run)
+LIB = os.environ.get("KSYM_ABI_LIB") or os.path.join(ROOT, "paper_1306_6291_amd", "libksym.so")
 
 
 def _declared_functions():
