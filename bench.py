@@ -10,9 +10,11 @@ in float64, the angle solve in float32, checks every D and refines the
 failing matrices in float64 inside the same kernel.
 
 Order: the inputs are generated and copied to the device; one forward with
-the flags and counters runs and its result is checked (residual and
-orthogonality of every matrix on the GPU, eigenvalues against LAPACK on a
-sample); then the warmup steps and the timed steps of the headline.
+the flags and counters runs and its result is checked (eigenvalues against
+LAPACK on a sample, residual and orthogonality of every matrix on the GPU);
+the steady-state leg (at least 0.2 s of untimed launches, then the timed
+steps) follows, then the warmup steps and the timed steps of the headline,
+between two counter-reset launches that mark them in a kernel trace.
 
 Printed: one JSON line with matrices/s, the roofline of the kernel (HBM,
 algorithmic bytes 84 per matrix), the CPU oracle's throughput on the host
@@ -26,8 +28,8 @@ algorithmic bytes and fraction of the HBM roof.
 Other workloads (--workload for a line of their own; in the default line
 under "workloads"): mixed (2^26 mixed 2x2/3x3 in 1024 groups, one persistent
 launch replayed from a HIP graph), grad (2^22 forward + backward), field
-(256^3 array-of-structures tensor field, forward + backward), copy (a device
-copy of known size, for counter calibration).
+(256^3 array-of-structures tensor field, forward + backward), eig2 (2^24
+float32 2x2), copy (a device copy of known size, for counter calibration).
 """
 
 from __future__ import annotations
@@ -69,8 +71,8 @@ def _source_digest():
 
 
 def _stored_profile(name):
-    """Key/value lines of profiles/<name>.txt (written from rocprofv3 runs), or
-    None when the file is missing or the kernel sources have changed since
+    """Key/value lines of profiles/<name>.txt (summaries of rocprofv3 runs),
+    or None when the file is missing or the kernel sources have changed since
     the counters were taken (its source_digest no longer matches)."""
     path = os.path.join(ROOT, "profiles", f"{name}.txt")
     if not os.path.exists(path):
@@ -85,23 +87,32 @@ def _stored_profile(name):
     return rec
 
 
-def _stored_traffic(name):
-    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs, or None."""
-    rec = _stored_profile(f"{name}_traffic")
+def _stored_float(name, key):
+    rec = _stored_profile(name)
     try:
-        return float(rec["hbm_bytes_per_launch"]) if rec else None
+        return float(rec[key]) if rec else None
     except (KeyError, ValueError):
         return None
+
+
+def _stored_traffic(name):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs, or None."""
+    return _stored_float(name, "hbm_bytes_per_launch")
 
 
 def _stored_valu(name):
     """VALU instructions per dispatch (SQ_INSTS_VALU, wave instructions) from
     the counter run, or None."""
-    rec = _stored_profile(f"{name}_valu")
-    try:
-        return float(rec["SQ_INSTS_VALU_per_dispatch"]) if rec else None
-    except (KeyError, ValueError):
-        return None
+    return _stored_float(name, "SQ_INSTS_VALU_per_dispatch")
+
+
+def _counters(name, n):
+    """The stored counter figures of one kernel on one workload: HBM bytes
+    per launch and VALU lane instructions per matrix (None where absent or
+    stale)."""
+    t, v = _stored_traffic(name), _stored_valu(name)
+    return {"traffic": t, "valu_lane_instr_per_matrix": v * 64 / n if v is not None else None,
+            "profile": f"profiles/{name}.txt"}
 
 
 def _cpu_threads():
@@ -246,15 +257,21 @@ def bench_precision(args, torch, ksym, synth):
         res["accuracy"] = _accuracy(P32, out, args.accuracy, torch)
     del flags
     print("[bench] accuracy checked; timing", file=sys.stderr, flush=True)
-    # the headline: W warmup steps, then exactly K timed steps
-    ms, wall = _time_steps(step, args.steps, args.warmup, torch)
-    res.update({"ms": ms, "wall": wall, "value": n / (ms * 1e-3),
-                "achieved": BYTES_3X3_F32 * n / (ms * 1e-3) / 1e9})
-    res["per_step"] = _step_stats(step, min(args.steps, 50), torch)
-    # steady state: after at least 0.2 s of further untimed launches
+    # steady state first: K steps after at least 0.2 s of untimed launches
+    # (the GPU's clocks need about that long under this load to leave their
+    # idle state; a short warmup after idle host work measures the ramp)
     ms_ss = _timed_after_warm(step, args.steps, torch)
     res["steady"] = dict({"ms_per_step": ms_ss, "value": n / (ms_ss * 1e-3), "steps": args.steps,
                           "after": "at least 0.2 s of untimed launches"}, **_roof(BYTES_3X3_F32 * n, ms_ss))
+    # the headline: W warmup steps, then exactly K timed steps, between two
+    # counter-reset launches that mark the region in a kernel trace
+    marker = ksym.workspace()
+    ksym.zero_counters(marker)
+    ms, wall = _time_steps(step, args.steps, args.warmup, torch)
+    ksym.zero_counters(marker)
+    res.update({"ms": ms, "wall": wall, "value": n / (ms * 1e-3),
+                "achieved": BYTES_3X3_F32 * n / (ms * 1e-3) / 1e9})
+    res["per_step"] = _step_stats(step, min(args.steps, 50), torch)
     # reduced-output modes on the same matrices, reported beside the metric:
     # eigenvalues only (no D, no angles: the eigenvalues-only kernel) and
     # eigenvalues and angles (no D: the full kernel, D kept in registers)
@@ -264,12 +281,16 @@ def bench_precision(args, torch, ksym, synth):
     res["lam_only"] = dict({"value": n / (ms_l * 1e-3), "ms_per_step": ms_l,
                             "bytes_per_matrix": BYTES_3X3_LAM_F32, "kernel": "k_eig3_lam (outputs lam only)",
                             "block": opts_l.block, "mats_per_lane": opts_l.mats_per_lane,
-                            "grid_mult": opts_l.grid_mult}, **_roof(BYTES_3X3_LAM_F32 * n, ms_l))
+                            "grid_mult": opts_l.grid_mult, **_counters("eig3_lam_precision", n)},
+                           **_roof(BYTES_3X3_LAM_F32 * n, ms_l))
     lam_phi = {"lam": out["lam"], "phi": out["phi"]}
-    ms_lp = _timed_after_warm(lambda: ksym.eig3(A, opts=opts, out=lam_phi), args.steps, torch)
+    opts_lp = ksym.tuned_opts("eig3_lamphi", ksym.F32)
+    ms_lp = _timed_after_warm(lambda: ksym.eig3(A, opts=opts_lp, out=lam_phi), args.steps, torch)
     res["lam_phi"] = dict({"value": n / (ms_lp * 1e-3), "ms_per_step": ms_lp,
                            "bytes_per_matrix": BYTES_3X3_LAMPHI_F32,
-                           "kernel": "k_eig3<float> with no D planes (lam and angles stored)"},
+                           "kernel": "k_eig3<float> with no D planes (lam and angles stored)",
+                           "block": opts_lp.block, "mats_per_lane": opts_lp.mats_per_lane,
+                           "grid_mult": opts_lp.grid_mult, **_counters("eig3_lamphi_precision", n)},
                           **_roof(BYTES_3X3_LAMPHI_F32 * n, ms_lp))
     # the same recipe at further seeds (timed step only), beside the headline
     if args.seeds > 1 and not args.n:
@@ -307,6 +328,8 @@ def bench_precision(args, torch, ksym, synth):
             rec.update({"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.steps,
                         "warmup": args.warmup})
             rec.update(_roof(BYTES_3X3_F64 * n, ms64))
+            rec.update(_counters({"fp64_fixup": "eig3_f64fixup_precision",
+                                  "fp64_plain": "eig3_f64plain_precision"}[name], n))
             f64[name] = rec
         res["fp64"] = f64
         del A64, out64
@@ -379,13 +402,33 @@ def bench_mixed(args, torch, ksym, synth):
                      "one persistent launch replayed from a HIP graph; outputs lam, D, angles",
          "kernel": "k_mixed", "value": total / (ms * 1e-3), "unit": "matrices/s", "ms_per_step": ms, "n": total,
          "ms_per_step_dist": per_step, "bytes_per_launch": bytes_alg, "frac2x2": frac2, "plan": plan.info(),
-         "refined": int(plan.ws[0].item()), "opts": plan.opts.as_dict()}
+         "refined": int(plan.ws[0].item()), "opts": plan.opts.as_dict(), **_counters("mixed", total)}
     r.update(_roof(bytes_alg, ms))
     plan.close()
     return r
 
 
-def _fwd_bwd(args, torch, ksym, fwd, out, w, G, n, label, kernels, opts):
+def bench_eig2(args, torch, ksym, synth):
+    n = args.n or (1 << 24)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(synth.BASE_SEED + 1005)
+    A = torch.from_numpy(rng.uniform(-1.0, 1.0, size=(3, n)).astype(np.float32)).to(dev)
+    out = {"lam": torch.empty((2, n), device=dev), "D": torch.empty((4, n), device=dev),
+           "phi": torch.empty((n,), device=dev)}
+    opts = ksym.tuned_opts("eig2", ksym.F32)
+
+    def step():
+        ksym.eig2(A, opts=opts, out=out)
+
+    ms = _timed(step, args, torch)
+    r = {"workload": "eig2: 2^24 float32 2x2, entries U[-1,1]; outputs lam, D, angle", "kernel": "k_eig2",
+         "value": n / (ms * 1e-3), "unit": "matrices/s", "ms_per_step": ms, "n": n,
+         "bytes_per_matrix": BYTES_2X2_F32, "opts": opts.as_dict(), **_counters("eig2", n)}
+    r.update(_roof(BYTES_2X2_F32 * n, ms))
+    return r
+
+
+def _fwd_bwd(args, torch, ksym, fwd, out, w, G, n, label, kernels, opts, prof):
     """Forward, backward and both as one step of a differentiation workload."""
     gA = torch.empty((6, n), device=out["lam"].device)
 
@@ -407,8 +450,8 @@ def _fwd_bwd(args, torch, ksym, fwd, out, w, G, n, label, kernels, opts):
     r = {"workload": label, "kernels": kernels, "value": n / (ms_s * 1e-3), "unit": "matrices/s (forward + backward)",
          "ms_per_step": ms_s, "n": n, "refined_fraction": refined / n, "opts": opts.as_dict(),
          "bytes_per_matrix": {"forward": fb, "backward": bb, "step": fb + bb},
-         "forward": dict({"ms": ms_f}, **_roof(fb * n, ms_f)),
-         "backward": dict({"ms": ms_b}, **_roof(bb * n, ms_b))}
+         "forward": dict({"ms": ms_f, **_counters(f"{prof}_fwd", n)}, **_roof(fb * n, ms_f)),
+         "backward": dict({"ms": ms_b, **_counters(f"{prof}_bwd", n)}, **_roof(bb * n, ms_b))}
     r.update(_roof((fb + bb) * n, ms_s))
     return r
 
@@ -430,7 +473,7 @@ def bench_grad(args, torch, ksym, synth):
     return _fwd_bwd(args, torch, ksym, fwd, out, w, G, n,
                     "grad: 2^22 float32 3x3, N(0,1) entries, relative gap >= 1e-3; loss sum w lam + sum G D; "
                     "forward (lam, D, gaps; float64 pair correction) then the adjoint",
-                    "k_eig3<float, GRAD> + k_eig3_bwd", opts)
+                    "k_eig3<float, GRAD> + k_eig3_bwd", opts, "grad")
 
 
 def bench_field(args, torch, ksym, synth):
@@ -451,7 +494,7 @@ def bench_field(args, torch, ksym, synth):
     return _fwd_bwd(args, torch, ksym, fwd, out, w, G, n,
                     f"field: {nx}^3 SPD tensor field, array-of-structures float32 records, eigenvalues "
                     "10^U[-4,-2], smooth rotations, 5 % isotropic; forward (float64 pair correction) then "
-                    "the adjoint", "k_eig3<float, AoS, GRAD> + k_eig3_bwd", opts)
+                    "the adjoint", "k_eig3<float, AoS, GRAD> + k_eig3_bwd", opts, "field")
 
 
 def main():
@@ -461,7 +504,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200,
                     help="untimed launches first (the GPU reaches its steady clock after ~0.1 s of work)")
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "mixed", "grad", "field", "copy"])
+                    choices=["precision", "mixed", "grad", "field", "eig2", "copy"])
     ap.add_argument("--n", type=int, default=0, help="override the batch size")
     ap.add_argument("--field-n", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
@@ -472,9 +515,9 @@ def main():
                          "(the first is the headline's), to show the spread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workloads", default="mixed,grad,field",
+    ap.add_argument("--workloads", default="mixed,grad,field,eig2",
                     help="precision workload: the other workloads timed into the same line "
-                         "(comma-separated from mixed, grad, field; empty for none)")
+                         "(comma-separated from mixed, grad, field, eig2; empty for none)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -540,14 +583,15 @@ def main():
             line["seed_spread"] = r["seeds"]
         if "accuracy" in r:
             line["accuracy"] = r["accuracy"]
-        line["timing"] = ("after the accuracy check of one forward (its device part last), "
+        line["timing"] = ("after the accuracy check of one forward and the steady-state leg, "
                           f"{args.warmup} warmup steps, then {args.steps} timed steps between HIP events "
-                          "on the launching stream")
+                          "on the launching stream; two k_zero_u32 launches mark the warmup and timed steps "
+                          "in a kernel trace")
         # the library's other workloads, each timed on its own inputs
         work = {}
         for name in [w for w in args.workloads.split(",") if w]:
             print(f"[bench] workload {name}", file=sys.stderr, flush=True)
-            fn = {"mixed": bench_mixed, "grad": bench_grad, "field": bench_field}[name]
+            fn = {"mixed": bench_mixed, "grad": bench_grad, "field": bench_field, "eig2": bench_eig2}[name]
             wargs = argparse.Namespace(**vars(args))
             wargs.n = 0
             work[name] = fn(wargs, torch, ksym, synth)
@@ -557,7 +601,7 @@ def main():
         print(json.dumps(line), flush=True)
         return
 
-    fn = {"mixed": bench_mixed, "grad": bench_grad, "field": bench_field}[args.workload]
+    fn = {"mixed": bench_mixed, "grad": bench_grad, "field": bench_field, "eig2": bench_eig2}[args.workload]
     r = fn(args, torch, ksym, synth)
     print(json.dumps({"workload": args.workload, **r}), flush=True)
 
