@@ -111,6 +111,11 @@ typedef enum {
     KSYM_PATH_FP64_FIXUP = 2
 } ksym_path;
 
+/* Largest grid_mult (workgroups per compute unit): with 64-thread groups it
+ * gives one tile per wave for a launch of up to 2^30 matrices, more than the
+ * 2^28 of one launch chunk. */
+#define KSYM_GRID_MULT_MAX 65536
+
 /*
  * Launch and threshold options.  Fill with ksym_opts_default() and change
  * fields; a NULL ksym_opts* means the defaults.
@@ -120,9 +125,12 @@ typedef enum {
  *   mats_per_lane  matrices each lane handles per tile: 1, 2 or 4 (3x3
  *                  kernels: 1 or 2).
  *   grid_mult      workgroups per compute unit of the grid-stride launch
- *                  (the grid is min(tiles, grid_mult * CUs)); 1..1024.  The
- *                  default 1024 makes the launch non-persistent (one tile
- *                  per wave) below about 2^18 tiles, which measured fastest.
+ *                  (the grid is min(tiles, grid_mult * CUs));
+ *                  1..KSYM_GRID_MULT_MAX.  The default KSYM_GRID_MULT_MAX
+ *                  gives every wave one tile at any batch size, which
+ *                  measured fastest: a wave that goes on to a further tile
+ *                  waits for its previous stores along with the next loads
+ *                  (one in-order counter covers both).
  *   tau_gap        relative eigenvalue gap min|lam_i - lam_j| / max|lam|
  *                  below which a matrix always takes the refinement (0 = off).
  *   tau_res        refinement if the residuals r_k = A d_k - lam_k d_k are too

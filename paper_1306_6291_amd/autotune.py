@@ -278,7 +278,7 @@ def main(argv=None):
             tuned = json.load(f)
     # large grid_mult values make the launch non-persistent (one wave tile
     # per wave), which measured fastest for the 3x3 kernels
-    gms = (16, 64, 256, 1024) if args.quick else (4, 16, 32, 64, 128, 256, 512, 1024)
+    gms = (16, 64, 256, 65536) if args.quick else (4, 16, 32, 64, 128, 256, 512, 1024, 65536)
     drains = (0, 8) if args.quick else (0, 4, 8, 16)
     shapes32 = _shapes((64, 128, 256, 512), (1, 2), gms, drains)
     shapes_aos = [s for s in shapes32 if (s["block"], s["mats_per_lane"]) in

@@ -84,8 +84,8 @@ ksym_status resolve_opts(ksym_dtype dt, const ksym_opts *in, ksym_opts *out) {
         return fail(KSYM_E_ARG, "block must be 64, 128, 256, 512 or 1024 (got %d)", o.block);
     if (o.mats_per_lane != 1 && o.mats_per_lane != 2 && o.mats_per_lane != 4)
         return fail(KSYM_E_ARG, "mats_per_lane must be 1, 2 or 4 (got %d)", o.mats_per_lane);
-    if (o.grid_mult < 1 || o.grid_mult > 1024)
-        return fail(KSYM_E_ARG, "grid_mult must be in 1..1024 (got %d)", o.grid_mult);
+    if (o.grid_mult < 1 || o.grid_mult > KSYM_GRID_MULT_MAX)
+        return fail(KSYM_E_ARG, "grid_mult must be in 1..%d (got %d)", KSYM_GRID_MULT_MAX, o.grid_mult);
     if (o.drain_tiles > (1 << 20)) return fail(KSYM_E_ARG, "drain_tiles must be in 0..2^20");
     if (!(o.tau_res > 0) || !(o.tau_dbl >= 0) || !(o.tau_gap >= 0) || !(o.tau_vec >= 0))
         return fail(KSYM_E_ARG, "thresholds must be finite and non-negative (tau_res > 0)");
@@ -384,7 +384,7 @@ void ksym_opts_default(ksym_dtype dtype, ksym_opts *o) {
     o->path = dtype == KSYM_F64 ? KSYM_PATH_FP64_FIXUP : KSYM_PATH_FP32_FIXUP;
     o->block = 256;
     o->mats_per_lane = 1;
-    o->grid_mult = 1024;   // one tile per wave for all but the largest batches
+    o->grid_mult = KSYM_GRID_MULT_MAX;   // one tile per wave at every batch size
     o->tau_gap = 0.0;
     o->tau_dbl = dtype == KSYM_F64 ? 1e-6 : 1e-9;
     o->drain_tiles = 8;
@@ -569,7 +569,7 @@ static ksym_status compose_impl(int k, ksym_dtype dtype, int64_t n, const void *
             for (int c = 0; c < na; ++c) ca.p.A[c] = (T *)A[c] + start;
             ca.n = (uint32_t)len;
             int grid = 0;
-            ksym_status st = grid_for(len, BS, 1024, &grid);
+            ksym_status st = grid_for(len, BS, KSYM_GRID_MULT_MAX, &grid);
             if (st != KSYM_OK) return st;
             hipError_t e = k == 3 ? launch(&k_compose3<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ca)
                                   : launch(&k_compose2<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ca);
@@ -642,7 +642,7 @@ ksym_status ksym_eig2_backward(ksym_dtype dtype, int64_t n, const void *const la
             ba.n = (uint32_t)len;
             ba.eps_rel = eps_rel;
             int grid = 0;
-            ksym_status st = grid_for(len, BS, 1024, &grid);
+            ksym_status st = grid_for(len, BS, KSYM_GRID_MULT_MAX, &grid);
             if (st != KSYM_OK) return st;
             hipError_t e = launch(&k_eig2_bwd<T, BS>, dim3(grid), dim3(BS), (hipStream_t)stream, ba);
             if (e != hipSuccess) return hip_fail(e, "launch k_eig2_bwd");

@@ -73,7 +73,7 @@ def test_defaults(lib):
     assert o.path == 0 and o.block == 256 and o.mats_per_lane in (1, 2, 4)
     assert 0 < o.tau_res < 1e-5
     assert o.drain_tiles >= 0 and o.reserved == 0
-    assert 1 <= o.grid_mult <= 1024
+    assert 1 <= o.grid_mult <= 65536
     lib.ksym_opts_default(1, ctypes.byref(o))
     assert o.path == 2 and 0 < o.tau_res < 1e-9
 
@@ -114,7 +114,7 @@ def test_eig3_argument_errors(lib):
     o.path = 0
     assert f(1, 10, ok, None, None, None, None, None, None, 0, ctypes.byref(o), None) == 2
     # launch-shape options
-    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 1025),
+    for field, bad in (("block", 96), ("mats_per_lane", 3), ("grid_mult", -1), ("grid_mult", 65537),
                        ("drain_tiles", (1 << 20) + 1)):
         lib.ksym_opts_default(0, ctypes.byref(o))
         setattr(o, field, bad)
