@@ -375,14 +375,17 @@ def bench_mixed(args, torch, ksym, synth):
     bytes_alg = 0
     for s, k in zip(sizes, kinds):
         s = int(s)
-        planes = torch.from_numpy(rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)).to(dev)
+        # each group its own allocation, every plane on a 256-byte boundary
+        # (row stride rounded up to 64 elements)
+        P = rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)
+        planes = ksym.line_aligned_planes(P.shape[0], s, device=dev, fill=P)
         if k == 3:
-            out = {"lam": torch.empty((3, s), device=dev), "D": torch.empty((9, s), device=dev),
-                   "phi": torch.empty((3, s), device=dev)}
+            out = {"lam": ksym.line_aligned_planes(3, s, device=dev), "D": ksym.line_aligned_planes(9, s, device=dev),
+                   "phi": ksym.line_aligned_planes(3, s, device=dev)}
             bytes_alg += BYTES_3X3_F32 * s
         else:
-            out = {"lam": torch.empty((2, s), device=dev), "D": torch.empty((4, s), device=dev),
-                   "phi": torch.empty((s,), device=dev)}
+            out = {"lam": ksym.line_aligned_planes(2, s, device=dev), "D": ksym.line_aligned_planes(4, s, device=dev),
+                   "phi": ksym.line_aligned_planes(1, s, device=dev)[0]}
             bytes_alg += BYTES_2X2_F32 * s
         groups.append((int(k), planes, out))
     plan = ksym.Plan(groups, opts=ksym.tuned_opts("mixed", ksym.F32))
@@ -398,8 +401,9 @@ def bench_mixed(args, torch, ksym, synth):
     ms = _timed(step, args, torch)
     per_step = _step_stats(step, min(args.steps, 50), torch)
     frac2 = float(sizes[kinds == 2].sum()) / total
-    r = {"workload": "mixed: 2^26 float32 2x2/3x3 (30 % 2x2), N(0,1) entries, 1024 groups of log-uniform sizes; "
-                     "one persistent launch replayed from a HIP graph; outputs lam, D, angles",
+    r = {"workload": "mixed: 2^26 float32 2x2/3x3 (30 % 2x2), N(0,1) entries, 1024 groups of log-uniform sizes, "
+                     "every plane 256-byte aligned; one persistent launch replayed from a HIP graph; "
+                     "outputs lam, D, angles",
          "kernel": "k_mixed", "value": total / (ms * 1e-3), "unit": "matrices/s", "ms_per_step": ms, "n": total,
          "ms_per_step_dist": per_step, "bytes_per_launch": bytes_alg, "frac2x2": frac2, "plan": plan.info(),
          "refined": int(plan.ws[0].item()), "opts": plan.opts.as_dict(), **_counters("mixed", total)}

@@ -318,7 +318,11 @@ ksym_status ksym_eig3_backward(ksym_dtype dtype, int64_t n, const void *const la
 /*
  * Mixed persistent batch: many groups of 2x2 or 3x3 matrices in one launch.
  * kind = 2 uses in[0..2], lam[0..1], D[0..3], phi[0]; kind = 3 uses the full
- * arrays as in ksym_eig3.  Pointers of unused slots are ignored.
+ * arrays as in ksym_eig3.  Pointers of unused slots are ignored.  When every
+ * plane of every group (and every flags plane) starts on a 256-byte
+ * boundary, each wave tile's part of a plane fills whole cache lines and the
+ * launch streams its loads and stores (non-temporal policy); otherwise it
+ * uses the default policy.  Results are the same either way.
  */
 typedef struct {
     int32_t kind;          /* 2 or 3 */

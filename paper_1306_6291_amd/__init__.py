@@ -127,6 +127,11 @@ def _dt(t):
     raise TypeError(f"ksym supports float32 and float64 tensors, got {t.dtype}")
 
 
+def _first_plane(planes):
+    """A tensor of a group's inputs: the (k, n) tensor, or the first of its k planes."""
+    return planes[0] if isinstance(planes, (list, tuple)) else planes
+
+
 def _ptr_array(ptrs):
     return (ctypes.c_void_p * len(ptrs))(*[p if p else None for p in ptrs])
 
@@ -183,6 +188,21 @@ def tuned_opts(kind="eig3", dtype=F32):
     if rec:
         return Opts.defaults(dtype, **rec["opts"])
     return Opts.defaults(dtype)
+
+
+def line_aligned_planes(k, n, dtype=torch.float32, device="cuda", fill=None):
+    """k planes of n elements that each start on a 256-byte boundary: one
+    (k, stride) allocation with the row stride rounded up to 64 elements (the
+    caching allocator's blocks are 512-byte aligned), returned as a list of
+    1-D views.  Mixed-batch groups laid out this way let the launch stream its
+    loads and stores (include/ksym.h, ksym_group).  fill: optional (k, n)
+    tensor or array copied in."""
+    es = torch.empty((), dtype=dtype).element_size()
+    stride = -(-max(int(n), 1) * es // 256) * 256 // es
+    t = torch.empty((k, stride), dtype=dtype, device=device)
+    if fill is not None:
+        t[:, :n].copy_(torch.as_tensor(fill))
+    return [t[c, :n] for c in range(k)]
 
 
 def workspace(device=None):
@@ -465,7 +485,7 @@ class Plan:
     dict of preallocated outputs (lam, D, phi, flags; any may be missing)."""
 
     def __init__(self, groups, opts=None):
-        ref = groups[0][1]
+        ref = _first_plane(groups[0][1])
         dt = _dt(ref)
         self.dtype = dt
         self.device = ref.device
@@ -520,7 +540,7 @@ def mixed_run_noalloc(groups, opts=None, ws=None, stream=None):
     no device memory (the library's fixed tables; see include/ksym.h for the
     limits).  groups as for Plan; ws: None or a workspace() tensor, whose
     counters are zeroed and accumulated.  Calls that overlap on one GPU race."""
-    ref = groups[0][1]
+    ref = _first_plane(groups[0][1])
     dt = _dt(ref)
     arr = _group_array(groups)
     o = _opts(dt, opts, _kind="mixed")

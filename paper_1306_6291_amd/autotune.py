@@ -191,13 +191,15 @@ def tune_mixed(log, shapes):
     groups = []
     for s, k in zip(sizes, kinds):
         s = int(s)
-        planes = torch.from_numpy(rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)).cuda()
+        # every plane on a 256-byte boundary (the streaming kernel variant)
+        P = rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)
+        planes = ksym.line_aligned_planes(P.shape[0], s, fill=P)
         if k == 3:
-            out = {"lam": torch.empty((3, s), device="cuda"), "D": torch.empty((9, s), device="cuda"),
-                   "phi": torch.empty((3, s), device="cuda")}
+            out = {"lam": ksym.line_aligned_planes(3, s), "D": ksym.line_aligned_planes(9, s),
+                   "phi": ksym.line_aligned_planes(3, s)}
         else:
-            out = {"lam": torch.empty((2, s), device="cuda"), "D": torch.empty((4, s), device="cuda"),
-                   "phi": torch.empty((s,), device="cuda")}
+            out = {"lam": ksym.line_aligned_planes(2, s), "D": ksym.line_aligned_planes(4, s),
+                   "phi": ksym.line_aligned_planes(1, s)[0]}
         groups.append((int(k), planes, out))
     log(f"[mixed/f32] {len(shapes)} launch shapes, {total} matrices in {len(groups)} groups")
     best = None
@@ -310,7 +312,7 @@ def main(argv=None):
         elif kind == "mixed/f32":
             rec = tune_mixed(log, [s for s in shapes32 if (s["block"], s["mats_per_lane"]) in
                                    ((64, 1), (128, 1), (256, 1), (256, 2), (512, 1))])
-            rec["workload"] = "2^26 mixed 2x2/3x3 in 1024 groups, graph replay"
+            rec["workload"] = "2^26 mixed 2x2/3x3 in 1024 groups, planes 256-byte aligned, graph replay"
         elif kind == "eig2/f32":
             rec = tune_eig2(log, _shapes((64, 128, 256, 512, 1024), (1, 2, 4), gms, (0,)))
             rec["workload"] = "2^24 float32 2x2, U[-1,1]"

@@ -200,9 +200,9 @@ template <typename T> BwdK<T> pick_bwd(int bs, int mpl) {
 }
 
 template <typename T> using MixK = void (*)(MixedArgs<T>);
-template <typename T> MixK<T> pick_mixed(int bs, int mpl) {
+template <typename T> MixK<T> pick_mixed(int bs, int mpl, bool stream = false) {
 #define KSYM_M(B, M) \
-    if (bs == B && mpl == M) return &k_mixed<T, B, M>;
+    if (bs == B && mpl == M) return stream ? &k_mixed<T, B, M, true> : &k_mixed<T, B, M, false>;
     KSYM_M(64, 1) KSYM_M(128, 1) KSYM_M(256, 1) KSYM_M(256, 2) KSYM_M(512, 1)
 #undef KSYM_M
     return nullptr;
@@ -369,6 +369,7 @@ struct ksym_plan {
     int grid;
     void *d_groups;
     TileInfo *d_tiles;
+    bool stream;   // every plane line-aligned: the streaming kernel variant
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -792,6 +793,25 @@ ksym_status check_groups(ksym_dtype dtype, int32_t ngroups, const ksym_group *gr
 // Planes a group of kind 2 or 3 uses, for the range count of the checks.
 constexpr int kGroupRanges = 6 + 3 + 9 + 3 + 1;
 
+// True when every plane of every group (inputs, outputs and flags present)
+// starts on a 256-byte boundary: a wave tile's part of each plane then fills
+// whole cache lines, and the mixed kernel can stream.
+bool groups_line_aligned(int32_t ngroups, const ksym_group *groups) {
+    for (int g = 0; g < ngroups; ++g) {
+        const ksym_group &G = groups[g];
+        const bool k3 = G.kind == 3;
+        auto ok = [](const void *const *p, int k) {
+            for (int c = 0; c < k; ++c)
+                if (p[c] && !aligned(p[c], 256)) return false;
+            return true;
+        };
+        if (!ok(G.in, k3 ? 6 : 3) || !ok(G.lam, k3 ? 3 : 2) || !ok(G.D, k3 ? 9 : 4) || !ok(G.phi, k3 ? 3 : 1))
+            return false;
+        if (G.flags && !aligned(G.flags, 256)) return false;
+    }
+    return true;
+}
+
 // The descriptor of matrices [start, start + len) of group G (every plane
 // pointer advanced by start; a descriptor covers at most KSYM_CHUNK).
 template <typename T> GroupDesc<T> make_desc(const ksym_group &G, int64_t start, int64_t len) {
@@ -859,7 +879,7 @@ ksym_status mixed_grid(const ksym_opts &o, int64_t ntiles, int *grid) {
 // Counter reset and the persistent mixed kernel over descriptor and tile
 // tables already in device memory.
 ksym_status launch_mixed(ksym_dtype dtype, const ksym_opts &o, const void *d_groups, const TileInfo *d_tiles,
-                         int32_t ndesc, int64_t ntiles, int grid, void *ws, hipStream_t st) {
+                         int32_t ndesc, int64_t ntiles, int grid, bool stream, void *ws, hipStream_t st) {
     if (ws) {
         hipError_t e = launch(&k_zero_u32, dim3(1), dim3(64), st, (unsigned *)ws, 2);
         if (e != hipSuccess) return hip_fail(e, "launch k_zero_u32");
@@ -881,7 +901,7 @@ ksym_status launch_mixed(ksym_dtype dtype, const ksym_opts &o, const void *d_gro
         a.prm.drain_tiles = o.drain_tiles;
         a.prm.counters = (unsigned *)ws;
         finish_params(a.prm);
-        MixK<T> k = pick_mixed<T>(o.block, o.mats_per_lane);
+        MixK<T> k = pick_mixed<T>(o.block, o.mats_per_lane, stream);
         hipError_t e = launch(k, dim3(grid), dim3(o.block), st, a);
         if (e != hipSuccess) return hip_fail(e, "launch k_mixed");
         return KSYM_OK;
@@ -935,6 +955,7 @@ ksym_status ksym_plan_create(ksym_dtype dtype, int32_t ngroups, const ksym_group
     p->opts = o;
     p->ngroups = (int32_t)ndesc;
     p->ntiles = ntiles;
+    p->stream = groups_line_aligned(ngroups, groups);
     s = mixed_grid(o, ntiles, &p->grid);
     if (s != KSYM_OK) { delete p; return s; }
     // one (descriptor, first-matrix offset) entry per wave tile
@@ -972,7 +993,7 @@ ksym_status ksym_plan_run(ksym_plan *p, void *ws, size_t ws_bytes, void *stream)
     if (!p) return fail(KSYM_E_ARG, "plan is NULL");
     ksym_status s = check_ws(ws, ws_bytes);
     if (s != KSYM_OK) return s;
-    return launch_mixed(p->dtype, p->opts, p->d_groups, p->d_tiles, p->ngroups, p->ntiles, p->grid, ws,
+    return launch_mixed(p->dtype, p->opts, p->d_groups, p->d_tiles, p->ngroups, p->ntiles, p->grid, p->stream, ws,
                         (hipStream_t)stream);
 }
 
@@ -1152,7 +1173,8 @@ ksym_status ksym_mixed_run_noalloc(ksym_dtype dtype, int32_t ngroups, const ksym
     };
     s = dtype == KSYM_F32 ? tables(float()) : tables(double());
     if (s != KSYM_OK) return s;
-    return launch_mixed(dtype, o, d_desc, d_tiles, (int32_t)ndesc, ntiles, grid, ws, st);
+    return launch_mixed(dtype, o, d_desc, d_tiles, (int32_t)ndesc, ntiles, grid,
+                        groups_line_aligned(ngroups, groups), ws, st);
 }
 
 }  // extern "C"

@@ -1254,13 +1254,13 @@ template <typename T> struct TableInputs {
     __device__ __forceinline__ const T *aos() const { return nullptr; }
 };
 
-template <typename T, int MPL>
+template <typename T, int MPL, int LP>
 __device__ __forceinline__ void load_mixed(WIn<T, MPL, false> &in, cptr<GroupDesc<T>> g, uint32_t base) {
-    load_wtile3<T, MPL, false, kCached>(in, TableInputs<T>{g}, (uint32_t)g->n, base);
+    load_wtile3<T, MPL, false, LP>(in, TableInputs<T>{g}, (uint32_t)g->n, base);
 }
 
 // One 2x2 wave tile of a mixed batch from inputs already in registers.
-template <typename T, int MPL>
+template <typename T, int MPL, int SP>
 __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space(4))) GroupDesc<T> &g,
                                               const WIn<T, MPL, false> &in, uint32_t base) {
     const uint32_t n = (uint32_t)g.n;
@@ -1269,19 +1269,26 @@ __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space
                        g.p3.out[O_D + 2], g.p3.out[O_D + 3], g.p3.out[O_PHI]};
 #pragma unroll
     for (int k = 0; k < MPL; ++k)
-        eig2_lane<T, kCached>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, n, base + k * WAVE + lane);
+        eig2_lane<T, SP>(in.a[k][0], in.a[k][1], in.a[k][2], out, g.p3.flags, n, base + k * WAVE + lane);
 }
 
 // One persistent launch over all groups.  Wave tile t is described by
 // tiles[t] (a tile never spans two groups, so a wave runs one kind at a
 // time); the wave reads the descriptor of tile t + 2*stride and the inputs of
 // tile t + stride while it computes tile t.  3x3 groups share the wave's
-// refinement queue.
-template <typename T, int BS, int MPL>
+// refinement queue.  STREAM: the non-temporal policy for the plane loads and
+// (float32) stores, chosen by the host when every plane starts on a 256-byte
+// boundary, so that no cache line holds parts of two waves' tiles; otherwise
+// the default policy, since two waves writing one line with non-temporal
+// stores measured up to 50 % slower.
+template <typename T, int BS, int MPL, bool STREAM>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1) ? 5 : 1)))
 void k_mixed(MixedArgs<T> a) {
     constexpr int NW = BS / WAVE;
     constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
+    // (the float64 checked path keeps its stores cached, as in k_eig3)
+    constexpr int LP = STREAM ? kStream : kCached;
+    constexpr int SP = (STREAM && sizeof(T) == 4) ? kStream : kCached;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
     __shared__ int qcount[NW];
     WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
@@ -1298,14 +1305,14 @@ void k_mixed(MixedArgs<T> a) {
         const bool has_next = t + stride < a.ntiles;
         TileInfo nxt2 = {0, 0};
         if (t + 2 * stride < a.ntiles) nxt2 = tile_at(tiles, t + 2 * stride);
-        if (has_next) load_mixed<T, MPL>(in_nxt, groups + nxt.group, nxt.base);
+        if (has_next) load_mixed<T, MPL, LP>(in_nxt, groups + nxt.group, nxt.base);
         const auto &g = groups[cur.group];
         const uint32_t n = (uint32_t)g.n;
         if (g.kind == 3)
-            wtile_eig3<T, PATH, MPL, false, kCached, false>(planes_of(cur.group), planes_of, cur.group, a.prm,
-                                                     in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
+            wtile_eig3<T, PATH, MPL, false, SP, false>(planes_of(cur.group), planes_of, cur.group, a.prm,
+                                                in_cur, n, cur.base, my, qn, qage, refined, nonfinite);
         else
-            wtile_eig2_in<T, MPL>(g, in_cur, cur.base);
+            wtile_eig2_in<T, MPL, SP>(g, in_cur, cur.base);
         cur = nxt;
         nxt = nxt2;
         in_cur = in_nxt;
@@ -1314,7 +1321,7 @@ void k_mixed(MixedArgs<T> a) {
         // the first tile peeled off, as in k_eig3: inside the loop the inputs
         // are register copies and need no memory wait
         cur = tile_at(tiles, t);
-        load_mixed<T, MPL>(in_cur, groups + cur.group, cur.base);
+        load_mixed<T, MPL, LP>(in_cur, groups + cur.group, cur.base);
         if (t + stride < a.ntiles) nxt = tile_at(tiles, t + stride);
         step();
         for (t += stride; t < a.ntiles; t += stride) step();

@@ -516,6 +516,37 @@ def test_mixed_plan_matches_individual_calls(ksym):
     plan.close()
 
 
+def test_mixed_plan_line_aligned_streams_same_results(ksym):
+    """The same 64 groups with every plane on a 256-byte boundary (row stride
+    rounded up to 64 elements): the plan takes the streaming kernel variant,
+    and its outputs, flags and counters equal the packed layout's bitwise."""
+    groups, host = _mixed_case(ksym, seed=208)
+    plan = ksym.Plan(groups)
+    plan.run()
+    torch.cuda.synchronize()
+    refined = int(plan.ws[0].item())
+    plan.close()
+    lined = []
+    for k, t, out in groups:
+        s = t.shape[1]
+        pl = ksym.line_aligned_planes(t.shape[0], s, fill=t)
+        o = {key: ksym.line_aligned_planes(v.shape[0], s) if v.dim() == 2 else ksym.line_aligned_planes(1, s)[0]
+             for key, v in out.items() if key != "flags"}
+        o["flags"] = ksym.line_aligned_planes(1, s, dtype=torch.uint8)[0]
+        lined.append((k, pl, o))
+    assert all(p.data_ptr() % 256 == 0 for _, pl, o in lined for p in pl)
+    plan = ksym.Plan(lined)
+    plan.run()
+    torch.cuda.synchronize()
+    assert int(plan.ws[0].item()) == refined
+    for (k, t, out), (_, pl, o) in zip(groups, lined):
+        for key in ("lam", "D", "phi"):
+            got = torch.stack(o[key]) if isinstance(o[key], list) else o[key]
+            assert torch.equal(got.view(torch.int32), out[key].view(torch.int32)), (k, key, t.shape)
+        assert torch.equal(o["flags"], out["flags"])
+    plan.close()
+
+
 def test_mixed_plan_graph_replays(ksym):
     """The plan captured in a HIP graph and replayed three times, with eager
     work (clearing the outputs) between replays: every replay reproduces the
@@ -638,13 +669,14 @@ def test_mixed_workload_full_size(ksym):
         s, k = int(s), int(k)
         P = rng.standard_normal((6 if k == 3 else 3, s), dtype=np.float32)
         host.append(P)
-        t = to_dev(P, torch.float32)
+        # the benchmark's layout: every plane on a 256-byte boundary
+        t = ksym.line_aligned_planes(P.shape[0], s, fill=P)
         if k == 3:
-            out = {"lam": torch.empty((3, s), device="cuda"), "D": torch.empty((9, s), device="cuda"),
-                   "phi": torch.empty((3, s), device="cuda")}
+            out = {"lam": ksym.line_aligned_planes(3, s), "D": ksym.line_aligned_planes(9, s),
+                   "phi": ksym.line_aligned_planes(3, s)}
         else:
-            out = {"lam": torch.empty((2, s), device="cuda"), "D": torch.empty((4, s), device="cuda"),
-                   "phi": torch.empty((s,), device="cuda")}
+            out = {"lam": ksym.line_aligned_planes(2, s), "D": ksym.line_aligned_planes(4, s),
+                   "phi": ksym.line_aligned_planes(1, s)[0]}
         groups.append((k, t, out))
     plan = ksym.Plan(groups, opts=ksym.tuned_opts("mixed", ksym.F32))
     stream = torch.cuda.Stream()
@@ -657,6 +689,8 @@ def test_mixed_workload_full_size(ksym):
     r2 = {"lam": [], "D": [], "phi": []}
     P3, P2 = [], []
     for (k, t, out), P in zip(groups, host):
+        t = torch.stack(t)
+        out = {key: torch.stack(v) if isinstance(v, list) else v for key, v in out.items()}
         if k == 3:
             pr = props3_gpu(t, out["lam"], out["D"])
             assert pr["order"], pr
