@@ -220,6 +220,11 @@ ksym_status ksym_zero_counters(void *ws, size_t ws_bytes, void *stream);
  * flags = optional uint8 plane (KSYM_FLAG_* bits).
  * ws  = workspace of ksym_eig3_workspace_bytes() bytes, or NULL (no counters).
  * Output arrays may be NULL, and so may single planes: those are not written.
+ * Performance: planes are read and written in tiles of 64 (float32) or 32
+ * (float64) consecutive elements per wavefront; output planes that start on
+ * 256-byte boundaries keep every cache line within one tile, and measured
+ * 30-40 % faster than output planes offset from that (input alignment
+ * matters about 5 %).
  * Eigenvalues-only mode (KSYM_F32): when no plane of D and none of phi is
  * requested, a reduced kernel runs the float64 cubic stage of §4 alone (the
  * angle solve, the check and the refinement serve the eigenvectors) and

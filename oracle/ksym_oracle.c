@@ -426,7 +426,9 @@ void ko_jacobi3_ld(const double A6[6], double lam_out[3], double V_out[9],
 /*   Abar = D [diag(lam_bar) + F o (D^T D_bar)] D^T,                         */
 /*   F_ij = (lam_j - lam_i) / ((lam_j - lam_i)^2 + eps^2), F_ii = 0,          */
 /* and the six plane gradients gA_ii = Abar_ii, gA_ij = Abar_ij + Abar_ji.   */
-/* eps = 0 gives the exact 1 / (lam_j - lam_i).                              */
+/* eps = 0 gives the exact 1 / (lam_j - lam_i).  An exactly repeated pair    */
+/* with eps = 0 takes F_ij = 0, the value of the regularised weight at      */
+/* lam_j = lam_i for every eps > 0 (the formula would read 0/0 there).       */
 /* Angle cotangents (phi, gphi non-NULL): with D = R1 R2 R3 (eq. (2.6)) and  */
 /* R_k = exp(phi_k [e_k]x), D^T dD = [w]x with w = M dphi, the columns of M  */
 /* R3^T R2^T e1 = (c2 c3, -c2 s3, s2), R3^T e2 = (s3, c3, 0), e3; so gphi     */
@@ -465,7 +467,7 @@ void ko_eig3_bwd(const double lam[3], const double D9[9], const double glam[3],
                 M[i][j] = glam ? glam[i] : 0.0;
             } else {
                 double d = lam[j] - lam[i];
-                M[i][j] = d / (d * d + eps * eps) * E[i][j];
+                M[i][j] = (d != 0.0 ? d / (d * d + eps * eps) : 0.0) * E[i][j];
             }
         }
     /* Abar = D M D^T */
@@ -515,7 +517,7 @@ void ko_eig2_bwd(const double lam[2], const double D4[4], const double glam[2], 
                 M[i][j] = glam ? glam[i] : 0.0;
             } else {
                 double d = lam[j] - lam[i];
-                M[i][j] = d / (d * d + eps * eps) * E[i][j];
+                M[i][j] = (d != 0.0 ? d / (d * d + eps * eps) : 0.0) * E[i][j];
             }
         }
     for (int i = 0; i < 2; ++i)

@@ -137,7 +137,9 @@ def _ptr_array(ptrs):
 
 
 def _rows(t, k):
-    """Pointers of the k rows of a contiguous (k, n) tensor, or of a list of k 1-D tensors."""
+    """Pointers of the k rows of a (k, n) tensor whose rows are each contiguous
+    (a contiguous tensor, or a view of a wider one as _planes makes), or of a
+    list of k 1-D tensors."""
     if isinstance(t, (list, tuple)):
         assert len(t) == k
         n = t[0].numel()
@@ -145,12 +147,31 @@ def _rows(t, k):
             if not x.is_contiguous() or x.numel() != n or x.dtype != t[0].dtype or x.device != t[0].device:
                 raise ValueError("planes must be contiguous, same length, dtype and device")
         return [x.data_ptr() for x in t], n, t[0]
-    if t.dim() != 2 or t.shape[0] != k or not t.is_contiguous():
-        raise ValueError(f"expected a contiguous ({k}, n) tensor, got shape {tuple(t.shape)}")
+    if t.dim() != 2 or t.shape[0] != k:
+        raise ValueError(f"expected a ({k}, n) tensor, got shape {tuple(t.shape)}")
     n = t.shape[1]
+    if t.is_contiguous():
+        row = n
+    elif t.stride(1) == 1 and t.stride(0) >= n:
+        row = t.stride(0)
+    else:
+        raise ValueError(f"the rows of the ({k}, n) tensor must each be contiguous (stride {tuple(t.stride())})")
     es = t.element_size()
     base = t.data_ptr()
-    return [base + c * n * es for c in range(k)], n, t
+    return [base + c * row * es for c in range(k)], n, t
+
+
+def _planes(k, n, dtype, device):
+    """A (k, n) tensor of output planes that each start on a 256-byte
+    boundary: contiguous when n elements fill whole 256-byte blocks, else a
+    view of a (k, stride) allocation with the row stride rounded up.  Output
+    planes that share cache lines between the tiles of two waves measured
+    30-40 % slower."""
+    es = torch.empty((), dtype=dtype).element_size()
+    stride = -(-max(int(n), 1) * es // 256) * 256 // es
+    if stride == n:
+        return torch.empty((k, n), dtype=dtype, device=device)
+    return torch.empty((k, stride), dtype=dtype, device=device)[:, :n]
 
 
 def _stream(t):
@@ -197,12 +218,10 @@ def line_aligned_planes(k, n, dtype=torch.float32, device="cuda", fill=None):
     1-D views.  Mixed-batch groups laid out this way let the launch stream its
     loads and stores (include/ksym.h, ksym_group).  fill: optional (k, n)
     tensor or array copied in."""
-    es = torch.empty((), dtype=dtype).element_size()
-    stride = -(-max(int(n), 1) * es // 256) * 256 // es
-    t = torch.empty((k, stride), dtype=dtype, device=device)
+    t = _planes(k, n, dtype, device)
     if fill is not None:
-        t[:, :n].copy_(torch.as_tensor(fill))
-    return [t[c, :n] for c in range(k)]
+        t.copy_(torch.as_tensor(fill))
+    return [t[c] for c in range(k)]
 
 
 def workspace(device=None):
@@ -219,8 +238,8 @@ def eig2(planes, opts=None, out=None):
     dt = _dt(ref)
     o = _opts(dt, opts, _kind="eig2")
     if out is None:
-        out = {"lam": torch.empty((2, n), dtype=ref.dtype, device=ref.device),
-               "D": torch.empty((4, n), dtype=ref.dtype, device=ref.device),
+        out = {"lam": _planes(2, n, ref.dtype, ref.device),
+               "D": _planes(4, n, ref.dtype, ref.device),
                "phi": torch.empty((n,), dtype=ref.dtype, device=ref.device),
                "flags": torch.empty((n,), dtype=torch.uint8, device=ref.device)}
     lam = _ptr_array(_rows(out["lam"], 2)[0]) if out.get("lam") is not None else None
@@ -233,9 +252,8 @@ def eig2(planes, opts=None, out=None):
 
 # ---------------------------------------------------------------- 3x3 -------
 def _alloc3(n, ref, outputs):
-    kw = dict(dtype=ref.dtype, device=ref.device)
-    shapes = {"lam": (3, n), "D": (9, n), "phi": (3, n), "gap": (3, n)}
-    out = {k: torch.empty(shapes[k], **kw) for k in shapes if k in outputs}
+    rows = {"lam": 3, "D": 9, "phi": 3, "gap": 3}
+    out = {k: _planes(rows[k], n, ref.dtype, ref.device) for k in rows if k in outputs}
     if "flags" in outputs:
         out["flags"] = torch.empty((n,), dtype=torch.uint8, device=ref.device)
     return out
@@ -299,7 +317,7 @@ def eig3_backward(lam, D, glam=None, gD=None, gap=None, eps_rel=None, out=None, 
     gd = _ptr_array(_rows(gD, 9)[0]) if gD is not None else None
     gp = _ptr_array(_rows(gap, 3)[0]) if gap is not None else None
     if out is None:
-        out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
+        out = _planes(6, n, ref.dtype, ref.device)
     if gphi is not None:
         if phi is None:
             raise ValueError("gphi needs the angles phi")
@@ -329,7 +347,7 @@ def eig2_backward(lam, D, glam=None, gD=None, gphi=None, eps_rel=None, out=None)
             raise ValueError("gphi must be a contiguous (n,) tensor of the planes' dtype")
         gp = gphi.data_ptr()
     if out is None:
-        out = torch.empty((3, n), dtype=ref.dtype, device=ref.device)
+        out = _planes(3, n, ref.dtype, ref.device)
     _check(_lib.ksym_eig2_backward(dt, n, _ptr_array(lp), _ptr_array(Dp), gl, gd, gp,
                                    _ptr_array(_rows(out, 3)[0]), float(eps_rel), _stream(ref)))
     return out
@@ -341,7 +359,7 @@ def compose3(lam, phi, out=None):
     lp, n, ref = _rows(lam, 3)
     fp = _rows(phi, 3)[0]
     if out is None:
-        out = torch.empty((6, n), dtype=ref.dtype, device=ref.device)
+        out = _planes(6, n, ref.dtype, ref.device)
     _check(_lib.ksym_compose3(_dt(ref), n, _ptr_array(lp), _ptr_array(fp), _ptr_array(_rows(out, 6)[0]),
                               _stream(ref)))
     return out
@@ -354,7 +372,7 @@ def compose2(lam, phi, out=None):
     if phi.dtype != ref.dtype or not phi.is_contiguous() or phi.numel() != n:
         raise ValueError("phi must be a contiguous (n,) tensor of lam's dtype")
     if out is None:
-        out = torch.empty((3, n), dtype=ref.dtype, device=ref.device)
+        out = _planes(3, n, ref.dtype, ref.device)
     _check(_lib.ksym_compose2(_dt(ref), n, _ptr_array(lp), phi.data_ptr(), _ptr_array(_rows(out, 3)[0]),
                               _stream(ref)))
     return out

@@ -913,6 +913,14 @@ template <typename T> __device__ __forceinline__ Eig2<T> eig2_one(T a11, T a22, 
 // Slots: 0 = max, 1 = min, 2 = mid; gaps g12 = lam0 - lam1, g13 = lam0 - lam2,
 // g32 = lam2 - lam1.  wb: the body-rate cotangent of the Euler angles (see
 // angle_body_cotangent), added to (E_32, E_13, E_21); zeros without angles.
+// The gap-regularised weight d / (d^2 + eps^2) of the adjoint, with the
+// value 0 that it takes for every eps > 0 also at d = 0 when eps = 0 (an
+// exactly repeated eigenvalue of the zero matrix, whose eps = eps_rel ||lam||
+// vanishes), where the formula would read 0/0.
+template <typename T> __device__ __forceinline__ T gap_weight(T d, T eps2) {
+    return d != T(0) ? Mth<T>::div(d, d * d + eps2) : T(0);
+}
+
 template <typename T>
 __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD[9], T g12, T g13,
                                          T g32, T eps2, const T wb[3], T gA[6]) {
@@ -929,9 +937,9 @@ __device__ __forceinline__ void adjoint3(const T D[9], const T gl[3], const T gD
     K02 += wb[1];
     K12 -= wb[0];
     // F_01 = (lam1 - lam0)/(..) = -g12/(g12^2+eps2); F_02 = -g13/(..); F_12 = (lam2 - lam1)/(..) = g32/(..)
-    const T S01 = -M::div(g12, g12 * g12 + eps2) * K01;
-    const T S02 = -M::div(g13, g13 * g13 + eps2) * K02;
-    const T S12 = M::div(g32, g32 * g32 + eps2) * K12;
+    const T S01 = -gap_weight(g12, eps2) * K01;
+    const T S02 = -gap_weight(g13, eps2) * K02;
+    const T S12 = gap_weight(g32, eps2) * K12;
     const T S00 = T(2) * gl[0], S11 = T(2) * gl[1], S22 = T(2) * gl[2];
     // Tm = D S (row-major)
     T Tm[9];
@@ -980,7 +988,7 @@ __device__ __forceinline__ void adjoint2(const T D[4], const T gl[2], const T gD
                                          T gA[3]) {
     const T e12 = D[0] * gD[1] + D[2] * gD[3];
     const T e21 = D[1] * gD[0] + D[3] * gD[2] + gphi;
-    const T f = Mth<T>::div(d, d * d + eps2);
+    const T f = gap_weight(d, eps2);
     const T m00 = gl[0], m01 = f * e12, m10 = -f * e21, m11 = gl[1];
     const T t00 = D[0] * m00 + D[1] * m10, t01 = D[0] * m01 + D[1] * m11;
     const T t10 = D[2] * m00 + D[3] * m10, t11 = D[2] * m01 + D[3] * m11;

@@ -425,3 +425,41 @@ def test_near_isotropic_all_paths(ksym, spread):
         jac = oracle.jacobi3(P64)["lam"]
         assert H.sorted_lam_err(P64, g["lam"], jac).max() < 1e-14
         assert H.residual3(P64, g["lam"], g["D"]).max() < 1e-13
+
+
+def test_library_outputs_start_on_256_byte_boundaries(ksym):
+    """At a batch size that is not a multiple of 64, the planes the binding
+    allocates (forward, backward, inverse map, 2x2) each start on a 256-byte
+    boundary (a row-strided view), and every result equals, bitwise, the same
+    call with contiguous caller-provided outputs."""
+    n = (1 << 16) - 24
+    P = synth.make_precision(n, seed=synth.BASE_SEED + 81)
+    A = to_dev(P, torch.float32)
+    print(f"line-aligned outputs: n={n}", flush=True)
+    out = ksym.eig3(A, outputs=("lam", "D", "phi", "gap", "flags"))
+    for key in ("lam", "D", "phi", "gap"):
+        rows = ksym._rows(out[key], out[key].shape[0])[0]
+        assert all(p % 256 == 0 for p in rows), key
+    mine = {"lam": torch.empty((3, n), device="cuda"), "D": torch.empty((9, n), device="cuda"),
+            "phi": torch.empty((3, n), device="cuda"), "gap": torch.empty((3, n), device="cuda"),
+            "flags": torch.empty((n,), dtype=torch.uint8, device="cuda")}
+    ksym.eig3(A, out=mine)
+    torch.cuda.synchronize()
+    for key in mine:
+        assert torch.equal(out[key], mine[key]), key
+    g = torch.Generator(device="cuda").manual_seed(5)
+    w = torch.randn((3, n), device="cuda", generator=g)
+    G = torch.randn((9, n), device="cuda", generator=g)
+    gA = ksym.eig3_backward(out["lam"], out["D"], w, G, gap=out["gap"])
+    gA2 = ksym.eig3_backward(mine["lam"], mine["D"], w, G, gap=mine["gap"], out=torch.empty((6, n), device="cuda"))
+    assert all(p % 256 == 0 for p in ksym._rows(gA, 6)[0]) and torch.equal(gA, gA2)
+    C = ksym.compose3(out["lam"], out["phi"])
+    assert torch.equal(C, ksym.compose3(mine["lam"], mine["phi"], out=torch.empty((6, n), device="cuda")))
+    B = to_dev(np.random.default_rng(6).uniform(-1, 1, (3, n)), torch.float32)
+    o2 = ksym.eig2(B)
+    m2 = {"lam": torch.empty((2, n), device="cuda"), "D": torch.empty((4, n), device="cuda"),
+          "phi": torch.empty((n,), device="cuda"), "flags": torch.empty((n,), dtype=torch.uint8, device="cuda")}
+    ksym.eig2(B, out=m2)
+    torch.cuda.synchronize()
+    for key in m2:
+        assert torch.equal(o2[key], m2[key]), key

@@ -423,6 +423,33 @@ def test_adjoint_regulariser_limit():
     assert np.abs(c).max() < 1e-10
 
 
+def test_adjoint_at_exactly_repeated_eigenvalues():
+    """With eps = 0 an exactly repeated pair takes the weight the regularised
+    adjoint gives it for every eps > 0 (zero), instead of 0/0: on the zero
+    matrix, diag(a, a, c) and a 2x2 multiple of I the eps = 0 adjoint is finite
+    and equals the adjoint at eps = 1e-150 (a regulariser that changes no
+    weight of a separated pair), and for the zero matrix it is the eigenvalue
+    part alone."""
+    rng = np.random.default_rng(43)
+    P = np.zeros((6, 3))
+    P[0, 1], P[1, 1], P[2, 1] = 0.5, 0.5, -0.25        # diag(a, a, c)
+    P[0, 2], P[1, 2], P[2, 2] = 0.0, 1.0, 1.0          # diag(0, 1, 1)
+    o = oracle.eig3(P)
+    w, G = rng.standard_normal((3, 3)), rng.standard_normal((9, 3))
+    a = oracle.eig3_bwd(o["lam"], o["D"], w, G, 0.0)
+    b = oracle.eig3_bwd(o["lam"], o["D"], w, G, 1e-150)
+    assert np.all(np.isfinite(a)) and np.abs(a - b).max() < 1e-14
+    D = H.as_mats(o["D"])[0]
+    M = D @ np.diag(w[:, 0]) @ D.T
+    ref0 = [M[0, 0], M[1, 1], M[2, 2], 2 * M[0, 1], 2 * M[0, 2], 2 * M[1, 2]]
+    assert np.abs(a[:, 0] - ref0).max() < 1e-15
+    Q = np.array([[2.0, 0.0], [2.0, 0.0], [0.0, 0.0]])  # 2I and the zero 2x2
+    o2 = oracle.eig2(Q)
+    g2 = oracle.eig2_bwd(o2["lam"], o2["D"], rng.standard_normal((2, 2)), rng.standard_normal((4, 2)),
+                         rng.standard_normal(2), eps=0.0)
+    assert np.all(np.isfinite(g2))
+
+
 def test_eig2_adjoint_against_central_differences():
     """2x2 adjoint of L = sum w*lam + sum G*D + g*phi (oracle) against central
     differences of the oracle's 2x2 forward (§3, pinned above), on matrices

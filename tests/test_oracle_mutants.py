@@ -50,7 +50,8 @@ MUTANTS = [
     ("eig2 phi factor", "f = 0.5 * atan(2.0 * a12 / d);", "f = 0.5 * atan(a12 / d);"),
     ("eig2 lam2 sign", "lam[1] = 0.5 * (a11 + a22 - sg * root);", "lam[1] = 0.5 * (a11 + a22 + sg * root);"),
     ("eig2 sign(0)", "double sg = (d >= 0.0) ? 1.0 : -1.0;", "double sg = (d > 0.0) ? 1.0 : -1.0;"),
-    ("bwd transposed E", "M[i][j] = d / (d * d + eps * eps) * E[i][j];", "M[i][j] = d / (d * d + eps * eps) * E[j][i];"),
+    ("bwd transposed E", "M[i][j] = (d != 0.0 ? d / (d * d + eps * eps) : 0.0) * E[i][j];",
+     "M[i][j] = (d != 0.0 ? d / (d * d + eps * eps) : 0.0) * E[j][i];"),
     ("bwd off-diagonal plane", "gA[4] = Abar[0][2] + Abar[2][0];", "gA[4] = Abar[0][2] + Abar[0][2];"),
     ("bwd gap sign", "double d = lam[j] - lam[i];", "double d = lam[i] - lam[j];"),
     ("eig2 bwd angle slot", "E[1][0] += gphi;", "E[0][1] += gphi;"),
