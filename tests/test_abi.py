@@ -463,3 +463,37 @@ def test_noalloc_rejects_bad_batches_before_any_hip_call(lib):
     assert f(0, 2, g, None, ctypes.c_void_p(ws + 2), 256, None) == 3  # misaligned
     assert f(0, 2, g, None, ctypes.c_void_p(arr[0].lam[1]), 256, None) == 1  # ws inside an output
     assert "overlaps" in _err(lib)
+
+
+def test_binding_row_pointers_and_line_aligned_planes():
+    """Host logic of the binding (CPU tensors, no GPU call): row pointers of a
+    contiguous (k, n) tensor, of a row-strided view and of a plane list; a
+    transposed view is refused; _planes and line_aligned_planes round the
+    row stride up to 256 bytes only when n needs it."""
+    torch = pytest.importorskip("torch")
+    import paper_1306_6291_amd as ksym
+    t = torch.zeros((6, 1000))
+    ptrs, n, _ = ksym._rows(t, 6)
+    assert n == 1000 and [p - ptrs[0] for p in ptrs] == [c * 4000 for c in range(6)]
+    wide = torch.zeros((3, 1024))[:, :1000]
+    ptrs, n, _ = ksym._rows(wide, 3)
+    assert n == 1000 and [p - ptrs[0] for p in ptrs] == [0, 4096, 8192]
+    with pytest.raises(ValueError):
+        ksym._rows(torch.zeros((1000, 3)).T, 3)
+    with pytest.raises(ValueError):
+        ksym._rows(torch.zeros((4, 1000)), 3)
+    planes = [torch.zeros(7) for _ in range(3)]
+    assert ksym._rows(planes, 3)[0] == [p.data_ptr() for p in planes]
+    for dtype, es in ((torch.float32, 4), (torch.float64, 8)):
+        for n in (0, 1, 63, 64, 65, 1000, 1 << 14):
+            p = ksym._planes(5, n, dtype, "cpu")
+            assert p.shape == (5, n)
+            if n > 0:
+                row = n if p.is_contiguous() else p.stride(0)
+                assert (row * es) % 256 == 0 and n <= row < n + 256 // es, (dtype, n, row)
+            lst = ksym.line_aligned_planes(3, n, dtype=dtype, device="cpu")
+            assert len(lst) == 3 and all(x.numel() == n and x.is_contiguous() for x in lst)
+            assert all((x.data_ptr() - lst[0].data_ptr()) % 256 == 0 for x in lst)
+    # contiguous when n already fills whole 256-byte blocks
+    assert ksym._planes(3, 1 << 14, torch.float32, "cpu").is_contiguous()
+    assert not ksym._planes(3, 1000, torch.float32, "cpu").is_contiguous()
