@@ -233,7 +233,8 @@ def workspace(device=None):
 # ---------------------------------------------------------------- 2x2 -------
 def eig2(planes, opts=None, out=None):
     """2x2 forward (paper §3).  planes: (3, n) tensor (A11, A22, A12).
-    Returns dict lam (2, n), D (4, n) = (D11, D12, D21, D22), phi (n,), flags (n,)."""
+    Returns dict lam (2, n), D (4, n) = (D11, D12, D21, D22), phi (n,), flags (n,);
+    lam and D rows each start on a 256-byte boundary (see eig3)."""
     ptrs, n, ref = _rows(planes, 3)
     dt = _dt(ref)
     o = _opts(dt, opts, _kind="eig2")
@@ -270,6 +271,9 @@ def _out_ptrs3(out):
 def eig3(planes, opts=None, path=None, outputs=("lam", "D", "phi", "flags"), out=None, ws=None):
     """3x3 forward (paper §4-§5).  planes: (6, n) tensor or 6 plane tensors.
     path: PATH_FP32_FIXUP (float32), PATH_FP64_PLAIN or PATH_FP64_FIXUP (float64).
+    Outputs the binding allocates are (k, n) tensors whose rows each start on
+    a 256-byte boundary: row-strided views when n needs it (use reshape, not
+    view, on them).
     ws: optional workspace() tensor; its words 0 and 1 accumulate the counts of
     refined and non-finite matrices."""
     ptrs, n, ref = _rows(planes, 6)
