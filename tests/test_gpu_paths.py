@@ -471,23 +471,25 @@ def test_autograd_angles_function(ksym):
 
 
 # ------------------------------------------------------------ mixed plan ---
-def _mixed_case(ksym, total=200000, ngroups=64, seed=206):
+def _mixed_case(ksym, total=200000, ngroups=64, seed=206, dtype=None):
+    dtype = dtype or torch.float32
     sizes, kinds = synth.mixed_group_sizes(total, ngroups, lo=100, hi=1e4, seed=seed)
     sizes[3] = 0      # an empty group
     sizes[5] = 1      # a one-matrix group
     rng = np.random.default_rng(seed)
     groups, host = [], []
+    kw = dict(dtype=dtype, device="cuda")
     for s, k in zip(sizes, kinds):
         s = int(s)
         P = rng.standard_normal((6 if k == 3 else 3, s)).astype(np.float32)
-        t = to_dev(P, torch.float32)
+        t = to_dev(P, dtype)
         if k == 3:
-            out = {"lam": torch.full((3, s), -7.0, device="cuda"), "D": torch.full((9, s), -7.0, device="cuda"),
-                   "phi": torch.full((3, s), -7.0, device="cuda"),
+            out = {"lam": torch.full((3, s), -7.0, **kw), "D": torch.full((9, s), -7.0, **kw),
+                   "phi": torch.full((3, s), -7.0, **kw),
                    "flags": torch.full((s,), 255, dtype=torch.uint8, device="cuda")}
         else:
-            out = {"lam": torch.full((2, s), -7.0, device="cuda"), "D": torch.full((4, s), -7.0, device="cuda"),
-                   "phi": torch.full((s,), -7.0, device="cuda"),
+            out = {"lam": torch.full((2, s), -7.0, **kw), "D": torch.full((4, s), -7.0, **kw),
+                   "phi": torch.full((s,), -7.0, **kw),
                    "flags": torch.full((s,), 255, dtype=torch.uint8, device="cuda")}
         groups.append((int(k), t, out))
         host.append((int(k), P))
@@ -516,11 +518,13 @@ def test_mixed_plan_matches_individual_calls(ksym):
     plan.close()
 
 
-def test_mixed_plan_line_aligned_streams_same_results(ksym):
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_mixed_plan_line_aligned_streams_same_results(ksym, dtype):
     """The same 64 groups with every plane on a 256-byte boundary (row stride
-    rounded up to 64 elements): the plan takes the streaming kernel variant,
+    rounded up to 256 bytes): the plan takes the streaming kernel variant,
     and its outputs, flags and counters equal the packed layout's bitwise."""
-    groups, host = _mixed_case(ksym, seed=208)
+    tdt = getattr(torch, dtype)
+    groups, host = _mixed_case(ksym, seed=208, dtype=tdt)
     plan = ksym.Plan(groups)
     plan.run()
     torch.cuda.synchronize()
@@ -529,8 +533,9 @@ def test_mixed_plan_line_aligned_streams_same_results(ksym):
     lined = []
     for k, t, out in groups:
         s = t.shape[1]
-        pl = ksym.line_aligned_planes(t.shape[0], s, fill=t)
-        o = {key: ksym.line_aligned_planes(v.shape[0], s) if v.dim() == 2 else ksym.line_aligned_planes(1, s)[0]
+        pl = ksym.line_aligned_planes(t.shape[0], s, dtype=tdt, fill=t)
+        o = {key: ksym.line_aligned_planes(v.shape[0], s, dtype=tdt) if v.dim() == 2
+             else ksym.line_aligned_planes(1, s, dtype=tdt)[0]
              for key, v in out.items() if key != "flags"}
         o["flags"] = ksym.line_aligned_planes(1, s, dtype=torch.uint8)[0]
         lined.append((k, pl, o))
@@ -542,7 +547,8 @@ def test_mixed_plan_line_aligned_streams_same_results(ksym):
     for (k, t, out), (_, pl, o) in zip(groups, lined):
         for key in ("lam", "D", "phi"):
             got = torch.stack(o[key]) if isinstance(o[key], list) else o[key]
-            assert torch.equal(got.view(torch.int32), out[key].view(torch.int32)), (k, key, t.shape)
+            bits = torch.int32 if tdt == torch.float32 else torch.int64
+            assert torch.equal(got.view(bits), out[key].view(bits)), (k, key, t.shape)
         assert torch.equal(o["flags"], out["flags"])
     plan.close()
 
