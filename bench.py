@@ -36,6 +36,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -57,16 +58,20 @@ BYTES_BWD_F32 = 120     # lam 12 + D 36 + glam 12 + gD 36 in, gA 24 out
 
 
 def _source_digest():
-    """sha256 of the HIP sources (csrc/*.hip, *.hpp), to tie stored counter
-    readings to the kernels they were taken on."""
+    """sha256 of the HIP sources (csrc/*.hip, *.hpp) with comments and
+    whitespace removed, to tie stored counter readings to the code they were
+    taken on (an edit of a comment leaves the readings valid)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1306_6291_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if not f.endswith((".hip", ".hpp")):
             continue
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode())
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(f.encode())
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -438,8 +438,9 @@ __device__ __forceinline__ rsrc_t plane_rsrc(const void *p, uint32_t bytes) {
 //  - stores that the refinement queue overwrites soon after: the drain waits
 //    for the wave's stores to complete, which takes longer for non-temporal
 //    ones (the float64 checked path drains often; it streams its loads only);
-//  - the mixed-batch kernel, whose groups start anywhere, so that a cache
-//    line is often shared by the tiles of two waves: it uses the default.
+//  - the mixed-batch kernel when its groups' planes start anywhere, so that
+//    a cache line is often shared by the tiles of two waves: it then uses
+//    the default (see k_mixed's STREAM variant for aligned planes).
 constexpr int kCached = 0, kStream = 2;
 template <int POL> __device__ __forceinline__ float bload(rsrc_t r, uint32_t off, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
