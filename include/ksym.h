@@ -84,8 +84,8 @@ typedef enum {
 } ksym_status;
 
 /* Per-matrix flag bits, written to the optional uint8 flags plane. */
-#define KSYM_FLAG_GENERAL   0u   /* general branch of §5 */
-#define KSYM_FLAG_DOUBLE    1u   /* two eigenvalues coincide (special case q^2 = 4p^3 != 0 of §5) */
+#define KSYM_FLAG_GENERAL   0u   /* distinct computed eigenvalues: general branch of §5 */
+#define KSYM_FLAG_DOUBLE    1u   /* two computed eigenvalues coincide to tau_dbl (special case q^2 = 4p^3 != 0 of §5) */
 #define KSYM_FLAG_TRIPLE    2u   /* p = 0: triple eigenvalue, D = I, angles 0 (§5) */
 #define KSYM_FLAG_FIXUP     4u   /* result rewritten by the float64 refinement */
 #define KSYM_FLAG_NONFINITE 8u   /* an input entry was Inf or NaN; outputs are NaN */
@@ -94,11 +94,15 @@ typedef enum {
  * Numerical paths for the 3x3 forward.
  *  KSYM_PATH_FP32_FIXUP (dtype F32 only): float32 inputs and outputs; the
  *    cubic step (p, q, arccos, cos/sin, eqs. (4.7)-(4.12)) in float64; the angle
- *    solve of §5 in float32; a float64 a-posteriori check of D; matrices that
- *    fail the check, whose relative eigenvalue gap is below tau_gap, or whose
- *    eigenvalues coincide are rewritten by a float64 refinement (isolated
+ *    solve of §5 in float32; a float32 a-posteriori check of D.  A result of
+ *    the general branch that fails the check while the middle eigenvalue lies
+ *    within tau_res sqrt(p) of another (or the eigenvalues coincide) is
+ *    computed again by the double-root branch of §5 (5.20)-(5.25) and checked
+ *    again.  Matrices that still fail, or whose relative eigenvalue gap is
+ *    below tau_gap, are rewritten by a float64 refinement (isolated
  *    eigenvector by cross products, Rayleigh-Ritz on its complement and one
- *    2x2 Jacobi rotation).
+ *    2x2 Jacobi rotation).  Differentiated calls (tau_vec > 0) refine every
+ *    double root instead.
  *  KSYM_PATH_FP64_PLAIN (dtype F64 only): the paper's formulas in float64,
  *    including the double-root branch, with no check and no refinement.
  *  KSYM_PATH_FP64_FIXUP (dtype F64 only): as PLAIN, plus the float64 check and
@@ -156,11 +160,14 @@ typedef enum {
  *                  provisional ones; a short wait keeps those lines in cache.
  *   tau_dbl        relative split (min distance of the middle eigenvalue to
  *                  the others, divided by sqrt(p)) below which the computed
- *                  eigenvalues are taken as a double root: the plain path
- *                  takes the paper's double-root branch, the checked paths
- *                  route the matrix to the refinement.  Default 1e-6 for
- *                  F64; 1e-9 for F32, whose angle solve takes its squared
- *                  cosines from float64 quotients and is checked anyway.
+ *                  eigenvalues are taken as a double root (KSYM_FLAG_DOUBLE):
+ *                  the plain path takes the paper's double-root branch; the
+ *                  float64 checked path and differentiated calls route the
+ *                  matrix to the refinement; the float32 path checks the
+ *                  general branch's result and, if it fails, the double-root
+ *                  branch's.  Default 1e-6 for F64; 1e-9 for F32, whose angle
+ *                  solve takes its squared cosines from float64 quotients
+ *                  and is checked anyway.
  * Negative thresholds (and drain_tiles < 0) select the dtype's default.
  */
 typedef struct {

@@ -30,7 +30,10 @@ __device__ __forceinline__ double rsqrt_any64(double x);
 template <typename T> struct Mth;
 
 template <> struct Mth<float> {
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    // (a constant argument is folded: the target builtin is not)
+    static __device__ __forceinline__ float sqrt(float x) {
+        return __builtin_constant_p(x) ? __builtin_sqrtf(x) : __builtin_amdgcn_sqrtf(x);
+    }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }

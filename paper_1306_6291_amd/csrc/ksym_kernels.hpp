@@ -180,11 +180,59 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     }
 }
 
+// The double-root branch of §5, eqs. (5.20)-(5.25), in float32 for a matrix
+// whose middle eigenvalue (nearly) coincides with another: the close pair is
+// taken as one eigenvalue lm (their mean) beside the isolated ls, phi3 = 0,
+// and phi1 from the selection of the general branch with G12 = 0.  The
+// columns of R1 R2 R3 are then put in the slot order (max, min, mid) (an odd
+// permutation takes a sign), and the angles are read back from that D.  Any
+// orthonormal basis of the pair's plane is an eigenbasis up to the pair's
+// split, so the residuals of this D are bounded by the split where the
+// general branch's angle formulas lose accuracy as 1 / split.
+// cos^2 phi2 = (A11 - ls) / (lm - ls) of (5.21) equals 1 - u1^2 for the
+// isolated unit eigenvector u, and at a double root A - lm I = (ls - lm) u u^T,
+// whose row i has the squared norm (ls - lm)^2 u_i^2.  Both cos^2 phi2 and
+// sin^2 phi2 are taken as quotients of such sums of squares (rows 2 and 3
+// against row 1), as the general branch forms its squared cosines: the
+// difference A11 - ls would carry the cubic step's absolute error, which the
+// square root in cos phi2 turns into its square root where cos^2 phi2 is
+// near 0 (a diagonal matrix with the isolated entry first).
+__device__ __forceinline__ void double_root_f32(const Cubic &cu, float A12, float A13, float A22, float A33,
+                                                float A23, float D[9], float phi[3]) {
+    const bool iso_max = !(cu.g13 < cu.g32);   // pair (mid, min), isolated max; else pair (max, mid)
+    const double lm = iso_max ? 0.5 * (cu.mu3 + cu.mu2) : 0.5 * (cu.mu1 + cu.mu3);
+    const double ls = iso_max ? cu.mu1 : cu.mu2;
+    const double b12 = A12, b13 = A13, b23 = A23;
+    const double e1 = cu.d1 - lm, e2 = cu.d2 - lm, e3 = cu.d3 - lm;
+    const double r1 = e1 * e1 + b12 * b12 + b13 * b13;                           // (ls - lm)^2 u1^2
+    const double r23 = e2 * e2 + e3 * e3 + b12 * b12 + b13 * b13 + 2.0 * b23 * b23;   // (ls - lm)^2 (u2^2 + u3^2)
+    const double inv = 1.0 / (r1 + r23);
+    const float s = (float)(r23 * inv), cs = (float)(r1 * inv);
+    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, 0.0f, (float)(lm - ls),
+                                              (float)(ls - lm), s, cs, 1.0f, 0.0f, true);
+    float Di[9];
+    build_D(R, Di);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        // isolated max: columns (3, 1, 2), an even permutation; isolated
+        // min: columns (1, 3, -2)
+        D[3 * r] = iso_max ? Di[3 * r + 2] : Di[3 * r];
+        D[3 * r + 1] = iso_max ? Di[3 * r] : Di[3 * r + 2];
+        D[3 * r + 2] = iso_max ? Di[3 * r + 1] : -Di[3 * r + 1];
+    }
+    extract_angles<float>(D, phi);
+}
+
 // The float32 path for one matrix: the cubic stage in float64 (with float32
 // polynomial tails), the squared cosines of the angle solve as float64
 // quotients, the rest in float32, and the a-posteriori check in float32 on
 // B = A - m I.  Outputs leave through sink.put(k, value) as soon as they
 // exist (plane k of lam, D, phi, gap), which keeps few of them in registers.
+// A result of the general branch that fails the check while the split of the
+// middle eigenvalue is below tau_res sqrt(p) gets a second attempt from the
+// double-root branch (double_root_f32), checked in the same way, before the
+// matrix goes to the refinement; the flag keeps the cubic stage's
+// classification (tau_dbl) either way.
 // Sets refine (and the isolated eigenvalue lc for the refinement, a float64
 // deviation in scaled units) and returns the flag.
 template <bool GRAD, typename Sink>
@@ -225,7 +273,9 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
         sink.template put_n<3>(O_LAM, lam);
         sink.template put_n<3>(O_GAP, gap);
     }
-    bool bad = !fin || (!cu.triple && dbl);
+    // differentiated calls refine every double root (the pair correction
+    // needs both columns of a pair); otherwise the check decides
+    bool bad = !fin || (GRAD && !cu.triple && dbl);
     if (prm.tau_gap > 0.0) {   // uniform: skipped at the default 0
         asm volatile("");      // (keeps the branch; see check_fails)
         const double l1 = __builtin_fabs(cu.m + cu.mu1), l2 = __builtin_fabs(cu.m + cu.mu2);
@@ -258,16 +308,33 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
         const bool close = split < 1e-5 * cu.sp;
         bad = bad || big || close;
         sink.template put_n<3>(O_PHI, phi);
+        sink.template put_n<9>(O_D, D);
     } else {
         sink.template put_n<3>(O_PHI, phi);
         build_D(R, D);
     }
-    sink.template put_n<9>(O_D, D);
     // ||A||_F^2 = tr(B^2) + 3 m^2 with tr(B^2) = (2/3) p
     const float fro2 = (float)__builtin_fma((2.0 / 3.0) * cu.sp, cu.sp, 3.0 * cu.m * cu.m);
-    bad = bad || check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D, (float)cu.mu1,
-                              (float)cu.mu2, prm.tau_res2_f * fro2);
-    refine = bad;
+    const float lim2 = prm.tau_res2_f * fro2;
+    bool fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D, (float)cu.mu1,
+                              (float)cu.mu2, lim2);
+    if constexpr (!GRAD) {
+        // second attempt for a (nearly) double root: the double-root branch,
+        // checked alike.  D is stored after it (it is in registers for the
+        // check anyway); the angles, already stored, are overwritten (same
+        // lane, same addresses: the stores stay in order)
+        const bool retry = fails && fin && !cu.triple && (dbl || split < prm.tau_res * cu.sp);
+        if (__ballot(retry)) {
+            if (retry) {
+                double_root_f32(cu, A12, A13, A22, A33, A23, D, phi);
+                fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
+                                     (float)cu.mu1, (float)cu.mu2, lim2);
+                sink.reloaded().template put_n<3>(O_PHI, phi);
+            }
+        }
+        sink.template put_n<9>(O_D, D);
+    }
+    refine = bad || fails;
     return flag;
 }
 
@@ -394,6 +461,11 @@ constexpr int WAVE = 64;
 // The value x, opaque to the optimizer (no instruction is emitted).
 __device__ __forceinline__ uint32_t fresh(uint32_t x) {
     asm volatile("" : "+v"(x));
+    return x;
+}
+// The same for a wave-uniform value in a scalar register.
+__device__ __forceinline__ int fresh_s(int x) {
+    asm volatile("" : "+s"(x));
     return x;
 }
 
@@ -554,6 +626,10 @@ template <typename T, int SP, typename Planes> struct LaneSink {
     __device__ __forceinline__ void flag(int f) const {
         st_plane<uint8_t, SP>(pl.flags(salt), pl.n, off, (uint8_t)f);
     }
+    // The same sink with plane pointers that are read again where it is
+    // used (a rare branch then loads its own descriptors instead of keeping
+    // the main path's in scalar registers throughout).
+    __device__ __forceinline__ LaneSink reloaded() const { return LaneSink{pl, fresh_s(salt), off}; }
 };
 
 // A refined result: scattered per-lane stores (the rare path).
@@ -778,8 +854,7 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
 // store that anything overwrites and goes straight to the barrier.
 template <typename T, int MPL, bool AOS, int NW, typename PlanesOf>
 __device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
-                                            int *qcount, int qn, unsigned &refined) {
-    const int w = wave_id();
+                                            int *qcount, int qn, int w, unsigned &refined) {
     const int lane = lane_id();
     if (qn > 0) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
     if (lane == 0) qcount[w] = qn;
@@ -845,7 +920,9 @@ void k_eig3(Eig3Args<T> args) {
     constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
     __shared__ WaveSmem<T, MPL, QUEUE, AOS> sm[NW];
     __shared__ int qcount[NW];
-    WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wave_id()];
+    // the wave index in a scalar register, kept for the final drain
+    const int wid = wave_id();
+    WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wid];
     const uint32_t n = (uint32_t)args.prm.n;
     const uint32_t ntiles = (n + WT - 1) / WT;
     KernargPlanes<T> pl;
@@ -857,7 +934,7 @@ void k_eig3(Eig3Args<T> args) {
     int qn = 0, qage = 0;
     WIn<T, MPL, AOS> cur, nxt;
     const uint32_t stride = gridDim.x * NW;
-    uint32_t t = blockIdx.x * NW + wave_id();
+    uint32_t t = blockIdx.x * NW + wid;
     auto inputs = [&](uint32_t tt) {
         return KernargInputs<T>{(uint32_t)(offsetof(Eig3Args<T>, p) + offsetof(Eig3Ptrs<T>, in)),
                                 (uint32_t)offsetof(Eig3Args<T>, aos), (int)(tt * (uint32_t)args.prm.zero)};
@@ -882,7 +959,7 @@ void k_eig3(Eig3Args<T> args) {
         step();
         for (t += stride; t < ntiles; t += stride) step();
     }
-    if constexpr (QUEUE) final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, refined);
+    if constexpr (QUEUE) final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, wid, refined);
     add_counters(args.prm.counters, refined, nonfinite);
 }
 
@@ -1292,14 +1369,15 @@ void k_mixed(MixedArgs<T> a) {
     constexpr int SP = (STREAM && sizeof(T) == 4) ? kStream : kCached;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
     __shared__ int qcount[NW];
-    WaveSmem<T, MPL, true, false> *my = &sm[wave_id()];
+    const int wid = wave_id();
+    WaveSmem<T, MPL, true, false> *my = &sm[wid];
     const cptr<GroupDesc<T>> groups = as_const(a.groups);
     const cptr<TileInfo> tiles = as_const(a.tiles);
     auto planes_of = [&](int g) { return TablePlanes<T>{&groups[g].p3, (uint32_t)groups[g].n}; };
     unsigned refined = 0, nonfinite = 0;
     int qn = 0, qage = 0;
     const int64_t stride = (int64_t)gridDim.x * NW;
-    int64_t t = (int64_t)blockIdx.x * NW + wave_id();
+    int64_t t = (int64_t)blockIdx.x * NW + wid;
     TileInfo cur = {0, 0}, nxt = {0, 0};
     WIn<T, MPL, false> in_cur, in_nxt;
     auto step = [&]() {
@@ -1327,7 +1405,7 @@ void k_mixed(MixedArgs<T> a) {
         step();
         for (t += stride; t < a.ntiles; t += stride) step();
     }
-    final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, refined);
+    final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, wid, refined);
     add_counters(a.prm.counters, refined, nonfinite);
 }
 

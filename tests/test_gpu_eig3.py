@@ -318,6 +318,42 @@ def test_all_matrices_refined_f32(ksym):
         check_f32_result(P64, g, lam_ref, V_ref, f"all-refined {block}x{mpl}")
 
 
+def test_double_roots_second_attempt_f32(ksym):
+    """Matrices with a repeated eigenvalue: Haar-rotated diag(a, a, c)
+    rounded to float32 (the pair's split is then at the rounding level) and
+    diagonal matrices with one entry repeated (an exact zero split).  Where
+    the general branch's result fails the check, the double-root branch of
+    §5 (5.20)-(5.25) is tried before the refinement; nearly all of these
+    matrices then need no refinement, every result meets the float32
+    tolerances, and the flags keep the cubic step's classification (the
+    same branch bits as when tau_gap forces every matrix into the
+    refinement)."""
+    rng = np.random.default_rng(16)
+    n_rot, n_diag = 16384, 4096
+    a, c = rng.uniform(-1, 1, n_rot), rng.uniform(-1, 1, n_rot)
+    Q = synth.haar_rotations(rng, n_rot)
+    P_rot = synth._sandwich(Q, np.stack([a, a, c], 1))
+    d = rng.uniform(-1, 1, (3, n_diag))
+    j = rng.integers(0, 3, n_diag)
+    k = (j + 1 + rng.integers(0, 2, n_diag)) % 3
+    d[k, np.arange(n_diag)] = d[j, np.arange(n_diag)]
+    P_diag = np.concatenate([d, np.zeros((3, n_diag))])
+    P32 = np.ascontiguousarray(np.concatenate([P_rot, P_diag], axis=1).astype(np.float32))
+    P64 = P32.astype(np.float64)
+    lam_ref, V_ref = certified_reference(P64)
+    g = _run(ksym, P32, torch.float32)
+    stats = check_f32_result(P64, g, lam_ref, V_ref, "double roots")
+    fixed = (g["flags"] & 4) != 0
+    print("double roots:", stats, "refined: rotated", fixed[:n_rot].mean(), "diagonal", fixed[n_rot:].mean())
+    assert fixed[:n_rot].mean() < 0.005, fixed[:n_rot].mean()
+    assert fixed[n_rot:].mean() < 0.005, fixed[n_rot:].mean()
+    assert int(g["ws"][0]) == int(fixed.sum())
+    forced = _run(ksym, P32, torch.float32, tau_gap=1.0)
+    assert np.all(forced["flags"] & 4)
+    check_f32_result(P64, forced, lam_ref, V_ref, "double roots, all refined")
+    assert np.array_equal(forced["flags"] & 3, g["flags"] & 3)
+
+
 def test_eigenvalues_and_angles_mode_f32(ksym):
     """Reduced-output mode lam + phi (no D planes, 48 B per matrix): the
     angles alone determine D (eq. (2.6)), so a caller can drop D's 36 B.  The
