@@ -95,10 +95,11 @@ typedef enum {
  *  KSYM_PATH_FP32_FIXUP (dtype F32 only): float32 inputs and outputs; the
  *    cubic step (p, q, arccos, cos/sin, eqs. (4.7)-(4.12)) in float64; the angle
  *    solve of §5 in float32; a float32 a-posteriori check of D.  A result of
- *    the general branch that fails the check while the middle eigenvalue lies
- *    within tau_res sqrt(p) of another (or the eigenvalues coincide) is
- *    computed again by the double-root branch of §5 (5.20)-(5.25) and checked
- *    again.  Matrices that still fail, or whose relative eigenvalue gap is
+ *    the general branch that fails the check is computed again and checked
+ *    again: for a diagonal matrix as the signed permutation of its axes, and
+ *    where the middle eigenvalue lies within tau_res sqrt(p) of another (or
+ *    the eigenvalues coincide) by the double-root branch of §5 (5.20)-(5.25).
+ *    Matrices that still fail, or whose relative eigenvalue gap is
  *    below tau_gap, are rewritten by a float64 refinement (isolated
  *    eigenvector by cross products, Rayleigh-Ritz on its complement and one
  *    2x2 Jacobi rotation).  Differentiated calls (tau_vec > 0) refine every

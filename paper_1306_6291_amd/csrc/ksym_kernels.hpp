@@ -223,16 +223,39 @@ __device__ __forceinline__ void double_root_f32(const Cubic &cu, float A12, floa
     extract_angles<float>(D, phi);
 }
 
+// A diagonal matrix (all off-diagonal entries zero): its eigenvectors are the
+// axes, so D is the signed permutation that puts them in the slot order
+// (max, min, mid) of its diagonal (the last column negated if the
+// permutation is odd, so that det D = +1), and the angles are read back
+// from it.  The general branch reaches this D only up to the square root of
+// the cubic step's absolute error, since each squared cosine is then exactly
+// 0 or 1.  The caller excludes p = 0, so the three slots are distinct.
+__device__ __forceinline__ void diagonal_f32(const Cubic &cu, float D[9], float phi[3]) {
+    const double x0 = cu.d1, x1 = cu.d2, x2 = cu.d3;
+    const int imax = x0 >= x1 ? (x0 >= x2 ? 0 : 2) : (x1 >= x2 ? 1 : 2);
+    const int imin = x0 < x1 ? (x0 < x2 ? 0 : 2) : (x1 < x2 ? 1 : 2);
+    const int imid = 3 - imax - imin;
+    const float last = imin == (imax == 2 ? 0 : imax + 1) ? 1.0f : -1.0f;   // even permutation: +1
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        D[3 * r] = r == imax ? 1.0f : 0.0f;
+        D[3 * r + 1] = r == imin ? 1.0f : 0.0f;
+        D[3 * r + 2] = r == imid ? last : 0.0f;
+    }
+    extract_angles<float>(D, phi);
+}
+
 // The float32 path for one matrix: the cubic stage in float64 (with float32
 // polynomial tails), the squared cosines of the angle solve as float64
 // quotients, the rest in float32, and the a-posteriori check in float32 on
 // B = A - m I.  Outputs leave through sink.put(k, value) as soon as they
 // exist (plane k of lam, D, phi, gap), which keeps few of them in registers.
-// A result of the general branch that fails the check while the split of the
-// middle eigenvalue is below tau_res sqrt(p) gets a second attempt from the
-// double-root branch (double_root_f32), checked in the same way, before the
-// matrix goes to the refinement; the flag keeps the cubic stage's
-// classification (tau_dbl) either way.
+// A result of the general branch that fails the check gets a second attempt,
+// checked in the same way, before the matrix goes to the refinement: the
+// signed permutation of a diagonal matrix (diagonal_f32), or the double-root
+// branch (double_root_f32) where the split of the middle eigenvalue is below
+// tau_res sqrt(p); the flag keeps the cubic stage's classification (tau_dbl)
+// either way.
 // Sets refine (and the isolated eigenvalue lc for the refinement, a float64
 // deviation in scaled units) and returns the flag.
 template <bool GRAD, typename Sink>
@@ -319,14 +342,20 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
     bool fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D, (float)cu.mu1,
                               (float)cu.mu2, lim2);
     if constexpr (!GRAD) {
-        // second attempt for a (nearly) double root: the double-root branch,
+        // second attempt for a diagonal matrix or a (nearly) double root,
         // checked alike.  D is stored after it (it is in registers for the
         // check anyway); the angles, already stored, are overwritten (same
         // lane, same addresses: the stores stay in order)
-        const bool retry = fails && fin && !cu.triple && (dbl || split < prm.tau_res * cu.sp);
-        if (__ballot(retry)) {
-            if (retry) {
-                double_root_f32(cu, A12, A13, A22, A33, A23, D, phi);
+        const bool cand = fails && fin && !cu.triple;
+        if (__ballot(cand)) {
+            const bool diag = A12 == 0.0f && A13 == 0.0f && A23 == 0.0f;
+            const bool near = dbl || split < prm.tau_res * cu.sp;
+            if (cand && (diag || near)) {
+                if (diag) {
+                    diagonal_f32(cu, D, phi);
+                } else {
+                    double_root_f32(cu, A12, A13, A22, A33, A23, D, phi);
+                }
                 fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                      (float)cu.mu1, (float)cu.mu2, lim2);
                 sink.reloaded().template put_n<3>(O_PHI, phi);

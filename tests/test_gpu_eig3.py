@@ -318,16 +318,18 @@ def test_all_matrices_refined_f32(ksym):
         check_f32_result(P64, g, lam_ref, V_ref, f"all-refined {block}x{mpl}")
 
 
-def test_double_roots_second_attempt_f32(ksym):
-    """Matrices with a repeated eigenvalue: Haar-rotated diag(a, a, c)
-    rounded to float32 (the pair's split is then at the rounding level) and
-    diagonal matrices with one entry repeated (an exact zero split).  Where
-    the general branch's result fails the check, the double-root branch of
-    §5 (5.20)-(5.25) is tried before the refinement; nearly all of these
-    matrices then need no refinement, every result meets the float32
-    tolerances, and the flags keep the cubic step's classification (the
-    same branch bits as when tau_gap forces every matrix into the
-    refinement)."""
+def test_second_attempt_doubles_and_diagonals_f32(ksym):
+    """Matrices on which the general branch's angle formulas lose accuracy:
+    Haar-rotated diag(a, a, c) rounded to float32 (the pair's split is then
+    at the rounding level), diagonal matrices with one entry repeated (an
+    exact zero split) and diagonal matrices with distinct entries (each
+    squared cosine exactly 0 or 1).  Where the general branch's result fails
+    the check, the double-root branch of §5 (5.20)-(5.25), or for a diagonal
+    matrix the signed permutation of its axes, is tried before the
+    refinement; nearly none of these matrices then need the refinement,
+    every result meets the float32 tolerances, and the flags keep the cubic
+    step's classification (the same branch bits as when tau_gap forces
+    every matrix into the refinement)."""
     rng = np.random.default_rng(16)
     n_rot, n_diag = 16384, 4096
     a, c = rng.uniform(-1, 1, n_rot), rng.uniform(-1, 1, n_rot)
@@ -337,20 +339,23 @@ def test_double_roots_second_attempt_f32(ksym):
     j = rng.integers(0, 3, n_diag)
     k = (j + 1 + rng.integers(0, 2, n_diag)) % 3
     d[k, np.arange(n_diag)] = d[j, np.arange(n_diag)]
-    P_diag = np.concatenate([d, np.zeros((3, n_diag))])
-    P32 = np.ascontiguousarray(np.concatenate([P_rot, P_diag], axis=1).astype(np.float32))
+    P_rep = np.concatenate([d, np.zeros((3, n_diag))])
+    P_dist = np.concatenate([rng.uniform(-1, 1, (3, n_diag)), np.zeros((3, n_diag))])
+    P32 = np.ascontiguousarray(np.concatenate([P_rot, P_rep, P_dist], axis=1).astype(np.float32))
     P64 = P32.astype(np.float64)
     lam_ref, V_ref = certified_reference(P64)
     g = _run(ksym, P32, torch.float32)
-    stats = check_f32_result(P64, g, lam_ref, V_ref, "double roots")
+    stats = check_f32_result(P64, g, lam_ref, V_ref, "doubles and diagonals")
     fixed = (g["flags"] & 4) != 0
-    print("double roots:", stats, "refined: rotated", fixed[:n_rot].mean(), "diagonal", fixed[n_rot:].mean())
-    assert fixed[:n_rot].mean() < 0.005, fixed[:n_rot].mean()
-    assert fixed[n_rot:].mean() < 0.005, fixed[n_rot:].mean()
+    parts = {"rotated doubles": fixed[:n_rot], "diagonal, repeated": fixed[n_rot:n_rot + n_diag],
+             "diagonal, distinct": fixed[n_rot + n_diag:]}
+    print("second attempt:", stats, {key: float(v.mean()) for key, v in parts.items()})
+    for key, v in parts.items():
+        assert v.mean() < 0.005, (key, v.mean())
     assert int(g["ws"][0]) == int(fixed.sum())
     forced = _run(ksym, P32, torch.float32, tau_gap=1.0)
     assert np.all(forced["flags"] & 4)
-    check_f32_result(P64, forced, lam_ref, V_ref, "double roots, all refined")
+    check_f32_result(P64, forced, lam_ref, V_ref, "doubles and diagonals, all refined")
     assert np.array_equal(forced["flags"] & 3, g["flags"] & 3)
 
 
