@@ -180,47 +180,40 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     }
 }
 
-// The double-root branch of §5, eqs. (5.20)-(5.25), in float32 for a matrix
-// whose middle eigenvalue (nearly) coincides with another: the close pair is
-// taken as one eigenvalue lm (their mean) beside the isolated ls, phi3 = 0,
-// and phi1 from the selection of the general branch with G12 = 0.  The
-// columns of R1 R2 R3 are then put in the slot order (max, min, mid) (an odd
-// permutation takes a sign), and the angles are read back from that D.  Any
-// orthonormal basis of the pair's plane is an eigenbasis up to the pair's
-// split, so the residuals of this D are bounded by the split where the
-// general branch's angle formulas lose accuracy as 1 / split.
-// cos^2 phi2 = (A11 - ls) / (lm - ls) of (5.21) equals 1 - u1^2 for the
-// isolated unit eigenvector u, and at a double root A - lm I = (ls - lm) u u^T,
-// whose row i has the squared norm (ls - lm)^2 u_i^2.  Both cos^2 phi2 and
-// sin^2 phi2 are taken as quotients of such sums of squares (rows 2 and 3
-// against row 1), as the general branch forms its squared cosines: the
-// difference A11 - ls would carry the cubic step's absolute error, which the
-// square root in cos phi2 turns into its square root where cos^2 phi2 is
-// near 0 (a diagonal matrix with the isolated entry first).
-__device__ __forceinline__ void double_root_f32(const Cubic &cu, float A12, float A13, float A22, float A33,
-                                                float A23, float D[9], float phi[3]) {
+// The double-root branch of §5, eqs. (5.20)-(5.25), in float32 and in the
+// general branch's slot order, for a matrix whose middle eigenvalue (nearly)
+// coincides with another: the close pair is taken as one eigenvalue lm (their
+// mean) beside the isolated ls.  At a double root A - lm I = (ls - lm) u u^T
+// for the isolated unit eigenvector u, so row i of A - lm I has the squared
+// norm (ls - lm)^2 u_i^2, and any orthonormal basis of the pair's plane
+// completes D.  With u in its slot (max or min) and the pair's basis chosen
+// so that the first-row entry of the other of those two columns vanishes
+// (phi3 = 0 for an isolated max, +-pi/2 for an isolated min), the squared
+// cosines of (5.1)-(5.2) are v = u1^2 and w = 1 or 0.  This is (5.21), whose
+// cos^2 phi2 = (A11 - ls)/(lm - ls) is 1 - u1^2 in the paper's column order
+// (u third, phi3 = 0), written for the slot order; v and 1 - v are taken as
+// quotients of the row norms, which keep their relative accuracy where
+// either is near 0 (the difference A11 - ls would carry the cubic step's
+// absolute error, and the square root in cos phi2 its square root).  The
+// angle selection of the general branch then gives phi1 and the signs.  The
+// residuals of this D are bounded by the pair's split, where the general
+// branch's angle formulas lose accuracy as 1 / split.
+__device__ __forceinline__ Rot<float> double_root_f32(const Cubic &cu, float A12, float A13, float A22,
+                                                      float A33, float A23, bool plus, float &v, float &s2sq,
+                                                      float &w, float &cw) {
     const bool iso_max = !(cu.g13 < cu.g32);   // pair (mid, min), isolated max; else pair (max, mid)
     const double lm = iso_max ? 0.5 * (cu.mu3 + cu.mu2) : 0.5 * (cu.mu1 + cu.mu3);
-    const double ls = iso_max ? cu.mu1 : cu.mu2;
     const double b12 = A12, b13 = A13, b23 = A23;
     const double e1 = cu.d1 - lm, e2 = cu.d2 - lm, e3 = cu.d3 - lm;
-    const double r1 = e1 * e1 + b12 * b12 + b13 * b13;                           // (ls - lm)^2 u1^2
+    const double r1 = e1 * e1 + b12 * b12 + b13 * b13;                                  // (ls - lm)^2 u1^2
     const double r23 = e2 * e2 + e3 * e3 + b12 * b12 + b13 * b13 + 2.0 * b23 * b23;   // (ls - lm)^2 (u2^2 + u3^2)
     const double inv = 1.0 / (r1 + r23);
-    const float s = (float)(r23 * inv), cs = (float)(r1 * inv);
-    const Rot<float> R = select_angles<float>(A12, A13, A22, A33, A23, 0.0f, (float)(lm - ls),
-                                              (float)(ls - lm), s, cs, 1.0f, 0.0f, true);
-    float Di[9];
-    build_D(R, Di);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        // isolated max: columns (3, 1, 2), an even permutation; isolated
-        // min: columns (1, 3, -2)
-        D[3 * r] = iso_max ? Di[3 * r + 2] : Di[3 * r];
-        D[3 * r + 1] = iso_max ? Di[3 * r] : Di[3 * r + 2];
-        D[3 * r + 2] = iso_max ? Di[3 * r + 1] : -Di[3 * r + 1];
-    }
-    extract_angles<float>(D, phi);
+    v = (float)(r1 * inv);
+    s2sq = (float)(r23 * inv);
+    w = iso_max ? 1.0f : 0.0f;
+    cw = iso_max ? 0.0f : 1.0f;
+    return select_angles<float>(A12, A13, A22, A33, A23, (float)cu.g12, (float)cu.g13, (float)cu.g32, v, s2sq, w,
+                                cw, plus);
 }
 
 // A diagonal matrix (all off-diagonal entries zero): its eigenvectors are the
@@ -354,7 +347,10 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
                 if (diag) {
                     diagonal_f32(cu, D, phi);
                 } else {
-                    double_root_f32(cu, A12, A13, A22, A33, A23, D, phi);
+                    float v2, s2sq2, w2, cw2;
+                    const Rot<float> R2 = double_root_f32(cu, A12, A13, A22, A33, A23, plus, v2, s2sq2, w2, cw2);
+                    angles_of(R2, v2, s2sq2, w2, cw2, phi);
+                    build_D(R2, D);
                 }
                 fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                      (float)cu.mu1, (float)cu.mu2, lim2);
