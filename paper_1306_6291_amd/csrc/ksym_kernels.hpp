@@ -180,62 +180,62 @@ __device__ __forceinline__ void eig3_one(const T ain[6], const Eig3Params &prm, 
     }
 }
 
-// The double-root branch of §5, eqs. (5.20)-(5.25), in float32 and in the
-// general branch's slot order, for a matrix whose middle eigenvalue (nearly)
-// coincides with another: the close pair is taken as one eigenvalue lm (their
-// mean) beside the isolated ls.  At a double root A - lm I = (ls - lm) u u^T
-// for the isolated unit eigenvector u, so row i of A - lm I has the squared
-// norm (ls - lm)^2 u_i^2, and any orthonormal basis of the pair's plane
-// completes D.  With u in its slot (max or min) and the pair's basis chosen
-// so that the first-row entry of the other of those two columns vanishes
-// (phi3 = 0 for an isolated max, +-pi/2 for an isolated min), the squared
-// cosines of (5.1)-(5.2) are v = u1^2 and w = 1 or 0.  This is (5.21), whose
-// cos^2 phi2 = (A11 - ls)/(lm - ls) is 1 - u1^2 in the paper's column order
-// (u third, phi3 = 0), written for the slot order; v and 1 - v are taken as
-// quotients of the row norms, which keep their relative accuracy where
-// either is near 0 (the difference A11 - ls would carry the cubic step's
-// absolute error, and the square root in cos phi2 its square root).  The
-// angle selection of the general branch then gives phi1 and the signs.  The
-// residuals of this D are bounded by the pair's split, where the general
-// branch's angle formulas lose accuracy as 1 / split.
-__device__ __forceinline__ Rot<float> double_root_f32(const Cubic &cu, float A12, float A13, float A22,
-                                                      float A33, float A23, bool plus, float &v, float &s2sq,
-                                                      float &w, float &cw) {
-    const bool iso_max = !(cu.g13 < cu.g32);   // pair (mid, min), isolated max; else pair (max, mid)
-    const double lm = iso_max ? 0.5 * (cu.mu3 + cu.mu2) : 0.5 * (cu.mu1 + cu.mu3);
-    const double b12 = A12, b13 = A13, b23 = A23;
-    const double e1 = cu.d1 - lm, e2 = cu.d2 - lm, e3 = cu.d3 - lm;
-    const double r1 = e1 * e1 + b12 * b12 + b13 * b13;                                  // (ls - lm)^2 u1^2
-    const double r23 = e2 * e2 + e3 * e3 + b12 * b12 + b13 * b13 + 2.0 * b23 * b23;   // (ls - lm)^2 (u2^2 + u3^2)
-    const double inv = 1.0 / (r1 + r23);
-    v = (float)(r1 * inv);
-    s2sq = (float)(r23 * inv);
-    w = iso_max ? 1.0f : 0.0f;
-    cw = iso_max ? 0.0f : 1.0f;
-    return select_angles<float>(A12, A13, A22, A33, A23, (float)cu.g12, (float)cu.g13, (float)cu.g32, v, s2sq, w,
-                                cw, plus);
-}
-
-// A diagonal matrix (all off-diagonal entries zero): its eigenvectors are the
-// axes, so D is the signed permutation that puts them in the slot order
-// (max, min, mid) of its diagonal (the last column negated if the
-// permutation is odd, so that det D = +1), and the angles are read back
-// from it.  The general branch reaches this D only up to the square root of
-// the cubic step's absolute error, since each squared cosine is then exactly
-// 0 or 1.  The caller excludes p = 0, so the three slots are distinct.
-__device__ __forceinline__ void diagonal_f32(const Cubic &cu, float D[9], float phi[3]) {
-    const double x0 = cu.d1, x1 = cu.d2, x2 = cu.d3;
-    const int imax = x0 >= x1 ? (x0 >= x2 ? 0 : 2) : (x1 >= x2 ? 1 : 2);
-    const int imin = x0 < x1 ? (x0 < x2 ? 0 : 2) : (x1 < x2 ? 1 : 2);
-    const int imid = 3 - imax - imin;
-    const float last = imin == (imax == 2 ? 0 : imax + 1) ? 1.0f : -1.0f;   // even permutation: +1
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        D[3 * r] = r == imax ? 1.0f : 0.0f;
-        D[3 * r + 1] = r == imin ? 1.0f : 0.0f;
-        D[3 * r + 2] = r == imid ? last : 0.0f;
+// The second attempt of the float32 path: the squared cosines v, 1 - v of
+// phi2 and w, 1 - w of phi3 (5.1)-(5.2) where the general branch's quotients
+// lose them, fed to the general branch's angle selection.
+//  - Double root, eqs. (5.20)-(5.25) in the general branch's slot order: the
+//    close pair is taken as one eigenvalue lm (their mean) beside the
+//    isolated ls.  At a double root A - lm I = (ls - lm) u u^T for the
+//    isolated unit eigenvector u, so row i of A - lm I has the squared norm
+//    (ls - lm)^2 u_i^2, and any orthonormal basis of the pair's plane
+//    completes D.  With u in its slot (max or min) and the pair's basis
+//    chosen so that the first-row entry of the other of those two columns
+//    vanishes (phi3 = 0 for an isolated max, +-pi/2 for an isolated min),
+//    v = u1^2 and w = 1 or 0.  This is (5.21), whose cos^2 phi2 =
+//    (A11 - ls)/(lm - ls) is 1 - u1^2 in the paper's column order (u third,
+//    phi3 = 0), written for the slot order; v and 1 - v are quotients of the
+//    row norms, which keep their relative accuracy where either is near 0
+//    (the difference A11 - ls would carry the cubic step's absolute error,
+//    and the square root in cos phi2 its square root).  The residuals of
+//    this D are bounded by the pair's split, where the general branch's
+//    angle formulas lose accuracy as 1 / split.
+//  - Diagonal matrix (all off-diagonal entries zero): D is a signed
+//    permutation, whose first row is the axis of A11's slot, so v = 1, w = 1
+//    (A11 the largest), v = 1, w = 0 (the smallest) or v = 0, w = 1 (the
+//    middle one).  The gaps are taken from the sorted diagonal, exact where
+//    two entries coincide, and the selection then gives phi1 = 0 or +-pi/2.
+//    The general branch reaches these squared cosines, exactly 0 or 1, only
+//    up to the cubic step's absolute error, and the square root turned that
+//    into about 1e-5 in D.
+__device__ __forceinline__ Rot<float> second_attempt_f32(const Cubic &cu, float A12, float A13, float A22,
+                                                         float A33, float A23, bool plus, bool diag, float &v,
+                                                         float &s2sq, float &w, float &cw) {
+    float G12 = (float)cu.g12, G13 = (float)cu.g13, G32 = (float)cu.g32;
+    if (diag) {
+        const double x0 = cu.d1, x1 = cu.d2, x2 = cu.d3;
+        const double hi = fmax(fmax(x0, x1), x2), lo = fmin(fmin(x0, x1), x2);
+        const double mid = fmax(fmin(x0, x1), fmin(fmax(x0, x1), x2));
+        G12 = (float)(hi - lo);
+        G13 = (float)(hi - mid);
+        G32 = (float)(mid - lo);
+        const bool top = x0 == hi, bottom = !top && x0 == lo;
+        v = (top || bottom) ? 1.0f : 0.0f;
+        w = bottom ? 0.0f : 1.0f;
+    } else {
+        const bool iso_max = !(cu.g13 < cu.g32);   // pair (mid, min), isolated max; else pair (max, mid)
+        const double lm = iso_max ? 0.5 * (cu.mu3 + cu.mu2) : 0.5 * (cu.mu1 + cu.mu3);
+        const double b12 = A12, b13 = A13, b23 = A23;
+        const double e1 = cu.d1 - lm, e2 = cu.d2 - lm, e3 = cu.d3 - lm;
+        const double r1 = e1 * e1 + b12 * b12 + b13 * b13;                                  // (ls - lm)^2 u1^2
+        const double r23 = e2 * e2 + e3 * e3 + b12 * b12 + b13 * b13 + 2.0 * b23 * b23;   // (ls - lm)^2 (u2^2 + u3^2)
+        const double inv = 1.0 / (r1 + r23);
+        v = (float)(r1 * inv);
+        w = iso_max ? 1.0f : 0.0f;
+        s2sq = (float)(r23 * inv);
     }
-    extract_angles<float>(D, phi);
+    if (diag) s2sq = 1.0f - v;
+    cw = 1.0f - w;
+    return select_angles<float>(A12, A13, A22, A33, A23, G12, G13, G32, v, s2sq, w, cw, plus);
 }
 
 // The float32 path for one matrix: the cubic stage in float64 (with float32
@@ -244,11 +244,11 @@ __device__ __forceinline__ void diagonal_f32(const Cubic &cu, float D[9], float 
 // B = A - m I.  Outputs leave through sink.put(k, value) as soon as they
 // exist (plane k of lam, D, phi, gap), which keeps few of them in registers.
 // A result of the general branch that fails the check gets a second attempt,
-// checked in the same way, before the matrix goes to the refinement: the
-// signed permutation of a diagonal matrix (diagonal_f32), or the double-root
-// branch (double_root_f32) where the split of the middle eigenvalue is below
-// tau_res sqrt(p); the flag keeps the cubic stage's classification (tau_dbl)
-// either way.
+// checked in the same way, before the matrix goes to the refinement: for a
+// diagonal matrix, or where the split of the middle eigenvalue is below
+// tau_res sqrt(p), the squared cosines of second_attempt_f32 go through the
+// same angle selection; the flag keeps the cubic stage's classification
+// (tau_dbl) either way.
 // Sets refine (and the isolated eigenvalue lc for the refinement, a float64
 // deviation in scaled units) and returns the flag.
 template <bool GRAD, typename Sink>
@@ -344,14 +344,11 @@ __device__ __forceinline__ int eig3_f32(const float ain[6], const Eig3Params &pr
             const bool diag = A12 == 0.0f && A13 == 0.0f && A23 == 0.0f;
             const bool near = dbl || split < prm.tau_res * cu.sp;
             if (cand && (diag || near)) {
-                if (diag) {
-                    diagonal_f32(cu, D, phi);
-                } else {
-                    float v2, s2sq2, w2, cw2;
-                    const Rot<float> R2 = double_root_f32(cu, A12, A13, A22, A33, A23, plus, v2, s2sq2, w2, cw2);
-                    angles_of(R2, v2, s2sq2, w2, cw2, phi);
-                    build_D(R2, D);
-                }
+                float v2, s2sq2, w2, cw2;
+                const Rot<float> R2 = second_attempt_f32(cu, A12, A13, A22, A33, A23, plus, diag, v2, s2sq2, w2,
+                                                         cw2);
+                angles_of(R2, v2, s2sq2, w2, cw2, phi);
+                build_D(R2, D);
                 fails = check2_fails((float)cu.d1, (float)cu.d2, (float)cu.d3, A12, A13, A23, D,
                                      (float)cu.mu1, (float)cu.mu2, lim2);
                 sink.reloaded().template put_n<3>(O_PHI, phi);
@@ -920,11 +917,11 @@ __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refine
 
 // float32: an occupancy target makes the compiler fit the kernel into the
 // registers of 6 waves per SIMD (80 VGPRs) with one matrix per lane and of
-// 5 waves (96) with two (one wave less for the differentiated variant); two matrices per lane at 6 waves would spill, and
-// their queue's LDS allows 5 waves per SIMD anyway.  The plain float64 path
-// runs faster at 4 waves (128 VGPRs, a few spills) than at 3; the checked
-// one does not, and neither does the mixed-batch kernel at a higher target.
-// The target never exceeds what the workgroup's LDS allows (160 KB per CU).
+// 5 waves (96) with two (one wave less for the differentiated variant); two
+// matrices per lane at 6 waves would spill, and their queue's LDS allows 5
+// waves per SIMD anyway.  The plain float64 path runs faster at 4 waves
+// (128 VGPRs, a few spills) than at 3; the checked one does not.  The
+// target never exceeds what the workgroup's LDS allows (160 KB per CU).
 template <typename T, int PATH, int BS, int MPL, bool AOS, bool GRAD>
 constexpr int eig3_waves_target() {
     constexpr int NW = BS / WAVE;
@@ -1383,9 +1380,10 @@ __device__ __forceinline__ void wtile_eig2_in(const __attribute__((address_space
 // (float32) stores, chosen by the host when every plane starts on a 256-byte
 // boundary, so that no cache line holds parts of two waves' tiles; otherwise
 // the default policy, since two waves writing one line with non-temporal
-// stores measured up to 50 % slower.
+// stores measured up to 50 % slower.  float32 with one matrix per lane fits
+// the 80 VGPRs of 6 waves per SIMD, like k_eig3.
 template <typename T, int BS, int MPL, bool STREAM>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1) ? 5 : 1)))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MPL == 1) ? 6 : 1)))
 void k_mixed(MixedArgs<T> a) {
     constexpr int NW = BS / WAVE;
     constexpr int PATH = (sizeof(T) == 4) ? PATH_FP32_FIXUP : PATH_FP64_FIXUP;
