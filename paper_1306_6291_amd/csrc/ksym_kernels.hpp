@@ -633,7 +633,13 @@ __device__ __forceinline__ void put3(const Planes &pl, int salt, uint32_t off, c
 }
 
 // Stores of one lane's matrix as its outputs are produced (float32 path).
-// Lanes past n and absent planes are dropped by the descriptors.
+// Lanes past n and absent planes are dropped by the descriptors.  In float32
+// an absent plane also skips its store instruction (a branch on the plane
+// pointer, uniform over the launch or the mixed batch's group): the
+// instruction would still occupy the wave's memory issue, which cost about
+// 1 % with the gaps and flags absent and 4 % with D absent too.  The float64
+// kernels keep every store (the branches raised their register use from
+// about 160 to 180 VGPRs, one wave less per SIMD).
 template <typename T, int SP, typename Planes> struct LaneSink {
     const Planes &pl;
     int salt;
@@ -643,10 +649,12 @@ template <typename T, int SP, typename Planes> struct LaneSink {
     template <int N> __device__ __forceinline__ void put_n(int k0, const T *v) const {
         const PtrN<T, N> q = pl.template outs<N>(k0 + salt);
 #pragma unroll
-        for (int i = 0; i < N; ++i) st_plane<T, SP>(q.p[i], pl.n, off, v[i]);
+        for (int i = 0; i < N; ++i)
+            if (sizeof(T) == 8 || q.p[i]) st_plane<T, SP>(q.p[i], pl.n, off, v[i]);
     }
     __device__ __forceinline__ void flag(int f) const {
-        st_plane<uint8_t, SP>(pl.flags(salt), pl.n, off, (uint8_t)f);
+        uint8_t *p = pl.flags(salt);
+        if (sizeof(T) == 8 || p) st_plane<uint8_t, SP>(p, pl.n, off, (uint8_t)f);
     }
     // The same sink with plane pointers that are read again where it is
     // used (a rare branch then loads its own descriptors instead of keeping
