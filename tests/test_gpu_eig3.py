@@ -389,6 +389,24 @@ def test_optional_outputs(ksym):
     assert np.array_equal(part["lam"], full["lam"])
 
 
+def test_absent_planes_leave_the_others_bitwise(ksym):
+    """The float32 kernels skip the stores of absent output planes, and the
+    arithmetic that only fed them: every subset of planes that keeps the full
+    kernel (D or the angles present) gives bitwise the full run's values on
+    the planes it has, on the precision recipe (second attempts and
+    refinement included) and in differentiated calls (tau_vec > 0)."""
+    P32 = synth.make_precision(40000 + 17, seed=77)
+    subsets = (("lam", "D"), ("D", "gap"), ("phi", "flags"), ("D", "phi", "flags"), ("lam", "phi", "gap"))
+    for extra in ({}, {"tau_vec": 1e-4}):
+        full = _run(ksym, P32, torch.float32, **extra)
+        assert int(full["ws"][0]) > 0
+        for outs in subsets:
+            part = _run(ksym, P32, torch.float32, outputs=outs, **extra)
+            for k in outs:
+                assert np.array_equal(part[k], full[k], equal_nan=True), (extra, outs, k)
+            assert int(part["ws"][0]) == int(full["ws"][0]), (extra, outs)
+
+
 def test_aos_matches_soa(ksym):
     """Array-of-structures input (records of six) gives bitwise the SoA result."""
     P32 = synth.make_precision(70001, seed=99)
