@@ -11,7 +11,9 @@
 // to its wave's queue in LDS (ballot + popcount for the count, mbcnt for the
 // lane's rank; the count lives in a scalar register).  When the queue holds 64
 // entries the wave refines them together, entry j on lane j, so the float64
-// refinement always runs on full wavefronts, and overwrites those outputs.
+// refinement runs on full wavefronts, and overwrites those outputs; what is
+// left when the wave has finished its tiles is refined in one partly filled
+// round.
 //
 // Memory access: every plane is read and written through a raw buffer
 // descriptor (base address and size in bytes) with a 32-bit lane offset.  A
@@ -874,48 +876,6 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
     }
 }
 
-// Refine what is left in the queues of all NW waves of the workgroup once
-// they have finished their tiles: the leftovers are pooled (entry e of the
-// concatenated queues goes to lane e % 64 of wave (e / 64) % NW), so a
-// workgroup pays for one partly filled refinement round instead of one per
-// wave.  A wave with queued entries first waits for its own stores, because
-// a refined result may now overwrite a provisional one that this wave wrote
-// and another wave refines; a wave with an empty queue (most of them) has no
-// store that anything overwrites and goes straight to the barrier.
-template <typename T, int MPL, bool AOS, int NW, typename PlanesOf>
-__device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
-                                            int *qcount, int qn, int w, unsigned &refined) {
-    const int lane = lane_id();
-    if (qn > 0) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
-    if (lane == 0) qcount[w] = qn;
-    __syncthreads();
-    int pre[NW + 1];
-    pre[0] = 0;
-#pragma unroll
-    for (int v = 0; v < NW; ++v) pre[v + 1] = pre[v] + qcount[v];
-    const int total = pre[NW];
-    for (int r = w; r * WAVE < total; r += NW) {
-        const int e = r * WAVE + lane;
-        bool ref = false;
-        if (e < total) {
-            int src = 0;
-#pragma unroll
-            for (int v = 1; v < NW; ++v) src += (e >= pre[v]) ? 1 : 0;
-            const int i = e - pre[src];
-            const WaveQueue<T, WAVE *(MPL + 1)> *q = &sm[src].q;
-            T a[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) a[c] = q->a[c][i];
-            const int g = q->grp[i];
-            ref = !is_special(g >> 24);
-            Out3<T> o;
-            refine_one<T>(a, q->lc[i], g >> 24, o);
-            write_out3(planes_of(g & 0xffffff), 0, q->off[i], o);
-        }
-        refined += (unsigned)__popcll(__ballot(ref));
-    }
-}
-
 __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refined, unsigned nonfinite) {
     if (counters && lane_id() == 0) {
         if (refined) atomicAdd(&counters[0], refined);
@@ -937,7 +897,7 @@ constexpr int eig3_waves_target() {
     // gets one wave less: at the plain variant's budget it would spill)
     constexpr int want = sizeof(T) == 4 ? (MPL == 1 ? 6 - GRAD : MPL == 2 ? 5 - GRAD : 1)
                                         : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1);
-    constexpr size_t lds = NW * (sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>) + sizeof(int));
+    constexpr size_t lds = NW * sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>);
     constexpr int by_lds = (int)(163840 / lds) * NW / 4;
     return want < by_lds ? want : (by_lds > 1 ? by_lds : 1);
 }
@@ -949,8 +909,7 @@ void k_eig3(Eig3Args<T> args) {
     constexpr int WT = WAVE * MPL;
     constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
     __shared__ WaveSmem<T, MPL, QUEUE, AOS> sm[NW];
-    __shared__ int qcount[NW];
-    // the wave index in a scalar register, kept for the final drain
+    // the wave index, in a scalar register
     const int wid = wave_id();
     WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wid];
     const uint32_t n = (uint32_t)args.prm.n;
@@ -989,7 +948,16 @@ void k_eig3(Eig3Args<T> args) {
         step();
         for (t += stride; t < ntiles; t += stride) step();
     }
-    if constexpr (QUEUE) final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, wid, refined);
+    // what is left (fewer than 64: the tiles drain full rounds) is refined
+    // by the wave itself, with no barrier: once refinement is rare, a
+    // workgroup barrier and a pooled round cost more than the occasional
+    // partly filled round of one wave
+    if constexpr (QUEUE) {
+        if (qn > 0) {
+            wave_sync();
+            refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+        }
+    }
     add_counters(args.prm.counters, refined, nonfinite);
 }
 
@@ -1399,7 +1367,6 @@ void k_mixed(MixedArgs<T> a) {
     constexpr int LP = STREAM ? kStream : kCached;
     constexpr int SP = (STREAM && sizeof(T) == 4) ? kStream : kCached;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
-    __shared__ int qcount[NW];
     const int wid = wave_id();
     WaveSmem<T, MPL, true, false> *my = &sm[wid];
     const cptr<GroupDesc<T>> groups = as_const(a.groups);
@@ -1436,7 +1403,10 @@ void k_mixed(MixedArgs<T> a) {
         step();
         for (t += stride; t < a.ntiles; t += stride) step();
     }
-    final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, wid, refined);
+    if (qn > 0) {   // the wave's own leftovers, as in k_eig3
+        wave_sync();
+        refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+    }
     add_counters(a.prm.counters, refined, nonfinite);
 }
 
