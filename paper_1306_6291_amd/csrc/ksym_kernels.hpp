@@ -4,7 +4,7 @@
 // matrices (MPL = matrices per lane) and walks them grid-stride; matrix
 // k*64 + lane of a tile belongs to `lane`, so every plane load and store is one
 // contiguous 64-element run and needs no staging.  The waves of a workgroup
-// never wait for each other: there is no workgroup barrier in the 3x3 kernels.
+// never wait for each other, except at the float64 kernels' final drain.
 //
 // Refinement routing (3x3 float32 and float64 check paths): a lane whose
 // matrix fails the check stores its provisional result and appends the matrix
@@ -13,7 +13,8 @@
 // entries the wave refines them together, entry j on lane j, so the float64
 // refinement runs on full wavefronts, and overwrites those outputs; what is
 // left when the wave has finished its tiles is refined in one partly filled
-// round.
+// round (float32: per wave; float64: pooled over the workgroup, the one
+// workgroup barrier of these kernels).
 //
 // Memory access: every plane is read and written through a raw buffer
 // descriptor (base address and size in bytes) with a 32-bit lane offset.  A
@@ -876,6 +877,52 @@ __device__ __forceinline__ void wtile_eig3(const Planes &pl, const PlanesOf &pla
     }
 }
 
+// Refine what is left in the queues of all NW waves of the workgroup once
+// they have finished their tiles: the leftovers are pooled (entry e of the
+// concatenated queues goes to lane e % 64 of wave (e / 64) % NW), so a
+// workgroup pays for one partly filled refinement round instead of one per
+// wave.  The float64 checked path, which refines a few percent of the
+// precision recipe, drains this way (one wave at a time it ran 6 % slower,
+// with four times the refinement rounds); the float32 kernels, which refine
+// far fewer matrices, let each wave refine its own leftovers with no
+// barrier.  A wave with queued entries first waits for its own stores, because
+// a refined result may now overwrite a provisional one that this wave wrote
+// and another wave refines; a wave with an empty queue (most of them) has no
+// store that anything overwrites and goes straight to the barrier.
+template <typename T, int MPL, bool AOS, int NW, typename PlanesOf>
+__device__ __forceinline__ void final_drain(const PlanesOf &planes_of, WaveSmem<T, MPL, true, AOS> *sm,
+                                            int *qcount, int qn, int w, unsigned &refined) {
+    const int lane = lane_id();
+    if (qn > 0) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's stores have completed
+    if (lane == 0) qcount[w] = qn;
+    __syncthreads();
+    int pre[NW + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) pre[v + 1] = pre[v] + qcount[v];
+    const int total = pre[NW];
+    for (int r = w; r * WAVE < total; r += NW) {
+        const int e = r * WAVE + lane;
+        bool ref = false;
+        if (e < total) {
+            int src = 0;
+#pragma unroll
+            for (int v = 1; v < NW; ++v) src += (e >= pre[v]) ? 1 : 0;
+            const int i = e - pre[src];
+            const WaveQueue<T, WAVE *(MPL + 1)> *q = &sm[src].q;
+            T a[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] = q->a[c][i];
+            const int g = q->grp[i];
+            ref = !is_special(g >> 24);
+            Out3<T> o;
+            refine_one<T>(a, q->lc[i], g >> 24, o);
+            write_out3(planes_of(g & 0xffffff), 0, q->off[i], o);
+        }
+        refined += (unsigned)__popcll(__ballot(ref));
+    }
+}
+
 __device__ __forceinline__ void add_counters(unsigned *counters, unsigned refined, unsigned nonfinite) {
     if (counters && lane_id() == 0) {
         if (refined) atomicAdd(&counters[0], refined);
@@ -897,7 +944,7 @@ constexpr int eig3_waves_target() {
     // gets one wave less: at the plain variant's budget it would spill)
     constexpr int want = sizeof(T) == 4 ? (MPL == 1 ? 6 - GRAD : MPL == 2 ? 5 - GRAD : 1)
                                         : (PATH == PATH_FP64_PLAIN && MPL == 1 ? 4 : 1);
-    constexpr size_t lds = NW * sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>);
+    constexpr size_t lds = NW * (sizeof(WaveSmem<T, MPL, PATH != PATH_FP64_PLAIN, AOS>) + sizeof(int));
     constexpr int by_lds = (int)(163840 / lds) * NW / 4;
     return want < by_lds ? want : (by_lds > 1 ? by_lds : 1);
 }
@@ -909,6 +956,7 @@ void k_eig3(Eig3Args<T> args) {
     constexpr int WT = WAVE * MPL;
     constexpr bool QUEUE = PATH != PATH_FP64_PLAIN;
     __shared__ WaveSmem<T, MPL, QUEUE, AOS> sm[NW];
+    __shared__ int qcount[NW];   // the float64 pooled drain only
     // the wave index, in a scalar register
     const int wid = wave_id();
     WaveSmem<T, MPL, QUEUE, AOS> *my = &sm[wid];
@@ -948,14 +996,19 @@ void k_eig3(Eig3Args<T> args) {
         step();
         for (t += stride; t < ntiles; t += stride) step();
     }
-    // what is left (fewer than 64: the tiles drain full rounds) is refined
-    // by the wave itself, with no barrier: once refinement is rare, a
-    // workgroup barrier and a pooled round cost more than the occasional
-    // partly filled round of one wave
+    // what is left (fewer than 64: the tiles drain full rounds): float32 is
+    // refined by the wave itself, with no barrier (refinement is rare there,
+    // and a workgroup barrier and a pooled round cost more than the
+    // occasional partly filled round of one wave); float64 is pooled
     if constexpr (QUEUE) {
-        if (qn > 0) {
-            wave_sync();
-            refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+        if constexpr (sizeof(T) == 8) {
+            final_drain<T, MPL, AOS, NW>(planes_of, sm, qcount, qn, wid, refined);
+        } else {
+            (void)qcount;
+            if (qn > 0) {
+                wave_sync();
+                refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+            }
         }
     }
     add_counters(args.prm.counters, refined, nonfinite);
@@ -1367,6 +1420,7 @@ void k_mixed(MixedArgs<T> a) {
     constexpr int LP = STREAM ? kStream : kCached;
     constexpr int SP = (STREAM && sizeof(T) == 4) ? kStream : kCached;
     __shared__ WaveSmem<T, MPL, true, false> sm[NW];
+    __shared__ int qcount[NW];   // the float64 pooled drain only
     const int wid = wave_id();
     WaveSmem<T, MPL, true, false> *my = &sm[wid];
     const cptr<GroupDesc<T>> groups = as_const(a.groups);
@@ -1403,9 +1457,15 @@ void k_mixed(MixedArgs<T> a) {
         step();
         for (t += stride; t < a.ntiles; t += stride) step();
     }
-    if (qn > 0) {   // the wave's own leftovers, as in k_eig3
-        wave_sync();
-        refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+    // the leftovers, as in k_eig3
+    if constexpr (sizeof(T) == 8) {
+        final_drain<T, MPL, false, NW>(planes_of, sm, qcount, qn, wid, refined);
+    } else {
+        (void)qcount;
+        if (qn > 0) {
+            wave_sync();
+            refined += drain_wave<T>(&my->q, qn, planes_of, 0);
+        }
     }
     add_counters(a.prm.counters, refined, nonfinite);
 }
