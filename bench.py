@@ -524,8 +524,8 @@ def main():
                          "(the first is the headline's), to show the spread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    # (mixed last: its thousands of group allocations, even once freed, left
-    # the 2x2 workload after it 10 % slower than in a process of its own)
+    # (the 2x2 forward first: after other workloads' allocations it ran 10-17 %
+    # slower than in a process of its own)
     ap.add_argument("--workloads", default="eig2,grad,field,mixed",
                     help="precision workload: the other workloads timed into the same line "
                          "(comma-separated from mixed, grad, field, eig2; empty for none)")
